@@ -1,0 +1,30 @@
+"""Plain, slow, obviously correct CPU oracle of the Chebyshev-BdG hot path.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call anything here.  The
+product library never does, and this package never imports the product
+package: the two share no code.  Inputs come from the seeded generators in
+``workloads``, which hold none of the method's arithmetic.
+
+Parts (each function cites the passage of the paper it follows):
+  core.py   explicit sparse Hamiltonian of eq. (hamil2), the vector recursion
+            of eq. (ref2) and its adjoint, in plain C (cbdg_oracle.c)
+  kpm.py    kernel factors, energy weights, the gap equation eq. (op1) and the
+            LDOS eq. (ldos), in NumPy FP64
+  scf.py    the self-consistency loop (plain mixing)
+
+Readings of passages the paper leaves open are listed with the code that
+uses them.
+"""
+from .core import (build_csr, bounds, moments, moments_backward, workload_csr, workload_bounds,
+                   workload_moments, max_threads, ensure_built)
+from .kpm import (jackson, lorentz, sign_coefficients, gap_weights, gap_map,
+                  ldos, ldos_weights, chebyshev_T)
+from .scf import scf_plain
+
+__all__ = [
+    "build_csr", "bounds", "moments", "moments_backward", "workload_csr", "workload_bounds",
+    "workload_moments", "max_threads", "ensure_built", "jackson", "lorentz",
+    "sign_coefficients", "gap_weights", "gap_map", "ldos", "ldos_weights",
+    "chebyshev_T", "scf_plain",
+]

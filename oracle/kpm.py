@@ -1,0 +1,94 @@
+"""Kernel factors, energy weights and observables in NumPy FP64 (test oracle).
+
+Conventions: moments mu_n are <bra|T_n(Ht)|s,e> for n = 0..N-1 (no
+1/(1+delta_{0n}) factor), Ht = (H - b)/a, energies are in units of t.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def jackson(N: int) -> np.ndarray:
+    """Jackson kernel factors g_n, n = 0..N-1.
+
+    The paper damps the truncated series with a kernel (paragraph before the
+    Lorentz-kernel equation); the Jackson form is the one of its KPM reference
+    (weisse2006): g_n = [(N-n+1) cos(pi n/(N+1)) + sin(pi n/(N+1)) cot(pi/(N+1))]/(N+1).
+    """
+    n = np.arange(N, dtype=np.float64)
+    q = np.pi / (N + 1)
+    return ((N - n + 1) * np.cos(q * n) + np.sin(q * n) / np.tan(q)) / (N + 1)
+
+
+def lorentz(N: int, lam: float) -> np.ndarray:
+    """Lorentz kernel factors sinh[lam (1 - n/N)] / sinh(lam) (the kernel
+    equation following eq. (ref2)); the broadening is eps = lam/N in rescaled
+    energy units."""
+    n = np.arange(N, dtype=np.float64)
+    return np.sinh(lam * (1.0 - n / N)) / np.sinh(lam)
+
+
+def chebyshev_T(n, x):
+    """T_n(x) = cos(n arccos x) on [-1, 1] (definition under the expansion of
+    f(x) in Chebyshev polynomials)."""
+    return np.cos(np.multiply.outer(np.asarray(n, dtype=np.float64), np.arccos(x)))
+
+
+def sign_coefficients(N: int, x_c: float = 1.0) -> np.ndarray:
+    """Chebyshev coefficients c_n of w(x) = 1 - 2 f = sign(x) on |x| < x_c,
+    w = 0 outside, so that w(x) = sum_n c_n T_n(x) (T = 0 limit of the weight
+    (1 - 2 f(E)) in eq. (op1); x_c = E_c/a is the rescaled cutoff).
+
+    With x = cos(theta):  c_n = (2/pi) int_0^pi w(cos theta) cos(n theta) dtheta
+    = 4 [sin(n pi/2) - sin(n arccos x_c)] / (n pi) for odd n, 0 for even n.
+    Reading: E_c is not fixed by the workloads, so the default is no cutoff.
+    """
+    c = np.zeros(N)
+    n = np.arange(1, N, dtype=np.float64)
+    tc = np.arccos(min(max(x_c, -1.0), 1.0))
+    odd = (np.arange(1, N) % 2) == 1
+    c[1:][odd] = 4.0 * (np.sin(n[odd] * np.pi / 2) - np.sin(n[odd] * tc)) / (n[odd] * np.pi)
+    return c
+
+
+def gap_weights(N: int, kernel: str = "jackson", lam: float = 0.0, x_c: float = 1.0):
+    g = jackson(N) if kernel == "jackson" else lorentz(N, lam)
+    return g * sign_coefficients(N, x_c)
+
+
+def gap_map(mu_he, U, N=None, kernel="jackson", lam=0.0, x_c=1.0):
+    """On-site order parameter from eq. (op1) at T = 0.
+
+    Reading of the printed prefactor (garbled in the source): with the
+    Bogoliubov eigenvectors (u_k(i), v_k(i)) = (<i,e|k>, <i,h|k>),
+    Delta_i = U <c_{i,up} c_{i,down}> = (U/2) sum_k u_k(i) conj(v_k(i)) tanh(E_k/2T),
+    which at T = 0 is (U/2) conj(<i,h| sign(H) |i,e>).  The sign function is
+    replaced by its damped Chebyshev series sum_n g_n c_n T_n(Ht), so
+        Delta_i^new = (U/2) conj( sum_n g_n c_n mu^he_n(i) ).
+    U may be a scalar or a per-row array.
+    """
+    mu_he = np.asarray(mu_he)
+    N = mu_he.shape[-1] if N is None else N
+    w = gap_weights(N, kernel, lam, x_c)
+    s = mu_he @ w
+    return 0.5 * np.asarray(U) * np.conj(s)
+
+
+def ldos_weights(N: int, energies, a: float, b: float, kernel: str = "jackson", lam: float = 0.0):
+    """W[m, n] with N_up(E_m, i) = sum_n W[m, n] mu^ee_n(i), from eq. (ldos) and
+    eq. (imag2):  -(1/pi) Im G^11_ii = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(Et)]
+    / (pi sqrt(1 - Et^2)) per unit of Et, divided by a for energy units,
+    with Et = (E - b)/a."""
+    g = jackson(N) if kernel == "jackson" else lorentz(N, lam)
+    et = (np.asarray(energies, dtype=np.float64) - b) / a
+    T = chebyshev_T(np.arange(N), et).T           # [m, n]
+    pref = np.where(np.arange(N) == 0, 1.0, 2.0) * g
+    return T * pref[None, :] / (np.pi * a * np.sqrt(1.0 - et * et))[:, None]
+
+
+def ldos(mu_ee, energies, a, b, kernel="jackson", lam=0.0):
+    """Local density of states per spin, N_up(E_m, i) for every row i of mu_ee.
+    Returns [rows, n_E]."""
+    mu_ee = np.asarray(mu_ee, dtype=np.float64)
+    W = ldos_weights(mu_ee.shape[-1], energies, a, b, kernel, lam)
+    return mu_ee @ W.T

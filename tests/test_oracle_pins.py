@@ -1,0 +1,422 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check is an exact
+diagonalisation, a closed form, an invariant, quadrature, or finite
+differences, chosen so that a dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails at least one of them.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import workloads as W
+from tests import ed
+
+
+def _small(Lx=6, Ly=5, seed=3, **kw):
+    return W.small_random(Lx, Ly, N=64, seed=seed, **kw)
+
+
+# ---------------------------------------------------------------- P1: ED moments
+@pytest.mark.parametrize("case", [
+    dict(),
+    dict(bc_x=W.PERIODIC, bc_y=W.PERIODIC),
+    dict(bc_x=W.PERIODIC),
+    dict(complex_=True),
+    dict(complex_=True, bond=True, flux=0.25),
+    dict(bond=True),
+])
+def test_moments_equal_exact_diagonalisation(case):
+    w = _small(**case)
+    e0, e1, a, b = oracle.workload_bounds(w)
+    mu_ee, mu_he = oracle.workload_moments(w, a, b, N=96)
+    r_ee, r_he = ed.ed_moments(w, a, b, w.start_sites, 96)
+    assert np.max(np.abs(mu_ee - r_ee.real)) < 1e-12
+    assert np.max(np.abs(r_ee.imag)) < 1e-12
+    assert np.max(np.abs(mu_he - r_he)) < 1e-12
+
+
+def test_config0_moments_equal_exact_diagonalisation():
+    w = W.config0()
+    _, _, a, b = oracle.workload_bounds(w)
+    assert abs(a - 2 * 10.5 / 1.99) < 1e-12      # Gershgorin: |5+0.5| + U/2 + 4t
+    mu_ee, mu_he = oracle.workload_moments(w, a, b)
+    r_ee, r_he = ed.ed_moments(w, a, b, w.start_sites, w.N)
+    assert np.max(np.abs(mu_ee - r_ee.real)) < 1e-12
+    assert np.max(np.abs(mu_he - r_he.real)) < 1e-12
+
+
+def test_nonzero_b_shift_equals_exact_diagonalisation():
+    # an asymmetric interval exercises the -b/a diagonal shift
+    w = _small(seed=11)
+    a, b = 6.5, 0.37
+    mu_ee, mu_he = oracle.workload_moments(w, a, b, N=50)
+    r_ee, r_he = ed.ed_moments(w, a, b, w.start_sites, 50)
+    assert np.max(np.abs(mu_ee - r_ee.real)) < 1e-12
+    assert np.max(np.abs(mu_he - r_he.real)) < 1e-12
+
+
+# ---------------------------------------------- P2: completeness and low moments
+@pytest.mark.parametrize("complex_", [False, True])
+def test_first_moments(complex_):
+    w = _small(complex_=complex_, bond=True, flux=0.3 if complex_ else 0.0)
+    a, b = 7.0, 0.0
+    H = oracle.workload_csr(w, a, b)
+    mu_ee, mu_he = oracle.moments(H, w.start_sites, 3)
+    assert np.all(mu_ee[:, 0] == 1.0) and np.all(mu_he[:, 0] == 0.0)
+    assert np.max(np.abs(mu_ee[:, 1] - (w.eps - w.mu_c - b) / a)) < 1e-15
+    assert np.max(np.abs(mu_he[:, 1] - np.conj(w.delta) / a)) < 1e-15
+    # mu_2 = 2 ||Ht e_{i,e}||^2 - 1, with the column norm from the dense ED matrix
+    Hd = (ed.dense_H(w) - b * np.eye(w.D)) / a
+    col = np.linalg.norm(Hd[:, :w.L2], axis=0) ** 2
+    assert np.max(np.abs(mu_ee[:, 2] - (2 * col - 1))) < 1e-14
+
+
+# ---------------------------------------------------------- P3: particle-hole symmetry
+@pytest.mark.parametrize("case", [dict(), dict(complex_=True, bond=True, flux=0.2)])
+def test_particle_hole_symmetry(case):
+    w = _small(**case)
+    _, _, a, b = oracle.workload_bounds(w)
+    assert b == 0.0
+    mu_ee, mu_he = oracle.workload_moments(w, a, b, N=80)
+    # <i,h|T_n|i,e> vanishes for even n when H anticommutes with C(u,v) = (-v*, u*)
+    assert np.max(np.abs(mu_he[:, 0::2])) < 1e-13
+    # the spectrum is symmetric
+    E = np.linalg.eigvalsh(ed.dense_H(w))
+    assert np.max(np.abs(np.sort(E) + np.sort(E)[::-1])) < 1e-12
+
+
+# ------------------------------------------------- P4: Bloch closed form (periodic)
+@pytest.mark.parametrize("L,N", [(8, 64), (24, 200)])
+def test_bloch_closed_form_periodic(L, N):
+    t, mu, dl = 1.0, -0.3, 0.25
+    w = W.Workload("bloch", L, L, W.PERIODIC, W.PERIODIC, t, mu, 0.0, np.zeros(L * L),
+                   np.full(L * L, dl), None, None, N, np.array([0, L + 3, L * L - 1], np.int32), 3)
+    a = 6.1
+    mu_ee, mu_he = oracle.workload_moments(w, a, 0.0)
+    k = 2 * np.pi * np.arange(L) / L
+    xi = (-2 * t * (np.cos(k)[:, None] + np.cos(k)[None, :]) - mu).ravel()
+    E = np.sqrt(xi ** 2 + dl ** 2)
+    Tp, Tm = ed.cheb_T(np.arange(N), E / a), ed.cheb_T(np.arange(N), -E / a)
+    u2, v2 = (1 + xi / E) / 2, (1 - xi / E) / 2
+    ref_ee = (Tp @ u2 + Tm @ v2) / L ** 2
+    ref_he = ((Tp - Tm) @ (dl / (2 * E))) / L ** 2
+    assert np.max(np.abs(mu_ee - ref_ee[None, :])) < 1e-13
+    assert np.max(np.abs(mu_he - ref_he[None, :])) < 1e-13
+
+
+# ------------------------------------------- P5: open-boundary sine-mode closed form
+def test_open_boundary_sine_modes():
+    Lx, Ly, t, mu, dl, N = 9, 7, 1.0, 0.2, 0.15, 120
+    sites = np.array([0, 4 + 9 * 3, 8 + 9 * 6, 2 + 9 * 1], np.int32)
+    w = W.Workload("sine", Lx, Ly, W.OPEN, W.OPEN, t, mu, 0.0, np.zeros(Lx * Ly),
+                   np.full(Lx * Ly, dl), None, None, N, sites, 4)
+    a = 5.5
+    mu_ee, mu_he = oracle.workload_moments(w, a, 0.0)
+
+    def modes(L):
+        m = np.arange(1, L + 1)
+        x = np.arange(L)
+        phi = np.sqrt(2 / (L + 1)) * np.sin(np.pi * np.outer(m, x + 1) / (L + 1))
+        return -2 * t * np.cos(np.pi * m / (L + 1)), phi
+
+    ex, px = modes(Lx)
+    ey, py = modes(Ly)
+    xi = (ex[:, None] + ey[None, :] - mu).ravel()
+    E = np.sqrt(xi ** 2 + dl ** 2)
+    Tp, Tm = ed.cheb_T(np.arange(N), E / a), ed.cheb_T(np.arange(N), -E / a)
+    for q, s in enumerate(sites):
+        x, y = s % Lx, s // Lx
+        wgt = (px[:, x][:, None] ** 2 * py[:, y][None, :] ** 2).ravel()
+        ref_ee = Tp @ (wgt * (1 + xi / E) / 2) + Tm @ (wgt * (1 - xi / E) / 2)
+        ref_he = (Tp - Tm) @ (wgt * dl / (2 * E))
+        assert np.max(np.abs(mu_ee[q] - ref_ee)) < 1e-13
+        assert np.max(np.abs(mu_he[q] - ref_he)) < 1e-13
+
+
+# ----------------------------------------------------------- P6: atomic limit t = 0
+def test_atomic_limit():
+    rng = np.random.default_rng(5)
+    Lx, Ly, N = 5, 4, 100
+    eps = rng.uniform(-2, 2, Lx * Ly)
+    dl = rng.uniform(0.05, 0.5, Lx * Ly) * np.exp(1j * rng.uniform(-3, 3, Lx * Ly))
+    w = W.Workload("atomic", Lx, Ly, W.OPEN, W.OPEN, 0.0, -0.4, 0.0, eps, dl, None, None, N,
+                   np.arange(Lx * Ly, dtype=np.int32), Lx * Ly, scalar="complex")
+    a = 4.0
+    mu_ee, mu_he = oracle.workload_moments(w, a, 0.0)
+    xi = eps + 0.4
+    R = np.sqrt(xi ** 2 + np.abs(dl) ** 2)
+    Tp, Tm = ed.cheb_T(np.arange(N), R / a).T, ed.cheb_T(np.arange(N), -R / a).T
+    ref_ee = ((1 + xi / R)[:, None] * Tp + (1 - xi / R)[:, None] * Tm) / 2
+    ref_he = (np.conj(dl) / (2 * R))[:, None] * (Tp - Tm)
+    assert np.max(np.abs(mu_ee - ref_ee)) < 1e-13
+    assert np.max(np.abs(mu_he - ref_he)) < 1e-13
+
+
+# ------------------------------------------------------ Peierls phases (Hofstadter)
+@pytest.mark.parametrize("L", [4, 6, 8])
+def test_pi_flux_hofstadter_spectrum(L):
+    """f = 1 puts a hopping phase pi on every plaquette; on an LxL torus the
+    spectrum is then +-2t sqrt(cos^2 kx + cos^2 ky), ky over half the zone."""
+    ph = W.landau_phases(L, L, 1.0)
+    H = oracle.build_csr(L, L, 1, 1, 1.0, 0.0, np.zeros(L * L), np.zeros(L * L), None, ph)
+    Hd = H.to_scipy().toarray()
+    he, hh = Hd[0::2, 0::2], Hd[1::2, 1::2]
+    k = 2 * np.pi * np.arange(L) / L
+    kh = 2 * np.pi * np.arange(L // 2) / L
+    e = 2 * np.sqrt(np.cos(k)[:, None] ** 2 + np.cos(kh)[None, :] ** 2).ravel()
+    ref = np.sort(np.concatenate([e, -e]))
+    assert np.max(np.abs(np.sort(np.linalg.eigvalsh(he)) - ref)) < 1e-12
+    assert np.max(np.abs(np.sort(np.linalg.eigvalsh(hh)) - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("f", [1.0 / 8, 0.3])
+def test_plaquette_flux_gauge_invariant(f):
+    """The hopping phase collected around each plaquette is pi*f (electron block)
+    and -pi*f (hole block), the Peierls substitution after eq. (hamil2)."""
+    Lx, Ly = 6, 5
+    ph = W.landau_phases(Lx, Ly, f)
+    H = oracle.build_csr(Lx, Ly, 0, 0, 1.0, 0.0, np.zeros(Lx * Ly), np.zeros(Lx * Ly), None, ph)
+    Hd = H.to_scipy().toarray()
+    for blk, sgn in ((0, 1.0), (1, -1.0)):
+        h = Hd[blk::2, blk::2]
+        tt = -h if blk == 0 else h        # t_ij in the electron block, conj(t_ij) in the hole block
+        for y in range(Ly - 1):
+            for x in range(Lx - 1):
+                s = x + Lx * y
+                loop = [s, s + 1, s + 1 + Lx, s + Lx, s]
+                prod = np.prod([tt[loop[i], loop[i + 1]] for i in range(4)])
+                assert abs(abs(prod) - 1.0) < 1e-14
+                assert abs(np.angle(prod * np.exp(-1j * sgn * np.pi * f))) < 1e-13
+
+
+# -------------------------------------------------------------- kernels and weights
+@pytest.mark.parametrize("N", [2, 7, 64, 1024])
+def test_jackson_is_autocorrelation_of_sine_window(N):
+    # Jackson's kernel is the normalised autocorrelation of the window sin(pi (k+1)/(N+1))
+    av = np.sin(np.pi * (np.arange(N) + 1) / (N + 1))
+    ac = np.array([np.dot(av[:N - k], av[k:]) for k in range(N)]) / np.dot(av, av)
+    assert np.max(np.abs(oracle.jackson(N) - ac)) < 1e-13
+
+
+def test_jackson_smoothed_delta_is_positive():
+    N = 128
+    g = oracle.jackson(N)
+    x = np.linspace(-0.999, 0.999, 801)
+    for x0 in (-0.7, 0.0, 0.31):
+        mu = ed.cheb_T(np.arange(N), x0)           # moments of delta(x - x0)
+        pref = np.where(np.arange(N) == 0, 1.0, 2.0)
+        f = (pref * g * mu) @ ed.cheb_T(np.arange(N), x) / (np.pi * np.sqrt(1 - x * x))
+        assert f.min() > -1e-12
+        assert abs(np.trapezoid(f, x) - 1.0) < 2e-2
+
+
+def test_lorentz_kernel_endpoints():
+    g = oracle.lorentz(100, 4.0)
+    assert g[0] == 1.0 and abs(g[-1] - np.sinh(4.0 * 0.01) / np.sinh(4.0)) < 1e-15
+
+
+@pytest.mark.parametrize("x_c", [1.0, 0.6, 0.13])
+def test_sign_coefficients_by_quadrature(x_c):
+    N = 41
+    c = oracle.sign_coefficients(N, x_c)
+    tc = np.arccos(x_c)
+    for n in range(N):
+        f = lambda th: np.sign(np.cos(th)) * (abs(np.cos(th)) < x_c) * np.cos(n * th)
+        pts = sorted({tc, np.pi / 2, np.pi - tc})
+        val, _ = integrate.quad(f, 0, np.pi, points=pts, limit=400, epsabs=1e-13)
+        ref = (1 if n == 0 else 2) / np.pi * val
+        assert abs(c[n] - ref) < 1e-11, n
+
+
+def test_sign_series_converges_to_sign():
+    c = oracle.sign_coefficients(4001)
+    x = np.array([-0.9, -0.5, -0.2, 0.3, 0.8])
+    val = c @ ed.cheb_T(np.arange(4001), x)
+    assert np.max(np.abs(val - np.sign(x))) < 2e-2
+
+
+# ------------------------------------------------- P8 / P9: gap equation vs ED
+def test_gap_map_equals_ed_with_same_polynomial_filter():
+    w = W.config0()
+    _, _, a, b = oracle.workload_bounds(w)
+    _, mu_he = oracle.workload_moments(w, a, b)
+    new = oracle.gap_map(mu_he, w.U).real
+    Et, V = ed.eig(w, a, b)
+    p = np.polynomial.chebyshev.chebval(Et, oracle.gap_weights(w.N))
+    u, v = V[:w.L2], V[w.L2:]
+    ref = 0.5 * w.U * np.sum(u * np.conj(v) * p[None, :], axis=1)
+    assert np.max(np.abs(new - ref.real)) < 1e-13
+    assert np.max(np.abs(ref.imag)) < 1e-13
+
+
+def test_gap_map_complex_delta_equals_ed():
+    """With a complex gap the conjugation matters: Delta_i = (U/2) sum_k u_k(i) conj(v_k(i)) p(E_k)."""
+    w = _small(seed=17, complex_=True, bond=True, flux=0.2)
+    _, _, a, b = oracle.workload_bounds(w)
+    N = 120
+    _, mu_he = oracle.workload_moments(w, a, b, N=N)
+    new = oracle.gap_map(mu_he, w.U)
+    Et, V = ed.eig(w, a, b)
+    p = np.polynomial.chebyshev.chebval(Et, oracle.gap_weights(N))
+    ref = 0.5 * w.U * np.sum(V[:w.L2] * np.conj(V[w.L2:]) * p[None, :], axis=1)
+    assert np.max(np.abs(ref.imag)) > 1e-3          # genuinely complex
+    assert np.max(np.abs(new - ref)) < 1e-13
+
+
+def test_gap_map_approaches_exact_ed_with_growing_N():
+    """Physics check, tolerance-bounded: the damped series converges to the
+    exact T = 0 sign weight as N grows."""
+    w = W.config0()
+    _, _, a, b = oracle.workload_bounds(w)
+    Et, V = ed.eig(w, a, b)
+    exact = 0.5 * w.U * np.sum(V[:w.L2] * V[w.L2:] * np.sign(Et)[None, :], axis=1)
+    errs = []
+    for N in (128, 512, 2048):
+        _, mu_he = oracle.workload_moments(w, a, b, N=N)
+        errs.append(np.max(np.abs(oracle.gap_map(mu_he, w.U).real - exact)))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 5e-3
+
+
+def test_atomic_limit_gap_is_bcs():
+    # t = 0: one site obeys Delta = (U/2) Delta / sqrt(xi^2 + Delta^2)
+    xi, U = 0.3, 2.0
+    dstar = np.sqrt((U / 2) ** 2 - xi ** 2)
+    w = W.Workload("bcs", 1, 1, W.OPEN, W.OPEN, 0.0, -xi, U, np.zeros(1), np.array([dstar]),
+                   None, None, 4096, np.array([0], np.int32), 1)
+    a = 2.0
+    _, mu_he = oracle.workload_moments(w, a, 0.0)
+    new = oracle.gap_map(mu_he, U).real
+    assert abs(new[0] - dstar) < 1e-3
+
+
+# ------------------------------------------------------------------------ LDOS
+def test_ldos_equals_kernel_broadened_ed():
+    w = _small(seed=21)
+    _, _, a, b = oracle.workload_bounds(w)
+    N = 200
+    mu_ee, _ = oracle.workload_moments(w, a, b, N=N)
+    E = np.linspace(-2.5, 2.5, 37)
+    got = oracle.ldos(mu_ee, E, a, b)
+    Et, V = ed.eig(w, a, b)
+    g = oracle.jackson(N)
+    x = (E - b) / a
+    # sum_k |u_k(i)|^2 K_N(x, E_k) with the Jackson-damped delta kernel, per unit energy
+    Tx = ed.cheb_T(np.arange(N), x)                                  # [N, m]
+    Tk = ed.cheb_T(np.arange(N), Et)                                 # [N, D]
+    pref = np.where(np.arange(N) == 0, 1.0, 2.0) * g
+    K = (Tk.T * pref) @ Tx / (np.pi * np.sqrt(1 - x * x))[None, :] / a    # [D, m]
+    ref = (np.abs(V[:w.L2]) ** 2) @ K
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    # normalisation: the LDOS integrates to mu_0 = 1 over the band (up to damping tails)
+    Ef = np.linspace(-a * 0.999, a * 0.999, 20001)
+    tot = np.trapezoid(oracle.ldos(mu_ee[:3], Ef, a, b), Ef, axis=1)
+    assert np.max(np.abs(tot - 1.0)) < 2e-2
+
+
+# ---------------------------------------------- P10 / P11 / P12: gradients
+def _dk_gradient(w, a, b, sites, w_ee, w_he):
+    """Daleckii-Krein derivative of L = sum_s <s,e|p_ee(Ht)|s,e> + <s,h|p_he(Ht)|s,e>."""
+    Et, V = ed.eig(w, a, b)
+    N = w_ee.shape[-1]
+    L2 = w.L2
+    D1 = ed.cheb_divided_difference(np.arange(N), Et[:, None], Et[None, :])   # [N, D, D]
+    ge = np.zeros(L2)
+    gd = np.zeros(L2)
+    # B = V^T M V with M = sum_s |s,e><bra_s|, weighted per n
+    P1 = np.zeros((len(Et), len(Et)))
+    Bsum = np.zeros((len(Et), len(Et)))
+    for q, s in enumerate(sites):
+        ket = V[s, :]
+        for wn, brarow in ((w_ee[q], V[s, :]), (w_he[q], V[L2 + s, :])):
+            pk = np.tensordot(wn, D1, axes=(0, 0))                     # [D, D] p^[1]
+            # d<bra|p(H)|ket> = sum_kl bra_k A_kl ket_l p1_kl with A = V^T dH V
+            Bsum += np.outer(brarow, ket) * pk
+    Ve, Vh = V[:L2], V[L2:]
+    for j in range(L2):
+        Ae = (np.outer(Ve[j], Ve[j]) - np.outer(Vh[j], Vh[j])) / a
+        Ad = (np.outer(Ve[j], Vh[j]) + np.outer(Vh[j], Ve[j])) / a
+        ge[j] = np.sum(Ae * Bsum)
+        gd[j] = np.sum(Ad * Bsum)
+    return ge, gd
+
+
+def _loss_weights(w, a, N, sites):
+    rng = np.random.default_rng(9)
+    return rng.normal(size=(len(sites), N)), rng.normal(size=(len(sites), N))
+
+
+def test_backward_equals_daleckii_krein():
+    w = W.small_random(6, 5, N=40, seed=8, n_sites=7)
+    _, _, a, b = oracle.workload_bounds(w)
+    N = 40
+    w_ee, w_he = _loss_weights(w, a, N, w.start_sites)
+    H = oracle.workload_csr(w, a, b)
+    ge, gd = oracle.moments_backward(H, w.start_sites, N, w_ee, w_he)
+    re, rd = _dk_gradient(w, a, b, w.start_sites, w_ee, w_he)
+    scale = max(np.max(np.abs(re)), np.max(np.abs(rd)))
+    assert np.max(np.abs(ge - re)) < 1e-12 * scale
+    assert np.max(np.abs(gd - rd)) < 1e-12 * scale
+
+
+def test_backward_equals_richardson_finite_differences():
+    w = W.small_random(5, 4, N=30, seed=12, n_sites=5)
+    _, _, a, b = oracle.workload_bounds(w)
+    N = 30
+    w_ee, w_he = _loss_weights(w, a, N, w.start_sites)
+    H = oracle.workload_csr(w, a, b)
+    ge, gd = oracle.moments_backward(H, w.start_sites, N, w_ee, w_he)
+
+    def loss(eps, delta):
+        Hq = oracle.build_csr(w.Lx, w.Ly, w.bc_x, w.bc_y, w.t, w.mu_c, eps, delta, None, None, a, b)
+        me, mh = oracle.moments(Hq, w.start_sites, N)
+        return np.sum(w_ee * me) + np.sum(w_he * mh)
+
+    def fd(j, which, h):
+        e, d = w.eps.copy(), np.array(w.delta, dtype=float)
+        arr = e if which == 0 else d
+        arr[j] += h
+        lp = loss(e, d)
+        arr[j] -= 2 * h
+        lm = loss(e, d)
+        return (lp - lm) / (2 * h)
+
+    for j in range(w.L2):
+        for which, g in ((0, ge), (1, gd)):
+            h = 1e-3
+            rich = (4 * fd(j, which, h / 2) - fd(j, which, h)) / 3
+            assert abs(g[j] - rich) < 1e-8 * max(1.0, abs(rich)), (j, which)
+
+
+def test_gap_jacobian_is_symmetric():
+    """J_F[i,j] = dF_i/dDelta_j of the gap map is symmetric for a real operator
+    and uniform U, so one reverse pass serves as a Jacobian-vector product."""
+    w = W.small_random(4, 4, N=48, seed=2)
+    _, _, a, b = oracle.workload_bounds(w)
+    N = 48
+    H = oracle.workload_csr(w, a, b)
+    wg = 0.5 * w.U * oracle.gap_weights(N)
+    J = np.zeros((w.L2, w.L2))
+    for i in range(w.L2):
+        dmu_he = np.zeros((w.L2, N))
+        dmu_he[i] = wg
+        _, gd = oracle.moments_backward(H, w.start_sites, N, np.zeros((w.L2, N)), dmu_he)
+        J[i] = gd
+    assert np.max(np.abs(J - J.T)) < 1e-13 * np.max(np.abs(J))
+
+
+# ---------------------------------------------------------------------- SCF
+def test_scf_matches_ed_self_consistency_with_same_filter():
+    """The oracle's plain-mixing fixed point is a fixed point of the ED gap map
+    with the same polynomial filter."""
+    w = W.config0()
+    delta, it, r, (a, b) = oracle.scf_plain(w, tol=1e-10, max_iter=300)
+    assert r < 1e-10
+    Et, V = ed.eig(w, a, b, delta)
+    p = np.polynomial.chebyshev.chebval(Et, oracle.gap_weights(w.N))
+    ref = 0.5 * w.U * np.sum(V[:w.L2] * V[w.L2:] * p[None, :], axis=1)
+    assert np.max(np.abs(ref - delta)) < 1e-9
+    # the impurity suppresses the gap locally
+    assert delta[W.site(16, 8, 8)] < delta[W.site(16, 2, 2)]
