@@ -1,0 +1,222 @@
+"""Benchmark of the Chebyshev-BdG hot path on one MI355X.
+
+One step = one self-consistency iteration over the whole 256x256 lattice of
+the disordered s-wave workload (t = 1, mu = -0.4, U = 2.5, 1% of sites with
+V ~ U[-2, 2], N = 1024 Jackson-damped moments, all 65536 sites in tiles of
+1024 start vectors, FP64):
+  operator update with the current Delta -> batched Chebyshev moments of all
+  65536 start vectors (64 tiles x 1023 recursion launches) -> T = 0 gap
+  equation with mixing and residual -> LDOS of every site at 64 energies.
+
+Prints one JSON line.  `value` is moments/s (start vectors x N per second)
+with every input resident in HBM.  `roofline` reports the recursion step
+kernel: algorithmic bytes per launch (3 * D * B * 16 B: read a_{n-1}, read
+a_{n-2}, write a_n) over its average launch duration, measured with HIP
+events on the launch stream; `traffic` comes from rocprofv3 counters stored
+under profiles/ (null when they were taken on a different kernel source).
+`cpu_baseline` times the CPU oracle on a bounded sample of start vectors.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Chebyshev moments/sec and HBM GB/s (FP64 vs FP32); self-consistent solve time"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("stencil.hpp", "recursion.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1007_1609_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kind: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "cheb_step_%s_traffic.txt" % kind)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{"):
+                rec = json.loads(line)
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, a, b, n_sites: int, threads: int):
+    import numpy as np
+
+    import oracle
+    sites = np.linspace(0, w.L2 - 1, n_sites).astype(np.int32)
+    H = oracle.workload_csr(w, a, b)
+    t0 = time.perf_counter()
+    oracle.moments(H, sites, w.N, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_sites * w.N / dt, "unit": "moments/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": "%d start sites of the same 256x256 lattice, N=%d, FP64 CSR recursion, "
+                      "%.1f s" % (n_sites, w.N, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--tiles", type=int, default=0, help="limit the number of tiles (0: whole lattice)")
+    ap.add_argument("--cpu-sites", type=int, default=0, help="oracle sample size (0: 2 per thread)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(start vectors would shard across GPUs with one Delta all-gather per iteration)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1007_1609_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    N = 1024 if args.precision == "fp64" else 2048
+    w = W.config1(N=N) if args.precision == "fp64" else W.config2()
+    prec = P.CBDG_FP64 if args.precision == "fp64" else P.CBDG_FP32_ACC64
+    s_bytes = 8 if args.precision == "fp64" else 4
+    tile = w.tile
+    n_tiles_all = (w.L2 + tile - 1) // tile
+    n_tiles = n_tiles_all if args.tiles <= 0 else min(args.tiles, n_tiles_all)
+    n_sites = min(w.L2, n_tiles * tile)
+
+    op = P.Operator.from_workload(w, dev)
+    a, b = op.bounds.a, op.bounds.b
+    wts = op.weights()
+    sites = torch.arange(n_sites, dtype=torch.int32, device=dev)
+    ws = P.workspace(P.moments_workspace_bytes(op, tile, prec), dev)
+    mu_ee = torch.empty((n_sites, N), dtype=torch.float64, device=dev)
+    mu_he = torch.empty((n_sites, N), dtype=torch.float64, device=dev)
+    delta = torch.as_tensor(w.delta[:n_sites], device=dev).clone()
+    delta_full = torch.as_tensor(w.delta, device=dev).clone()
+    nxt = torch.empty_like(delta)
+    resid = torch.empty(1, dtype=torch.float64, device=dev)
+    energies = torch.linspace(-1.0, 1.0, 64, dtype=torch.float64, device=dev)
+    ldos = torch.empty((n_sites, 64), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    tile_events = []
+
+    def step(record):
+        nonlocal delta, nxt
+        op.update_delta(delta_full)
+        for k in range(n_tiles):
+            lo, hi = k * tile, min(n_sites, (k + 1) * tile)
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            P.chebyshev_moments(op, sites[lo:hi], N, tile, prec, ws=ws, out=(mu_ee[lo:hi], mu_he[lo:hi]))
+            if record:
+                e1.record(stream)
+                tile_events.append((e0, e1, hi - lo))
+        P.gap_update(mu_he, wts, w.U, delta, 1.0, delta_out=nxt, resid=resid)
+        P.ldos(mu_ee, wts, energies, out=ldos)
+        delta, nxt = nxt, delta
+        delta_full[:n_sites].copy_(delta)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_stop)
+    ms_per_step = ms_total / args.steps
+    moments_per_step = n_sites * N
+    value = moments_per_step * args.steps / (ms_total / 1e3)
+
+    # dominant kernel: the recursion step; one tile call = N-1 step launches
+    # (plus a buffer clear and a seed kernel, counted against the step kernel)
+    launches = 0
+    kern_ms = 0.0
+    alg_bytes = 0.0
+    D = 2 * w.L2
+    for e0, e1, bt in tile_events:
+        kern_ms += e0.elapsed_time(e1)
+        launches += N - 1
+        bp = (bt + 63) // 64 * 64
+        alg_bytes += (N - 1) * 3.0 * D * bp * s_bytes
+    avg_launch_ms = kern_ms / launches
+    bytes_per_launch = alg_bytes / launches
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    traffic = stored_traffic(args.precision)
+    ok = P.check_moments(mu_ee, mu_he, 1e-9 if args.precision == "fp64" else 1e-4)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "moments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 recursion, f64 moments and sums",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: 256x256 open lattice, 655 disordered sites V~U[-2,2] (seed 1), "
+                        "t=1 mu=-0.4 U=2.5, N=%d Jackson, %d start sites in tiles of %d, "
+                        "one SCF iteration (moments + gap update + LDOS at 64 energies) per step"
+                        % (w.name, N, n_sites, tile, ),
+            "lattice": [w.Lx, w.Ly], "N": N, "start_sites": n_sites, "tile": tile,
+            "precision": args.precision, "bounds_a": a,
+        },
+        "roofline": {
+            "kernel": "k_cheb_step<%s>" % ("double" if s_bytes == 8 else "float"),
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": avg_launch_ms * 1e3,
+            "launches_timed": launches,
+        },
+        "moments_bounded": bool(ok),
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+        n_cpu = args.cpu_sites or max(8, min(64, 2 * threads))
+        line["cpu_baseline"] = cpu_baseline(w, a, b, n_cpu, threads)
+    else:
+        line["cpu_baseline"] = None
+    op.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * cbdg.h -- C ABI of the Chebyshev-BdG hot path on MI355X (gfx950).
+ *
+ * Method: L. Covaci, F. M. Peeters, M. Berciu, "Chebyshev-BdG: an efficient
+ * numerical approach to inhomogeneous superconductivity" (arXiv:1007.1609).
+ * The library builds the rescaled Nambu BdG operator of eq. (hamil2), runs
+ * the vector recursion of eq. (ref2) from many start vectors |s,e> at once,
+ * reads the local moments of eqs. (coeff1)/(coeff2), and turns them into the
+ * order parameter (eq. (op1)) and the local density of states (eq. (ldos)).
+ * Reverse-mode derivatives of each step are provided.
+ *
+ * Conventions fixed at this boundary
+ *   - Lattice site index s = x + Lx*y (x fastest), 0 <= s < L2 = Lx*Ly.
+ *   - Nambu components: e = c^dag_{s,up}|vac> (electron), h = c_{s,down}|vac>
+ *     (hole); the start vector of a recursion is |s,e>.
+ *   - Moments: mu_ee[k*N + n] = <s,e|T_n(Ht)|s,e> and
+ *     mu_he[k*N + n] = <s,h|T_n(Ht)|s,e> for s = start_sites[k],
+ *     n = 0..N-1, Ht = (H - b)/a.  They are the paper's a_n^{11}, a_n^{12}
+ *     without the 1/(1 + delta_{0n}) factor, so mu_ee[k*N] = 1.
+ *   - Complex values are interleaved (re, im) FP64 (complex128) unless
+ *     stated.  "scalar" selects real FP64 or complex128 for Delta and mu_he.
+ *   - Energies are in units of the hopping t's unit; LDOS is per spin (N_up)
+ *     per unit energy.
+ *
+ * Memory and streams
+ *   - Every array argument is a caller-owned, contiguous DEVICE pointer unless
+ *     marked "host".  The library never frees or retains a caller pointer
+ *     past the call.  The only library-owned object is cbdg_op (coefficient
+ *     copies), released with cbdg_op_destroy.
+ *   - Workspaces are caller-allocated device memory of at least the size the
+ *     matching *_workspace_size call returns.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued asynchronously on it; no call synchronises except
+ *     cbdg_build_bdg when it computes the spectral bounds (fixed == NULL),
+ *     which waits for one scalar.
+ *   - Calls that share an operator or workspace on different streams race;
+ *     order them on one stream.
+ *
+ * Errors
+ *   Every call returns CBDG_OK (0) or a negative code; cbdg_last_error()
+ *   returns a message for the last failure on the calling thread.  Argument
+ *   errors are detected on the host before any device work is enqueued.
+ *   Values that live on the device (start sites, energies) cannot be checked
+ *   on the host: a start site outside [0, L2) yields a row of NaN moments and
+ *   an energy outside the expansion interval yields NaN LDOS values, both of
+ *   which cbdg_check_moments / the caller can detect.
+ */
+#ifndef CBDG_H
+#define CBDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CBDG_OK            0
+#define CBDG_EINVAL       -1  /* bad argument (detected on the host)          */
+#define CBDG_ENOMEM       -2  /* device allocation failed                      */
+#define CBDG_EHIP         -3  /* a HIP runtime call or kernel launch failed    */
+#define CBDG_EBOUNDS      -4  /* spectrum not inside [-1, 1] after rescaling   */
+#define CBDG_EUNSUPPORTED -5  /* valid request this build does not implement   */
+
+enum cbdg_bc { CBDG_BC_OPEN = 0, CBDG_BC_PERIODIC = 1 };
+enum cbdg_scalar { CBDG_REAL = 0, CBDG_COMPLEX = 1 };
+enum cbdg_precision { CBDG_FP64 = 0, CBDG_FP32_ACC64 = 1 };
+enum cbdg_kernel { CBDG_KERNEL_JACKSON = 0, CBDG_KERNEL_LORENTZ = 1 };
+
+/* Lattice geometry and number type (host struct).
+ * Periodic directions need at least 3 sites. */
+typedef struct cbdg_lattice {
+    int32_t Lx, Ly;
+    int32_t bc_x, bc_y;   /* enum cbdg_bc */
+    int32_t scalar;       /* enum cbdg_scalar */
+} cbdg_lattice;
+
+/* Spectral interval and rescaling Ht = (H - b)/a (host struct). */
+typedef struct cbdg_bounds {
+    double E_min, E_max;  /* interval that contains the spectrum of H        */
+    double a, b;          /* a = (E_max - E_min)/(2 - eta), b = (E_max+E_min)/2 */
+} cbdg_bounds;
+
+/* Kernel damping and energy weighting of the truncated expansion (host).
+ *   kernel  CBDG_KERNEL_JACKSON (default) or CBDG_KERNEL_LORENTZ with
+ *           parameter lambda (broadening lambda/N in rescaled units)
+ *   T       temperature; only T = 0 is implemented (else EUNSUPPORTED)
+ *   E_c     cutoff energy of the gap equation (<= 0: no cutoff)
+ *   a, b    the operator's rescaling (from cbdg_bounds) */
+typedef struct cbdg_weights {
+    int32_t kernel;
+    double lambda;
+    double T;
+    double E_c;
+    double a, b;
+} cbdg_weights;
+
+typedef struct cbdg_op cbdg_op;
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *cbdg_last_error(void);
+
+/*
+ * Build the rescaled BdG operator of eq. (hamil2):
+ *   on-site 2x2 block  [[eps_i - mu_c, Delta_i], [conj(Delta_i), -(eps_i - mu_c)]]
+ *   bond 2x2 block     [[-t_ij, Delta_ij], [conj(Delta_ij), conj(t_ij)]]
+ * with t_ij = t exp(i theta_ij) on the bond i -> j = i + x^ (or + y^),
+ * t_ji = conj(t_ij), Delta_ji = Delta_ij (Peierls phases: the paragraph after
+ * eq. (hamil2)), and the rescaling of the paragraph after eq. (rec).
+ *
+ *   lat          host; geometry and scalar type
+ *   t, mu_c      hopping amplitude and chemical potential
+ *   eps          [L2] FP64 on-site potential
+ *   delta        [L2] on-site Delta_i, FP64 (REAL) or complex128 (COMPLEX)
+ *   delta_bond   [2*L2] or NULL: bond Delta for the bond s -> s+x^ (first L2
+ *                entries) and s -> s+y^ (next L2), same scalar type as delta;
+ *                entries of bonds that leave an open lattice are ignored
+ *   peierls      [2*L2] FP64 or NULL: phase theta of the same bonds; needs
+ *                lat->scalar == CBDG_COMPLEX
+ *   fixed        host or NULL.  NULL: compute the Gershgorin bound R = max
+ *                row sum of |H| with every |Delta_i| raised to at least
+ *                delta_cap, set E_max = -E_min = R, b = 0,
+ *                a = 2R/(2 - eta) (synchronises on one scalar).  Otherwise
+ *                use fixed->a and fixed->b as given (a > 0).
+ *   delta_cap    >= 0, see fixed (U/2 keeps the bound valid for every
+ *                iterate of the gap map)
+ *   eta          in (0, 1): safety margin of the rescaling
+ *   op           host out: new operator handle (library-owned)
+ *   out          host out or NULL: the bounds used
+ * The operator keeps FP64 and FP32 copies of the rescaled coefficients;
+ * the input arrays are not retained.
+ */
+int cbdg_build_bdg(const cbdg_lattice *lat, double t, double mu_c,
+                   const double *eps, const void *delta, const void *delta_bond,
+                   const double *peierls, const cbdg_bounds *fixed,
+                   double delta_cap, double eta, void *stream,
+                   cbdg_op **op, cbdg_bounds *out);
+
+/* Replace the operator's on-site (and, if delta_bond != NULL and the operator
+ * was built with bond pairing, bond) order parameter, keeping a and b frozen:
+ * the self-consistency update of the paragraph after the current density.
+ * Same layouts as cbdg_build_bdg. */
+int cbdg_op_update_delta(cbdg_op *op, const void *delta, const void *delta_bond,
+                         void *stream);
+
+/* Release an operator (NULL is a no-op).  Synchronises the device. */
+int cbdg_op_destroy(cbdg_op *op);
+
+/* Rescaling (a, b) of an operator (host out). */
+int cbdg_op_bounds(const cbdg_op *op, cbdg_bounds *out);
+
+/* Bytes of workspace cbdg_chebyshev_moments needs for tiles of `tile` start
+ * vectors at `precision` (host out). */
+int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision,
+                                size_t *bytes);
+
+/*
+ * Chebyshev moments of eqs. (coeff1)/(coeff2) through the vector recursion
+ * of eq. (ref2):  a_0 = |s,e>,  a_1 = Ht a_0,  a_n = 2 Ht a_{n-1} - a_{n-2},
+ * mu_ee[k][n] = <s,e|a_n>,  mu_he[k][n] = <s,h|a_n>.
+ * The start vectors are processed in tiles of `tile` vectors; all tiles run
+ * inside this call.
+ *   start_sites  [n_start] int32 lattice sites (duplicates allowed)
+ *   n_start      >= 0 (0: nothing is done)
+ *   N            number of moments, >= 1
+ *   tile         start vectors per tile, >= 1
+ *   precision    CBDG_FP64, or CBDG_FP32_ACC64: recursion vectors and
+ *                coefficients in FP32 (complex64 for COMPLEX), moments
+ *                widened exactly to FP64
+ *   workspace    >= cbdg_moments_workspace_size(op, tile, precision) bytes
+ *   mu_ee        out [n_start*N] FP64
+ *   mu_he        out [n_start*N] FP64 (REAL) or complex128 (COMPLEX)
+ */
+int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                           int32_t N, int32_t tile, int32_t precision,
+                           void *workspace, size_t workspace_bytes,
+                           double *mu_ee, void *mu_he, void *stream);
+
+/* Bounds check of moments: |mu| <= 1 holds for every moment when the
+ * spectrum of Ht lies in [-1, 1].  Writes 1 to *flag if any |mu_ee| or
+ * |mu_he| exceeds 1 + tol or is not finite, else 0.
+ *   flag  out, one int32 on the device */
+int cbdg_check_moments(const double *mu_ee, const void *mu_he, int64_t n_rows, int32_t N,
+                       int32_t scalar, double tol, int32_t *flag, void *stream);
+
+/*
+ * One step of the T = 0 gap equation, eq. (op1), from the anomalous moments:
+ *   Delta_new[r] = (U_r/2) conj( sum_n g_n c_n mu_he[r][n] )
+ * where g_n is the kernel and c_n are the Chebyshev coefficients of the
+ * weight (1 - 2f(E)) = sign(E) on |E| < E_c; then plain mixing
+ *   delta_out[r] = (1 - alpha) delta_in[r] + alpha Delta_new[r]
+ * and the residual *resid = max_r |Delta_new[r] - delta_in[r]|.
+ *   mu_he      [n_rows*N] FP64 (REAL) or complex128 (COMPLEX)
+ *   U, U_rows  coupling: U_rows ([n_rows] FP64) if not NULL, else U
+ *   delta_in   [n_rows], delta_out [n_rows] (may alias delta_in)
+ *   resid      out, one FP64 on the device (NaN if any Delta_new is NaN)
+ */
+int cbdg_gap_update(const void *mu_he, int64_t n_rows, int32_t N, int32_t scalar,
+                    const cbdg_weights *w, double U, const double *U_rows,
+                    const void *delta_in, double alpha, void *delta_out,
+                    double *resid, void *stream);
+
+/*
+ * Local density of states per spin, eq. (ldos) with eq. (imag2):
+ *   ldos[r][m] = [g_0 mu_ee[r][0] + 2 sum_{n>=1} g_n mu_ee[r][n] T_n(x_m)]
+ *                / (pi a sqrt(1 - x_m^2)),   x_m = (energies[m] - b)/a
+ *   mu_ee     [n_rows*N] FP64
+ *   energies  [n_E] FP64; |x_m| >= 1 gives NaN
+ *   ldos      out [n_rows*n_E] FP64
+ */
+int cbdg_ldos(const double *mu_ee, int64_t n_rows, int32_t N, const cbdg_weights *w,
+              const double *energies, int32_t n_E, double *ldos, void *stream);
+
+/* Transpose of cbdg_gap_update for a REAL operator:
+ *   d_mu_he[r][n] = alpha (U_r/2) g_n c_n d_delta_out[r]
+ *   d_delta_in[r] = (1 - alpha) d_delta_out[r]        (if d_delta_in != NULL)
+ * Outputs are overwritten.  COMPLEX returns EUNSUPPORTED. */
+int cbdg_gap_update_backward(const double *d_delta_out, int64_t n_rows, int32_t N,
+                             const cbdg_weights *w, double U, const double *U_rows,
+                             double alpha, double *d_mu_he, double *d_delta_in,
+                             void *stream);
+
+/* Transpose of cbdg_ldos:  d_mu_ee[r][n] = sum_m d_ldos[r][m] W[m][n]
+ * (overwritten). */
+int cbdg_ldos_backward(const double *d_ldos, int64_t n_rows, int32_t N,
+                       const cbdg_weights *w, const double *energies, int32_t n_E,
+                       double *d_mu_ee, void *stream);
+
+/* Bytes of workspace cbdg_chebyshev_moments_backward needs (host out).
+ * ckpt_stride 0 selects k = ceil(sqrt(N)). */
+int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
+                                 int32_t ckpt_stride, size_t *bytes);
+
+/*
+ * Reverse-mode derivative of the moments for a REAL FP64 operator with
+ * (a, b) held fixed.  For L = sum_k sum_n (dmu_ee[k][n] mu_ee[k][n] +
+ * dmu_he[k][n] mu_he[k][n]) it ADDS dL/deps_j to grad_eps[j] and dL/dDelta_j
+ * to grad_delta[j] (on-site, real).  Per tile: a forward pass stores the
+ * vector pairs (a_{jk}, a_{jk+1}) every k = ckpt_stride steps; segments are
+ * then recomputed in reverse and the transposed recursion
+ *   lam_n = w_n + 2 Ht^T lam_{n+1} - lam_{n+2}
+ * runs over them, accumulating sum_{n>=1} c_n <lam_n, dHt/dtheta a_{n-1}>
+ * (c_1 = 1, c_n = 2).  The sum over start vectors is reduced in a fixed
+ * order, so repeated calls give identical bits.
+ *   dmu_ee, dmu_he  [n_start*N] FP64 (either may be NULL: zero)
+ *   grad_eps, grad_delta  [L2] FP64, accumulated into (caller zeroes)
+ * COMPLEX operators, bond pairing or Peierls phases return EUNSUPPORTED.
+ */
+int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t *start_sites,
+                                    int64_t n_start, int32_t N, int32_t tile,
+                                    int32_t ckpt_stride, const double *dmu_ee,
+                                    const double *dmu_he, void *workspace,
+                                    size_t workspace_bytes, double *grad_eps,
+                                    double *grad_delta, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBDG_H */

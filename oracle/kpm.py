@@ -51,12 +51,40 @@ def sign_coefficients(N: int, x_c: float = 1.0) -> np.ndarray:
     return c
 
 
-def gap_weights(N: int, kernel: str = "jackson", lam: float = 0.0, x_c: float = 1.0):
+def sign_weight_coefficients(N: int, a: float = 1.0, b: float = 0.0, E_c: float = 0.0) -> np.ndarray:
+    """Chebyshev coefficients of w(x) = sign(E) on |E| < E_c (E_c <= 0: no
+    cutoff), E = a x + b, the T = 0 weight (1 - 2f(E)) of eq. (op1) for any
+    rescaling.  With x = cos(theta) the weight is piecewise constant in theta:
+    +1 between acos(x_hi) and acos(x_0), -1 between acos(x_0) and acos(x_lo),
+    x_0 = -b/a, x_hi = (E_c - b)/a, x_lo = (-E_c - b)/a clipped to [-1, 1];
+    each piece integrates cos(n theta) exactly.
+    """
+    x0 = -b / a
+    if E_c > 0:
+        xhi, xlo = min((E_c - b) / a, 1.0), max((-E_c - b) / a, -1.0)
+    else:
+        xhi, xlo = 1.0, -1.0
+    pieces = [(np.arccos(xhi), np.arccos(x0), 1.0), (np.arccos(x0), np.arccos(xlo), -1.0)]
+    n = np.arange(N, dtype=np.float64)
+    c = np.zeros(N)
+    for lo, hi, val in pieces:
+        c[0] += val * (hi - lo) / np.pi
+        c[1:] += val * 2.0 / np.pi * (np.sin(n[1:] * hi) - np.sin(n[1:] * lo)) / n[1:]
+    return c
+
+
+def gap_weights(N: int, kernel: str = "jackson", lam: float = 0.0, x_c: float = 1.0,
+                a: float = None, b: float = 0.0, E_c: float = 0.0):
+    """g_n c_n of the gap equation.  With a given, the general weight
+    sign(E) on |E| < E_c for the rescaling (a, b); else the b = 0 closed form
+    with rescaled cutoff x_c."""
     g = jackson(N) if kernel == "jackson" else lorentz(N, lam)
+    if a is not None:
+        return g * sign_weight_coefficients(N, a, b, E_c)
     return g * sign_coefficients(N, x_c)
 
 
-def gap_map(mu_he, U, N=None, kernel="jackson", lam=0.0, x_c=1.0):
+def gap_map(mu_he, U, N=None, kernel="jackson", lam=0.0, x_c=1.0, a=None, b=0.0, E_c=0.0):
     """On-site order parameter from eq. (op1) at T = 0.
 
     Reading of the printed prefactor (garbled in the source): with the
@@ -69,7 +97,7 @@ def gap_map(mu_he, U, N=None, kernel="jackson", lam=0.0, x_c=1.0):
     """
     mu_he = np.asarray(mu_he)
     N = mu_he.shape[-1] if N is None else N
-    w = gap_weights(N, kernel, lam, x_c)
+    w = gap_weights(N, kernel, lam, x_c, a, b, E_c)
     s = mu_he @ w
     return 0.5 * np.asarray(U) * np.conj(s)
 

@@ -1,0 +1,238 @@
+"""Torch-facing helpers over the C ABI.
+
+PyTorch supplies device memory and the current HIP stream; every number is
+computed by libcbdg.so.  Inputs must already be contiguous device tensors of
+the documented dtype (float64, complex128 for complex Delta, int32 sites);
+nothing is converted silently.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    return t.data_ptr()
+
+
+def weights(a: float, b: float, kernel: str = "jackson", lam: float = 0.0, T: float = 0.0,
+            E_c: float = 0.0) -> L.cbdg_weights:
+    k = {"jackson": L.CBDG_KERNEL_JACKSON, "lorentz": L.CBDG_KERNEL_LORENTZ}[kernel]
+    return L.cbdg_weights(k, float(lam), float(T), float(E_c), float(a), float(b))
+
+
+@dataclass
+class Bounds:
+    E_min: float
+    E_max: float
+    a: float
+    b: float
+
+
+class Operator:
+    """Handle of a rescaled BdG operator (cbdg_build_bdg / cbdg_op_destroy)."""
+
+    def __init__(self, Lx, Ly, t, mu_c, eps, delta, delta_bond=None, peierls=None, *,
+                 bc_x=0, bc_y=0, complex_=False, fixed: Optional[Tuple[float, float]] = None,
+                 delta_cap=0.0, eta=0.01):
+        L.load()
+        self.Lx, self.Ly = int(Lx), int(Ly)
+        self.scalar = L.CBDG_COMPLEX if complex_ else L.CBDG_REAL
+        ddt = torch.complex128 if complex_ else torch.float64
+        lat = L.cbdg_lattice(self.Lx, self.Ly, int(bc_x), int(bc_y), self.scalar)
+        fb = None
+        if fixed is not None:
+            a, b = fixed
+            fb = L.cbdg_bounds(b - a, b + a, float(a), float(b))
+        out = L.cbdg_bounds()
+        h = C.c_void_p()
+        L.cbdg_build_bdg(C.byref(lat), float(t), float(mu_c), _ptr(eps, torch.float64, "eps"),
+                         _ptr(delta, ddt, "delta"), _ptr(delta_bond, ddt, "delta_bond"),
+                         _ptr(peierls, torch.float64, "peierls"),
+                         C.byref(fb) if fb is not None else None, float(delta_cap), float(eta),
+                         _stream(), C.byref(h), C.byref(out))
+        self.handle = h
+        self.bounds = Bounds(out.E_min, out.E_max, out.a, out.b)
+        self.has_bond = delta_bond is not None
+        self._alive = True
+
+    @classmethod
+    def from_workload(cls, w, device="cuda", delta=None, fixed=None):
+        cplx = w.scalar == "complex"
+        ddt = torch.complex128 if cplx else torch.float64
+        eps = torch.as_tensor(w.eps, dtype=torch.float64, device=device).contiguous()
+        dl = torch.as_tensor(w.delta if delta is None else delta, dtype=ddt, device=device).contiguous()
+        db = None if w.delta_bond is None else torch.as_tensor(
+            w.delta_bond.reshape(-1) if cplx else w.delta_bond.real.reshape(-1), dtype=ddt,
+            device=device).contiguous()
+        ph = None if w.peierls is None else torch.as_tensor(
+            w.peierls.reshape(-1), dtype=torch.float64, device=device).contiguous()
+        return cls(w.Lx, w.Ly, w.t, w.mu_c, eps, dl, db, ph, bc_x=w.bc_x, bc_y=w.bc_y,
+                   complex_=cplx, fixed=fixed, delta_cap=w.delta_cap, eta=w.eta)
+
+    @property
+    def L2(self):
+        return self.Lx * self.Ly
+
+    @property
+    def is_complex(self):
+        return self.scalar == L.CBDG_COMPLEX
+
+    def update_delta(self, delta: torch.Tensor, delta_bond: Optional[torch.Tensor] = None):
+        ddt = torch.complex128 if self.is_complex else torch.float64
+        L.cbdg_op_update_delta(self.handle, _ptr(delta, ddt, "delta"),
+                               _ptr(delta_bond, ddt, "delta_bond"), _stream())
+
+    def weights(self, kernel="jackson", lam=0.0, E_c=0.0):
+        return weights(self.bounds.a, self.bounds.b, kernel, lam, 0.0, E_c)
+
+    def close(self):
+        if getattr(self, "_alive", False):
+            L.cbdg_op_destroy(self.handle)
+            self._alive = False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def moments_workspace_bytes(op: Operator, tile: int, precision: int = L.CBDG_FP64) -> int:
+    n = C.c_size_t()
+    L.cbdg_moments_workspace_size(op.handle, int(tile), int(precision), C.byref(n))
+    return n.value
+
+
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def chebyshev_moments(op: Operator, sites: torch.Tensor, N: int, tile: int,
+                      precision: int = L.CBDG_FP64, ws: Optional[torch.Tensor] = None,
+                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+    """mu_ee [n, N] float64 and mu_he [n, N] (float64 or complex128)."""
+    n = int(sites.numel())
+    eff = max(1, min(int(tile), n))
+    need = moments_workspace_bytes(op, eff, precision)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, sites.device)
+    if out is None:
+        mu_ee = torch.empty((n, N), dtype=torch.float64, device=sites.device)
+        mu_he = torch.empty((n, N), dtype=torch.complex128 if op.is_complex else torch.float64,
+                            device=sites.device)
+    else:
+        mu_ee, mu_he = out
+    L.cbdg_chebyshev_moments(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N), int(tile),
+                             int(precision), _ptr(ws, None, "workspace"), ws.numel(),
+                             _ptr(mu_ee, torch.float64, "mu_ee"), _ptr(mu_he, None, "mu_he"),
+                             _stream())
+    return mu_ee, mu_he
+
+
+def check_moments(mu_ee: torch.Tensor, mu_he: torch.Tensor, tol: float = 1e-9) -> bool:
+    """True when every moment is finite with |mu| <= 1 + tol (synchronises)."""
+    flag = torch.empty(1, dtype=torch.int32, device=mu_ee.device)
+    n, N = mu_ee.shape
+    L.cbdg_check_moments(_ptr(mu_ee, torch.float64, "mu_ee"), _ptr(mu_he, None, "mu_he"), n, N,
+                         L.CBDG_COMPLEX if mu_he.is_complex() else L.CBDG_REAL, float(tol),
+                         _ptr(flag), _stream())
+    return int(flag.item()) == 0
+
+
+def gap_update(mu_he: torch.Tensor, w: L.cbdg_weights, U: float, delta_in: torch.Tensor,
+               alpha: float = 1.0, U_rows: Optional[torch.Tensor] = None,
+               delta_out: Optional[torch.Tensor] = None, resid: Optional[torch.Tensor] = None):
+    n, N = mu_he.shape
+    cplx = mu_he.is_complex()
+    if delta_out is None:
+        delta_out = torch.empty_like(delta_in)
+    if resid is None:
+        resid = torch.empty(1, dtype=torch.float64, device=mu_he.device)
+    ddt = torch.complex128 if cplx else torch.float64
+    L.cbdg_gap_update(_ptr(mu_he, ddt, "mu_he"), n, N, L.CBDG_COMPLEX if cplx else L.CBDG_REAL,
+                      C.byref(w), float(U), _ptr(U_rows, torch.float64, "U_rows"),
+                      _ptr(delta_in, ddt, "delta_in"), float(alpha), _ptr(delta_out, ddt, "delta_out"),
+                      _ptr(resid, torch.float64, "resid"), _stream())
+    return delta_out, resid
+
+
+def ldos(mu_ee: torch.Tensor, w: L.cbdg_weights, energies: torch.Tensor,
+         out: Optional[torch.Tensor] = None):
+    n, N = mu_ee.shape
+    nE = int(energies.numel())
+    if out is None:
+        out = torch.empty((n, nE), dtype=torch.float64, device=mu_ee.device)
+    L.cbdg_ldos(_ptr(mu_ee, torch.float64, "mu_ee"), n, N, C.byref(w),
+                _ptr(energies, torch.float64, "energies"), nE, _ptr(out, torch.float64, "ldos"),
+                _stream())
+    return out
+
+
+def gap_update_backward(d_delta_out: torch.Tensor, N: int, w: L.cbdg_weights, U: float,
+                        alpha: float = 1.0, U_rows: Optional[torch.Tensor] = None,
+                        want_delta_in: bool = True):
+    n = int(d_delta_out.numel())
+    d_mu = torch.empty((n, N), dtype=torch.float64, device=d_delta_out.device)
+    d_in = torch.empty_like(d_delta_out) if want_delta_in else None
+    L.cbdg_gap_update_backward(_ptr(d_delta_out, torch.float64, "d_delta_out"), n, int(N), C.byref(w),
+                               float(U), _ptr(U_rows, torch.float64, "U_rows"), float(alpha),
+                               _ptr(d_mu, torch.float64, "d_mu_he"), _ptr(d_in, torch.float64, "d_delta_in"),
+                               _stream())
+    return d_mu, d_in
+
+
+def ldos_backward(d_ldos: torch.Tensor, N: int, w: L.cbdg_weights, energies: torch.Tensor):
+    n, nE = d_ldos.shape
+    d_mu = torch.empty((n, N), dtype=torch.float64, device=d_ldos.device)
+    L.cbdg_ldos_backward(_ptr(d_ldos, torch.float64, "d_ldos"), n, int(N), C.byref(w),
+                         _ptr(energies, torch.float64, "energies"), nE, _ptr(d_mu, torch.float64, "d_mu_ee"),
+                         _stream())
+    return d_mu
+
+
+def backward_workspace_bytes(op: Operator, tile: int, N: int, ckpt_stride: int = 0) -> int:
+    n = C.c_size_t()
+    L.cbdg_backward_workspace_size(op.handle, int(tile), int(N), int(ckpt_stride), C.byref(n))
+    return n.value
+
+
+def chebyshev_moments_backward(op: Operator, sites: torch.Tensor, N: int, tile: int,
+                               dmu_ee: Optional[torch.Tensor], dmu_he: Optional[torch.Tensor],
+                               ckpt_stride: int = 0, grad_eps: Optional[torch.Tensor] = None,
+                               grad_delta: Optional[torch.Tensor] = None,
+                               ws: Optional[torch.Tensor] = None):
+    n = int(sites.numel())
+    eff = max(1, min(int(tile), n))
+    need = backward_workspace_bytes(op, eff, N, ckpt_stride)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, sites.device)
+    if grad_eps is None:
+        grad_eps = torch.zeros(op.L2, dtype=torch.float64, device=sites.device)
+    if grad_delta is None:
+        grad_delta = torch.zeros(op.L2, dtype=torch.float64, device=sites.device)
+    L.cbdg_chebyshev_moments_backward(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N),
+                                      int(tile), int(ckpt_stride),
+                                      _ptr(dmu_ee, torch.float64, "dmu_ee"),
+                                      _ptr(dmu_he, torch.float64, "dmu_he"),
+                                      _ptr(ws, None, "workspace"), ws.numel(),
+                                      _ptr(grad_eps, torch.float64, "grad_eps"),
+                                      _ptr(grad_delta, torch.float64, "grad_delta"), _stream())
+    return grad_eps, grad_delta

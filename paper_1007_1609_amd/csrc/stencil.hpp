@@ -1,0 +1,188 @@
+// Device-side building blocks of the matrix-free Nambu BdG stencil:
+// Nambu pairs of one start vector at one site, their loads and stores, and
+// the action of the rescaled operator Ht on one site (eq. (hamil2)).
+#pragma once
+
+#include "common.hpp"
+
+namespace cbdg {
+
+// One Nambu pair (electron, hole) of one vector at one site.
+template <typename T, bool C> struct Pair;
+template <typename T> struct Pair<T, false> { T e, h; };
+template <typename T> struct Pair<T, true> { T er, ei, hr, hi; };
+
+template <typename T, bool C> struct Storage;
+template <> struct Storage<double, false> { using type = double2; };
+template <> struct Storage<float, false> { using type = float2; };
+template <> struct Storage<double, true> { using type = double4; };
+template <> struct Storage<float, true> { using type = float4; };
+
+template <typename T, bool C> __device__ __forceinline__ Pair<T, C> zero_pair()
+{
+    Pair<T, C> p;
+    if constexpr (C) { p.er = p.ei = p.hr = p.hi = T(0); }
+    else { p.e = p.h = T(0); }
+    return p;
+}
+
+template <typename T, bool C>
+__device__ __forceinline__ Pair<T, C> ld(const typename Storage<T, C>::type *p)
+{
+    Pair<T, C> r;
+    if constexpr (C) {
+        if constexpr (sizeof(T) == 8) {
+            const double2 *q = reinterpret_cast<const double2 *>(p);
+            double2 u = q[0], v = q[1];
+            r.er = u.x; r.ei = u.y; r.hr = v.x; r.hi = v.y;
+        } else {
+            float4 u = *p;
+            r.er = u.x; r.ei = u.y; r.hr = u.z; r.hi = u.w;
+        }
+    } else {
+        auto u = *p;
+        r.e = u.x; r.h = u.y;
+    }
+    return r;
+}
+
+template <typename T, bool C>
+__device__ __forceinline__ void st(typename Storage<T, C>::type *p, const Pair<T, C> &v)
+{
+    if constexpr (C) {
+        if constexpr (sizeof(T) == 8) {
+            double2 *q = reinterpret_cast<double2 *>(p);
+            q[0] = double2{v.er, v.ei};
+            q[1] = double2{v.hr, v.hi};
+        } else {
+            *p = float4{v.er, v.ei, v.hr, v.hi};
+        }
+    } else {
+        using S = typename Storage<T, C>::type;
+        *p = S{v.e, v.h};
+    }
+}
+
+// Neighbour coefficients of site i towards j: hopping t_ij and bond pairing
+// Delta_ij (both divided by a).  Uniform operators carry one real t.
+template <typename T, bool C> struct Link;
+template <typename T> struct Link<T, false> { T t, d; };
+template <typename T> struct Link<T, true> { T tr, ti, dr, di; };
+
+// (Ht a)(i) for one vector, given the pair at i, its four neighbours and the
+// four links:
+//   (Ht a)(i,e) = de a(i,e) + Delta_i a(i,h) + sum_j [-t_ij a(j,e) + Delta_ij a(j,h)]
+//   (Ht a)(i,h) = conj(Delta_i) a(i,e) + dh a(i,h) + sum_j [conj(Delta_ij) a(j,e) + conj(t_ij) a(j,h)]
+template <typename T, bool C>
+__device__ __forceinline__ Pair<T, C> apply_general(const OnSite<T> &o, const Pair<T, C> &c,
+                                                    const Pair<T, C> *nb, const Link<T, C> *lk)
+{
+    Pair<T, C> r;
+    if constexpr (C) {
+        // on-site
+        T er = o.de * c.er + (o.dr * c.hr - o.di * c.hi);
+        T ei = o.de * c.ei + (o.dr * c.hi + o.di * c.hr);
+        T hr = (o.dr * c.er + o.di * c.ei) + o.dh * c.hr;
+        T hi = (o.dr * c.ei - o.di * c.er) + o.dh * c.hi;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const Pair<T, C> &a = nb[q];
+            const Link<T, C> &l = lk[q];
+            // -t a_e + d a_h
+            er += -(l.tr * a.er - l.ti * a.ei) + (l.dr * a.hr - l.di * a.hi);
+            ei += -(l.tr * a.ei + l.ti * a.er) + (l.dr * a.hi + l.di * a.hr);
+            // conj(d) a_e + conj(t) a_h
+            hr += (l.dr * a.er + l.di * a.ei) + (l.tr * a.hr + l.ti * a.hi);
+            hi += (l.dr * a.ei - l.di * a.er) + (l.tr * a.hi - l.ti * a.hr);
+        }
+        r.er = er; r.ei = ei; r.hr = hr; r.hi = hi;
+    } else {
+        T e = o.de * c.e + o.dr * c.h;
+        T h = o.dr * c.e + o.dh * c.h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            e += -lk[q].t * nb[q].e + lk[q].d * nb[q].h;
+            h += lk[q].d * nb[q].e + lk[q].t * nb[q].h;
+        }
+        r.e = e; r.h = h;
+    }
+    return r;
+}
+
+// Uniform real hopping t (th = t/a) and no bond pairing.
+template <typename T, bool C>
+__device__ __forceinline__ Pair<T, C> apply_uniform(const OnSite<T> &o, T th, const Pair<T, C> &c,
+                                                    const Pair<T, C> &l, const Pair<T, C> &r,
+                                                    const Pair<T, C> &d, const Pair<T, C> &u)
+{
+    Pair<T, C> y;
+    if constexpr (C) {
+        y.er = o.de * c.er + (o.dr * c.hr - o.di * c.hi) - th * ((l.er + r.er) + (d.er + u.er));
+        y.ei = o.de * c.ei + (o.dr * c.hi + o.di * c.hr) - th * ((l.ei + r.ei) + (d.ei + u.ei));
+        y.hr = (o.dr * c.er + o.di * c.ei) + o.dh * c.hr + th * ((l.hr + r.hr) + (d.hr + u.hr));
+        y.hi = (o.dr * c.ei - o.di * c.er) + o.dh * c.hi + th * ((l.hi + r.hi) + (d.hi + u.hi));
+    } else {
+        y.e = o.de * c.e + o.dr * c.h - th * ((l.e + r.e) + (d.e + u.e));
+        y.h = o.dr * c.e + o.dh * c.h + th * ((l.h + r.h) + (d.h + u.h));
+    }
+    return y;
+}
+
+// out = 2 y - p   (or y on the first step)
+template <typename T, bool C>
+__device__ __forceinline__ Pair<T, C> cheb_combine(const Pair<T, C> &y, const Pair<T, C> &p, bool first)
+{
+    Pair<T, C> o;
+    if constexpr (C) {
+        o.er = first ? y.er : T(2) * y.er - p.er;
+        o.ei = first ? y.ei : T(2) * y.ei - p.ei;
+        o.hr = first ? y.hr : T(2) * y.hr - p.hr;
+        o.hi = first ? y.hi : T(2) * y.hi - p.hi;
+    } else {
+        o.e = first ? y.e : T(2) * y.e - p.e;
+        o.h = first ? y.h : T(2) * y.h - p.h;
+    }
+    return o;
+}
+
+// Links of site (x, y): +x, -x, +y, -y, built from the forward bond
+// coefficients of the site and of its backward neighbours (t_ji = conj(t_ij),
+// Delta_ji = Delta_ij).  A missing neighbour gets a zero link; its halo pair
+// is zero too.
+template <typename T, bool C>
+__device__ __forceinline__ void links_of(const void *bonds, int64_t s, int64_t s_left, int64_t s_down,
+                                         Link<T, C> *lk)
+{
+    if constexpr (C) {
+        const BondsC<T> *B = reinterpret_cast<const BondsC<T> *>(bonds);
+        const BondsC<T> o = B[s];
+        lk[0] = Link<T, C>{o.txr, o.txi, o.dxr, o.dxi};
+        lk[2] = Link<T, C>{o.tyr, o.tyi, o.dyr, o.dyi};
+        if (s_left >= 0) { const BondsC<T> q = B[s_left]; lk[1] = Link<T, C>{q.txr, -q.txi, q.dxr, q.dxi}; }
+        else lk[1] = Link<T, C>{T(0), T(0), T(0), T(0)};
+        if (s_down >= 0) { const BondsC<T> q = B[s_down]; lk[3] = Link<T, C>{q.tyr, -q.tyi, q.dyr, q.dyi}; }
+        else lk[3] = Link<T, C>{T(0), T(0), T(0), T(0)};
+    } else {
+        const BondsR<T> *B = reinterpret_cast<const BondsR<T> *>(bonds);
+        const BondsR<T> o = B[s];
+        lk[0] = Link<T, C>{o.tx, o.dx};
+        lk[2] = Link<T, C>{o.ty, o.dy};
+        if (s_left >= 0) { const BondsR<T> q = B[s_left]; lk[1] = Link<T, C>{q.tx, q.dx}; }
+        else lk[1] = Link<T, C>{T(0), T(0)};
+        if (s_down >= 0) { const BondsR<T> q = B[s_down]; lk[3] = Link<T, C>{q.ty, q.dy}; }
+        else lk[3] = Link<T, C>{T(0), T(0)};
+    }
+}
+
+// Maps a hardware workgroup id to a logical tile id so that consecutive
+// logical ids run on the same XCD (workgroups are dispatched round-robin over
+// the 8 XCDs): neighbouring strips then share their halo rows in one L2.
+__device__ __forceinline__ int xcd_remap(int id, int n)
+{
+    constexpr int kXcd = 8;
+    const int q = n / kXcd, r = n % kXcd;
+    const int xcd = id % kXcd, k = id / kXcd;
+    return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+}  // namespace cbdg

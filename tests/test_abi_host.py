@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/cbdg.h declares with the argument count the
+binding uses, and rejects bad arguments on the host before touching HIP."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cbdg.h")
+LIBSO = os.path.join(ROOT, "paper_1007_1609_amd", "libcbdg.so")
+
+
+def _ensure_lib():
+    if not os.path.exists(LIBSO):
+        subprocess.check_call(["python", os.path.join(ROOT, "paper_1007_1609_amd", "build.py")])
+    from paper_1007_1609_amd import _lib
+    return _lib
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    decls = {}
+    for m in re.finditer(r"(?:int|const char \*)\s*(cbdg_\w+)\s*\(([^)]*)\)\s*;", text):
+        args = m.group(2).strip()
+        n = 0 if args in ("", "void") else args.count(",") + 1
+        decls[m.group(1)] = n
+    return decls
+
+
+def test_header_declares_the_boundary_calls():
+    d = _declared()
+    for name in ("cbdg_build_bdg", "cbdg_op_update_delta", "cbdg_op_destroy", "cbdg_chebyshev_moments",
+                 "cbdg_gap_update", "cbdg_ldos", "cbdg_chebyshev_moments_backward",
+                 "cbdg_gap_update_backward", "cbdg_ldos_backward", "cbdg_last_error"):
+        assert name in d, name
+
+
+def test_library_exports_every_declared_symbol():
+    L = _ensure_lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", LIBSO], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (cbdg_\w+)", out))
+    for name in _declared():
+        assert name in exported, name
+    lib = L.load()
+    for name in _declared():
+        assert hasattr(lib, name)
+
+
+def test_binding_argument_counts_match_header():
+    L = _ensure_lib()
+    d = _declared()
+    for name, argtypes in L.SIGNATURES.items():
+        assert d[name] == len(argtypes), name
+    assert set(L.SIGNATURES) | {"cbdg_last_error"} == set(d)
+
+
+def test_host_validation_without_gpu():
+    L = _ensure_lib()
+    lib = L.load()
+    # build: NULL lattice, empty lattice, periodic too short, Peierls on a real operator
+    assert lib.cbdg_build_bdg(None, 1.0, 0.0, None, None, None, None, None, 0.0, 0.01, None, None, None) == L.CBDG_EINVAL
+    h = C.c_void_p()
+    lat = L.cbdg_lattice(0, 4, 0, 0, 0)
+    assert lib.cbdg_build_bdg(C.byref(lat), 1.0, 0.0, 8, 8, None, None, None, 0.0, 0.01, None, C.byref(h), None) == L.CBDG_EINVAL
+    assert "empty" in L.cbdg_last_error()
+    lat = L.cbdg_lattice(2, 4, 1, 0, 0)
+    assert lib.cbdg_build_bdg(C.byref(lat), 1.0, 0.0, 8, 8, None, None, None, 0.0, 0.01, None, C.byref(h), None) == L.CBDG_EINVAL
+    assert "periodic" in L.cbdg_last_error()
+    lat = L.cbdg_lattice(4, 4, 0, 0, L.CBDG_REAL)
+    assert lib.cbdg_build_bdg(C.byref(lat), 1.0, 0.0, 8, 8, None, 8, None, 0.0, 0.01, None, C.byref(h), None) == L.CBDG_EINVAL
+    assert "COMPLEX" in L.cbdg_last_error()
+    lat = L.cbdg_lattice(4, 4, 0, 0, L.CBDG_REAL)
+    assert lib.cbdg_build_bdg(C.byref(lat), 1.0, 0.0, 8, 8, None, None, None, 0.0, 1.5, None, C.byref(h), None) == L.CBDG_EINVAL
+    assert "eta" in L.cbdg_last_error()
+    # moments: NULL op, bad N
+    n = C.c_size_t()
+    assert lib.cbdg_moments_workspace_size(None, 64, 0, C.byref(n)) == L.CBDG_EINVAL
+    assert lib.cbdg_chebyshev_moments(None, None, 0, 8, 8, 0, None, 0, None, None, None) == L.CBDG_EINVAL
+    # gap update: bad N, bad kernel, finite temperature, E = 0 outside the interval
+    w = L.cbdg_weights(0, 0.0, 0.0, 0.0, 2.0, 0.0)
+    assert lib.cbdg_gap_update(None, 4, 0, 0, C.byref(w), 1.0, None, None, 1.0, None, 8, None) == L.CBDG_EINVAL
+    bad = L.cbdg_weights(7, 0.0, 0.0, 0.0, 2.0, 0.0)
+    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(bad), 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
+    hot = L.cbdg_weights(0, 0.0, 0.1, 0.0, 2.0, 0.0)
+    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(hot), 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EUNSUPPORTED
+    off = L.cbdg_weights(0, 0.0, 0.0, 0.0, 2.0, 5.0)
+    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(off), 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
+    lor = L.cbdg_weights(1, 0.0, 0.0, 0.0, 2.0, 0.0)
+    assert lib.cbdg_ldos(8, 4, 8, C.byref(lor), 8, 4, 8, None) == L.CBDG_EINVAL
+    assert lib.cbdg_check_moments(None, None, 4, 8, 0, 1e-9, None, None) == L.CBDG_EINVAL
+    assert lib.cbdg_op_destroy(None) == L.CBDG_OK
+
+
+def test_python_errors_carry_message():
+    L = _ensure_lib()
+    with pytest.raises(L.CbdgError) as e:
+        L.cbdg_moments_workspace_size(None, 0, 0, None)
+    assert e.value.code == L.CBDG_EINVAL and "moments_workspace_size" in str(e.value)

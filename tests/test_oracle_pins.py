@@ -230,6 +230,24 @@ def test_sign_coefficients_by_quadrature(x_c):
         assert abs(c[n] - ref) < 1e-11, n
 
 
+@pytest.mark.parametrize("a,b,E_c", [(3.0, 0.0, 0.0), (3.0, 0.4, 0.0), (2.5, -0.3, 1.1), (4.0, 0.2, 9.0)])
+def test_general_sign_weight_by_quadrature(a, b, E_c):
+    """sign(E) on |E| < E_c with E = a x + b, integrated against T_n numerically."""
+    N = 33
+    c = oracle.sign_weight_coefficients(N, a, b, E_c)
+    for n in range(N):
+        def f(th):
+            E = a * np.cos(th) + b
+            inside = (abs(E) < E_c) if E_c > 0 else True
+            return np.sign(E) * inside * np.cos(n * th)
+        pts = [np.arccos(np.clip(v, -1, 1)) for v in (-b / a, (E_c - b) / a, (-E_c - b) / a)]
+        val, _ = integrate.quad(f, 0, np.pi, points=sorted(set(pts)), limit=400, epsabs=1e-13)
+        assert abs(c[n] - (1 if n == 0 else 2) / np.pi * val) < 1e-11, n
+    if b == 0.0:
+        x_c = min(E_c / a, 1.0) if E_c > 0 else 1.0
+        assert np.max(np.abs(c - oracle.sign_coefficients(N, x_c))) < 1e-14
+
+
 def test_sign_series_converges_to_sign():
     c = oracle.sign_coefficients(4001)
     x = np.array([-0.9, -0.5, -0.2, 0.3, 0.8])

@@ -1,0 +1,210 @@
+"""GPU moments vs the CPU oracle, element by element (FP64: |diff| <= 1e-10,
+moments are bounded by mu_0 = 1), across lattices that span several strips,
+row segments and vector chunks with ragged tails, the operator variants, the
+edge cases, and the full 256x256 lattice at the benchmark's launch shape on
+sampled start sites."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.gpu_common import DEV, TOL_MOMENT, gpu_moments, maxdiff
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(w, N=None, tile=None, sites=None):
+    op, g_ee, g_he = gpu_moments(w, sites=sites, N=N, tile=tile)
+    a, b = op.bounds.a, op.bounds.b
+    o_ee, o_he = oracle.workload_moments(w, a, b, sites=sites, N=N)
+    op.close()
+    assert maxdiff(g_ee, o_ee) <= TOL_MOMENT
+    assert maxdiff(g_he, o_he) <= TOL_MOMENT
+    return g_ee, g_he
+
+
+def test_config0_all_sites():
+    w = W.config0()
+    op, g_ee, g_he = gpu_moments(w)
+    _, _, a, b = oracle.workload_bounds(w)
+    assert abs(op.bounds.a - a) <= 1e-14 * a and op.bounds.b == 0.0
+    o_ee, o_he = oracle.workload_moments(w, a, b)
+    op.close()
+    print("config0 max |diff| ee %.2e he %.2e" % (maxdiff(g_ee, o_ee), maxdiff(g_he, o_he)))
+    assert maxdiff(g_ee, o_ee) <= TOL_MOMENT
+    assert maxdiff(g_he, o_he) <= TOL_MOMENT
+
+
+@pytest.mark.parametrize("Lx,Ly,tile,n_sites", [
+    (13, 37, 100, 160),    # ragged strips (13 = 8 + 5), two row segments, ragged tiles
+    (40, 70, 300, 300),    # 5 strips, 3 segments, a tile wider than one 256-lane chunk
+    (9, 5, 7, 45),         # many tiny tiles
+])
+def test_ragged_shapes(Lx, Ly, tile, n_sites):
+    w = W.small_random(Lx, Ly, N=96, seed=Lx * Ly, n_sites=n_sites)
+    _check(w, tile=tile)
+
+
+@pytest.mark.parametrize("case", [
+    dict(bc_x=W.PERIODIC, bc_y=W.PERIODIC),
+    dict(bc_x=W.PERIODIC),
+    dict(bc_y=W.PERIODIC),
+    dict(bond=True),
+    dict(bond=True, bc_x=W.PERIODIC, bc_y=W.PERIODIC),
+    dict(complex_=True),
+    dict(complex_=True, flux=0.3),
+    dict(complex_=True, bond=True, flux=0.2, bc_x=W.PERIODIC),
+    dict(complex_=True, bond=True, flux=0.25, bc_x=W.PERIODIC, bc_y=W.PERIODIC),
+])
+def test_operator_variants(case):
+    w = W.small_random(11, 35, N=80, seed=7, **case)
+    _check(w, tile=128)
+
+
+def test_fixed_bounds_with_shift():
+    w = W.small_random(10, 9, N=64, seed=3)
+    op, g_ee, g_he = gpu_moments(w, fixed=(6.25, 0.31))
+    o_ee, o_he = oracle.workload_moments(w, 6.25, 0.31)
+    op.close()
+    assert maxdiff(g_ee, o_ee) <= TOL_MOMENT and maxdiff(g_he, o_he) <= TOL_MOMENT
+
+
+@pytest.mark.parametrize("Lx,Ly", [(1, 1), (1, 17), (23, 1), (2, 2)])
+def test_degenerate_lattices(Lx, Ly):
+    w = W.small_random(Lx, Ly, N=40, seed=5)
+    _check(w)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_few_moments(N):
+    w = W.small_random(6, 6, N=N, seed=1)
+    _check(w, N=N)
+
+
+def test_duplicate_and_unsorted_sites():
+    w = W.small_random(12, 10, N=50, seed=2)
+    sites = np.array([5, 5, 119, 0, 64, 5, 33], dtype=np.int32)
+    _check(w, sites=sites, tile=3)
+
+
+def test_empty_start_set():
+    import paper_1007_1609_amd as P
+    w = W.small_random(6, 6, N=10, seed=1)
+    op = P.Operator.from_workload(w, DEV)
+    mu_ee, mu_he = P.chebyshev_moments(op, torch.zeros(0, dtype=torch.int32, device=DEV), 10, 64)
+    assert mu_ee.shape == (0, 10)
+    op.close()
+
+
+def test_out_of_range_site_gives_nan_row_and_flag():
+    import paper_1007_1609_amd as P
+    w = W.small_random(6, 6, N=12, seed=1)
+    op, g_ee, g_he = gpu_moments(w, sites=np.array([3, -1, 36, 7], np.int32), tile=4)
+    assert np.all(np.isnan(g_ee[1])) and np.all(np.isnan(g_ee[2])) and np.all(np.isfinite(g_ee[[0, 3]]))
+    o_ee, _ = oracle.workload_moments(w, op.bounds.a, op.bounds.b, sites=[3, 7], N=12)
+    assert maxdiff(g_ee[[0, 3]], o_ee) <= TOL_MOMENT
+    mu_ee = torch.as_tensor(g_ee, device=DEV)
+    mu_he = torch.as_tensor(g_he, device=DEV)
+    assert not P.check_moments(mu_ee, mu_he)
+    assert P.check_moments(mu_ee[[0, 3]].contiguous(), mu_he[[0, 3]].contiguous())
+    op.close()
+
+
+def test_bounds_violation_is_detected():
+    """A rescaling that leaves part of the spectrum outside [-1, 1] makes the
+    recursion grow; the moment check reports it."""
+    import paper_1007_1609_amd as P
+    w = W.small_random(8, 8, N=400, seed=4)
+    op, g_ee, g_he = gpu_moments(w, fixed=(1.2, 0.0))
+    ok = P.check_moments(torch.as_tensor(g_ee, device=DEV), torch.as_tensor(g_he, device=DEV))
+    op.close()
+    assert not ok
+
+
+def test_deterministic_bits():
+    w = W.small_random(20, 20, N=64, seed=9)
+    _, a1, b1 = gpu_moments(w, tile=128)
+    _, a2, b2 = gpu_moments(w, tile=128)
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+def test_tile_size_does_not_change_results():
+    w = W.small_random(17, 19, N=64, seed=12)
+    _, a1, b1 = gpu_moments(w, tile=64)
+    _, a2, b2 = gpu_moments(w, tile=1000)
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+def test_full_size_lattice_sampled_sites():
+    """256x256, one tile of 1024 start vectors, N = 1024 (the benchmark's
+    launch shape); eight sampled start vectors checked against the oracle and
+    every row against mu_0 = 1, |mu| <= 1 and particle-hole symmetry."""
+    w = W.config1()
+    sites = np.arange(1024, dtype=np.int32) * 61 % w.L2
+    op, g_ee, g_he = gpu_moments(w, sites=sites, tile=1024)
+    a, b = op.bounds.a, op.bounds.b
+    op.close()
+    pick = [0, 1, 100, 511, 512, 700, 1022, 1023]
+    o_ee, o_he = oracle.workload_moments(w, a, b, sites=sites[pick])
+    print("256x256 sampled max |diff| ee %.2e he %.2e" % (maxdiff(g_ee[pick], o_ee), maxdiff(g_he[pick], o_he)))
+    assert maxdiff(g_ee[pick], o_ee) <= TOL_MOMENT
+    assert maxdiff(g_he[pick], o_he) <= TOL_MOMENT
+    assert np.all(g_ee[:, 0] == 1.0) and np.all(g_he[:, 0] == 0.0)
+    assert np.max(np.abs(g_ee)) <= 1.0 + 1e-12 and np.max(np.abs(g_he)) <= 1.0 + 1e-12
+    assert np.max(np.abs(g_he[:, 0::2])) < 1e-12
+
+
+def test_bloch_closed_form_on_gpu_256():
+    """Periodic 256x256 lattice with uniform Delta: every site has the Bloch
+    closed-form moments, which need no oracle run at this size."""
+    L, N, t, mu, dl = 256, 256, 1.0, -0.3, 0.25
+    w = W.Workload("bloch256", L, L, W.PERIODIC, W.PERIODIC, t, mu, 0.0, np.zeros(L * L),
+                   np.full(L * L, dl), None, None, N, np.arange(0, L * L, 997, dtype=np.int32), 128)
+    a = 6.1
+    _, g_ee, g_he = gpu_moments(w, fixed=(a, 0.0))
+    k = 2 * np.pi * np.arange(L) / L
+    xi = (-2 * t * (np.cos(k)[:, None] + np.cos(k)[None, :]) - mu).ravel()
+    E = np.sqrt(xi ** 2 + dl ** 2)
+    n = np.arange(N)
+    Tp, Tm = np.cos(np.outer(n, np.arccos(E / a))), np.cos(np.outer(n, np.arccos(-E / a)))
+    ref_ee = (Tp @ ((1 + xi / E) / 2) + Tm @ ((1 - xi / E) / 2)) / L ** 2
+    ref_he = ((Tp - Tm) @ (dl / (2 * E))) / L ** 2
+    assert maxdiff(g_ee, ref_ee[None, :]) < 1e-10
+    assert maxdiff(g_he, ref_he[None, :]) < 1e-10
+
+
+def test_complex_full_size_lattice_sampled_sites():
+    """512x512 with Peierls flux 1/256 and the vortex d-wave bond profile,
+    complex128, N = 256, two sampled start vectors against the oracle."""
+    w = W.config3(N=256)
+    sites = w.start_sites[[0, 2100]]
+    op, g_ee, g_he = gpu_moments(w, sites=sites, tile=64)
+    a, b = op.bounds.a, op.bounds.b
+    assert abs(a - 2 * 4.8 / 1.99) < 1e-9
+    op.close()
+    o_ee, o_he = oracle.workload_moments(w, a, b, sites=sites, N=256)
+    assert maxdiff(g_ee, o_ee) <= TOL_MOMENT and maxdiff(g_he, o_he) <= TOL_MOMENT
+
+
+def test_fp32_recursion_error_is_small():
+    """FP32 vectors and coefficients, moments widened to FP64: report the
+    error against the FP64 oracle (bar 2e-5 absolute at N = 512)."""
+    w = W.small_random(48, 48, N=512, seed=14, n_sites=64)
+    op, g_ee, g_he = gpu_moments(w, tile=64, precision=1)
+    o_ee, o_he = oracle.workload_moments(w, op.bounds.a, op.bounds.b)
+    op.close()
+    e = max(maxdiff(g_ee, o_ee), maxdiff(g_he, o_he))
+    print("fp32 recursion, 48x48 N=512: max |mu_gpu32 - mu_oracle64| = %.2e" % e)
+    assert e < 2e-5
+    assert np.all(g_ee[:, 0] == 1.0)
+
+
+def test_fp32_complex_error_is_small():
+    w = W.small_random(24, 20, N=256, seed=15, complex_=True, bond=True, flux=0.1, n_sites=40)
+    op, g_ee, g_he = gpu_moments(w, tile=64, precision=1)
+    o_ee, o_he = oracle.workload_moments(w, op.bounds.a, op.bounds.b)
+    op.close()
+    e = max(maxdiff(g_ee, o_ee), maxdiff(g_he, o_he))
+    print("complex64 recursion, 24x20 N=256: max error %.2e" % e)
+    assert e < 2e-5
