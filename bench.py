@@ -57,19 +57,52 @@ def stored_traffic(kind: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, a, b, n_sites: int, threads: int):
+def cpu_baseline(w, a, b, n_sites: int, threads: int, target_s: float = 15.0):
+    """Oracle moments/s on a bounded sample of start sites: a pilot of one
+    site per thread sizes the timed sample to about target_s seconds."""
     import numpy as np
 
     import oracle
-    sites = np.linspace(0, w.L2 - 1, n_sites).astype(np.int32)
     H = oracle.workload_csr(w, a, b)
+    if n_sites <= 0:
+        pilot = np.linspace(0, w.L2 - 1, threads).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.moments(H, pilot, w.N, n_threads=threads)
+        per_round = time.perf_counter() - t0
+        n_sites = int(max(1, min(64, round(target_s / max(per_round, 1e-3))))) * threads
+    sites = np.linspace(0, w.L2 - 1, n_sites).astype(np.int32)
     t0 = time.perf_counter()
     oracle.moments(H, sites, w.N, n_threads=threads)
     dt = time.perf_counter() - t0
     return {"value": n_sites * w.N / dt, "unit": "moments/s", "cores": oracle.max_threads(),
             "kind": "oracle",
-            "sample": "%d start sites of the same 256x256 lattice, N=%d, FP64 CSR recursion, "
-                      "%.1f s" % (n_sites, w.N, dt)}
+            "sample": "%d start sites spread over the same 256x256 lattice, N=%d, FP64 CSR "
+                      "recursion, %.1f s" % (n_sites, w.N, dt)}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def copy_probe(dev, nbytes=2 << 30, reps=8):
+    """Plain device-to-device copy of a known size: the reference for HBM
+    counter scaling and the achievable copy bandwidth."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"probe": "device copy", "bytes_read_per_launch": nbytes,
+                      "bytes_written_per_launch": nbytes, "launches": reps + 1,
+                      "avg_ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
 
 
 def main():
@@ -79,8 +112,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--tiles", type=int, default=0, help="limit the number of tiles (0: whole lattice)")
-    ap.add_argument("--cpu-sites", type=int, default=0, help="oracle sample size (0: 2 per thread)")
+    ap.add_argument("--cpu-sites", type=int, default=0, help="oracle sample size (0: sized to about 15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain 2 GiB device copy instead (HBM calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
@@ -95,6 +130,9 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        copy_probe(dev)
+        return
     N = 1024 if args.precision == "fp64" else 2048
     w = W.config1(N=N) if args.precision == "fp64" else W.config2()
     prec = P.CBDG_FP64 if args.precision == "fp64" else P.CBDG_FP32_ACC64
@@ -111,8 +149,9 @@ def main():
     ws = P.workspace(P.moments_workspace_bytes(op, tile, prec), dev)
     mu_ee = torch.empty((n_sites, N), dtype=torch.float64, device=dev)
     mu_he = torch.empty((n_sites, N), dtype=torch.float64, device=dev)
-    delta = torch.as_tensor(w.delta[:n_sites], device=dev).clone()
+    full = n_sites == w.L2
     delta_full = torch.as_tensor(w.delta, device=dev).clone()
+    delta = delta_full if full else torch.as_tensor(w.delta[:n_sites], device=dev).clone()
     nxt = torch.empty_like(delta)
     resid = torch.empty(1, dtype=torch.float64, device=dev)
     energies = torch.linspace(-1.0, 1.0, 64, dtype=torch.float64, device=dev)
@@ -122,7 +161,7 @@ def main():
 
     def step(record):
         nonlocal delta, nxt
-        op.update_delta(delta_full)
+        op.update_delta(delta if full else delta_full)
         for k in range(n_tiles):
             lo, hi = k * tile, min(n_sites, (k + 1) * tile)
             if record:
@@ -136,17 +175,21 @@ def main():
         P.gap_update(mu_he, wts, w.U, delta, 1.0, delta_out=nxt, resid=resid)
         P.ldos(mu_ee, wts, energies, out=ldos)
         delta, nxt = nxt, delta
-        delta_full[:n_sites].copy_(delta)
+        if not full:  # reduced runs only: the rest of the lattice keeps its Delta
+            delta_full[:n_sites].copy_(delta)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step(False)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("warmup step %d done" % (i + 1))
     t_start = torch.cuda.Event(enable_timing=True)
     t_stop = torch.cuda.Event(enable_timing=True)
     t_start.record(stream)
     wall0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step(True)
+        if args.steps > 1:
+            log("step %d enqueued" % (i + 1))
     t_stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -208,10 +251,10 @@ def main():
         "moments_bounded": bool(ok),
         "wall_s_timed": wall,
     }
+    log("timed steps done: %.1f ms/step, %.3g moments/s, %.0f GB/s" % (ms_per_step, value, achieved))
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
-        n_cpu = args.cpu_sites or max(8, min(64, 2 * threads))
-        line["cpu_baseline"] = cpu_baseline(w, a, b, n_cpu, threads)
+        line["cpu_baseline"] = cpu_baseline(w, a, b, args.cpu_sites, threads)
     else:
         line["cpu_baseline"] = None
     op.close()
