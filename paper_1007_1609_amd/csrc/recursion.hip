@@ -11,8 +11,8 @@
 //   - lanes map to vectors, so every neighbour read of a wavefront is one
 //     contiguous run, and the per-site coefficients are wave-uniform scalar
 //     loads reused by all 64 lanes;
-//   - each lane owns a strip of W sites along x and marches up a segment of
-//     rows in y, keeping rows y-1, y, y+1 of a_{n-1} in registers, so a_{n-1}
+//   - each lane owns a strip of W sites along x (W divides Lx, so every
+//     strip is full) and marches up a segment of rows in y, keeping rows y-1, y, y+1 of a_{n-1} in registers, so a_{n-1}
 //     is read about once (plus the strip's x halo and the segment's y halo,
 //     which neighbouring strips on the same XCD fetch at nearly the same time);
 //   - a_{n-2} is read and a_n written by the same lane at the same address.
@@ -23,6 +23,26 @@
 #include <type_traits>
 
 namespace cbdg {
+
+// Load/store flavours of the three streams (1 = nontemporal) and extra
+// padding of the lane stride.  a_{n-2} and a_n are touched once per step and
+// stream past the caches; a_{n-1} is read through L2, where neighbouring
+// strips and row segments pick up each other's halo columns and rows.
+// Measured on MI355X (256x256, 1024 vectors, FP64): nontemporal a_{n-2}/a_n
+// cut the step from 719 to 665 us at W = 4; a nontemporal a_{n-1} or a
+// padded lane stride did not help.
+#ifndef CBDG_NT_A1
+#define CBDG_NT_A1 0
+#endif
+#ifndef CBDG_NT_A2
+#define CBDG_NT_A2 1
+#endif
+#ifndef CBDG_NT_OUT
+#define CBDG_NT_OUT 1
+#endif
+#ifndef CBDG_LANE_PAD
+#define CBDG_LANE_PAD 0
+#endif
 
 struct StepArgs {
     const void *prev1;   // a_{n-1}
@@ -42,8 +62,10 @@ struct StepArgs {
     int n_strips, n_segs, nblocks;
 };
 
-template <typename T, bool C, bool GEN, int W, int YS>
-__global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs A)
+template <typename T, bool C, bool GEN, bool FIRST, int W, int YS>
+__global__ __launch_bounds__(kBlock) void k_cheb_step(
+    StepArgs A, const typename Storage<T, C>::type *__restrict__ a1,
+    const OnSite<T> *__restrict__ ons, const void *__restrict__ bonds)
 {
     using P = Pair<T, C>;
     using S = typename Storage<T, C>::type;
@@ -52,85 +74,131 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs A)
     const int rest = lb / A.n_strips;
     const int seg = rest % A.n_segs;
     const int chunk = rest / A.n_segs;
-    const int b = chunk * kBlock + threadIdx.x;
-    if (b >= A.Bt) return;
+    const uint32_t b = chunk * kBlock + threadIdx.x;
+    if (b >= (uint32_t)A.Bt) return;
 
     const int Lx = A.Lx, Ly = A.Ly;
     const int x0 = strip * W;
     const int y0 = seg * YS;
     const int y1 = min(y0 + YS, Ly);
     const int64_t Bp = A.Bp;
-    const S *a1 = reinterpret_cast<const S *>(A.prev1);
+    // a1 (a_{n-1}) is never written by this launch -- out aliases a_{n-2}
+    // only -- and the coefficients are read-only, which lets the wave-uniform
+    // coefficient reads become scalar loads.  Addresses are a wave-uniform
+    // base (site * Bp) plus the lane's vector index.
     const S *a2 = reinterpret_cast<const S *>(A.prev2);
     S *ao = reinterpret_cast<S *>(A.out);
-    const OnSite<T> *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
     const int my_site = A.sites[b];
     const T th = T(A.th);
-    const bool first = A.first != 0;
 
-    // column k of the register window holds x = x0 - 1 + k
-    auto col_of = [&](int k) -> int {
-        int x = x0 - 1 + k;
-        if (x >= 0 && x < Lx) return x;
-        if (A.bcx && (x == -1 || x == Lx)) return x < 0 ? x + Lx : x - Lx;
-        return -1;
-    };
-    auto row_of = [&](int y) -> int {
-        if (y >= 0 && y < Ly) return y;
-        if (A.bcy && (y == -1 || y == Ly)) return y < 0 ? y + Ly : y - Ly;
-        return -1;
-    };
-    auto load_row = [&](P *row, int y, int kbeg, int kend) {
-        const int yy = row_of(y);
+    // Column k of the register window holds x = x0 - 1 + k.  Every column gets
+    // an in-bounds column index and a mask; a column outside an open lattice is
+    // loaded from a valid column and its bits cleared, so each row is one
+    // branch-free clause of loads.
+    int cx[W + 2];
+    uint32_t cm[W + 2];
+#pragma unroll
+    for (int k = 0; k < W + 2; ++k) {
+        const int x = x0 - 1 + k;
+        bool ok;
+        if (x < 0) { ok = A.bcx != 0; cx[k] = A.bcx ? x + Lx : 0; }
+        else if (x >= Lx) { ok = A.bcx && x == Lx; cx[k] = ok ? 0 : Lx - 1; }
+        else { ok = true; cx[k] = x; }
+        cm[k] = ok ? ~0u : 0u;
+    }
+    // Raw loads of row y; returns the row's mask (masks are applied by
+    // apply_mask once the loads have had time to land).
+    auto load_row = [&](P *row, int y) -> uint32_t {
+        bool ok = true;
+        int yy = y;
+        if (y < 0) { ok = A.bcy != 0; yy = A.bcy ? y + Ly : 0; }
+        else if (y >= Ly) { ok = A.bcy != 0; yy = A.bcy ? y - Ly : Ly - 1; }
+        const int64_t rbase = (int64_t)yy * Lx;
 #pragma unroll
         for (int k = 0; k < W + 2; ++k) {
-            if (k < kbeg || k >= kend) continue;
-            const int xx = col_of(k);
-            if (yy >= 0 && xx >= 0) row[k] = ld<T, C>(a1 + ((int64_t)yy * Lx + xx) * Bp + b);
-            else row[k] = zero_pair<T, C>();
+            const S *q = a1 + (rbase + cx[k]) * Bp + b;
+            row[k] = CBDG_NT_A1 ? ld_nt<T, C>(q) : ld<T, C>(q);
+        }
+        return ok ? ~0u : 0u;
+    };
+    auto apply_mask = [&](P *row, uint32_t rm) {
+#pragma unroll
+        for (int k = 0; k < W + 2; ++k) row[k] = masked<T, C>(row[k], rm & cm[k]);
+    };
+    auto load_prev2 = [&](P *row, int y) {
+        const int64_t rbase = (int64_t)y * Lx;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const S *q = a2 + (rbase + x0 + k) * Bp + b;
+            row[k] = CBDG_NT_A2 ? ld_nt<T, C>(q) : ld<T, C>(q);
         }
     };
 
-    P up[W + 2], cur[W + 2], dn[W + 2];
-    load_row(up, y0 - 1, 1, W + 1);
-    load_row(cur, y0, 0, W + 2);
+    // Rows y-1, y, y+1 of a_{n-1} and row y of a_{n-2} are in registers while
+    // row y is computed; the loads for row y+1 are issued first so their
+    // latency overlaps the arithmetic and the stores of row y.  The lane's own
+    // moment is captured with a select and stored once at the end, so the
+    // loop body issues a fixed number of memory operations.
+    P up[W + 2], cur[W + 2], dn[W + 2], nx[W + 2], pc[W], pn[W];
+    P mval = zero_pair<T, C>();
+    bool found = false;
+    apply_mask(up, load_row(up, y0 - 1));
+    apply_mask(cur, load_row(cur, y0));
+    apply_mask(dn, load_row(dn, y0 + 1));
+    if constexpr (!FIRST) load_prev2(pc, y0);
 
-    for (int y = y0; y < y1; ++y) {
-        load_row(dn, y + 1, 0, W + 2);
+    auto compute_row = [&](int y) {
+        const int64_t srow = (int64_t)y * Lx;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const int x = x0 + k;
-            if (x >= Lx) continue;
-            const int64_t s = (int64_t)y * Lx + x;
+            const int64_t s = srow + x;
             const OnSite<T> o = ons[s];
             P yv;
             if constexpr (GEN) {
                 const int64_t sl = x > 0 ? s - 1 : (A.bcx ? s + Lx - 1 : -1);
                 const int64_t sd = y > 0 ? s - Lx : (A.bcy ? s + (int64_t)(Ly - 1) * Lx : -1);
                 Link<T, C> lk[4];
-                links_of<T, C>(A.bonds, s, sl, sd, lk);
+                links_of<T, C>(bonds, s, sl, sd, lk);
                 P nb[4] = {cur[k + 2], cur[k], dn[k + 1], up[k + 1]};
                 yv = apply_general<T, C>(o, cur[k + 1], nb, lk);
             } else {
                 yv = apply_uniform<T, C>(o, th, cur[k + 1], cur[k], cur[k + 2], up[k + 1], dn[k + 1]);
             }
-            P pv = first ? zero_pair<T, C>() : ld<T, C>(a2 + s * Bp + b);
-            P ov = cheb_combine<T, C>(yv, pv, first);
-            st<T, C>(ao + s * Bp + b, ov);
-            if (s == my_site) {
-                const int64_t m = (int64_t)b * A.N + A.n;
-                if constexpr (C) {
-                    A.mu_ee[m] = (double)ov.er;
-                    A.mu_he[2 * m] = (double)ov.hr;
-                    A.mu_he[2 * m + 1] = (double)ov.hi;
-                } else {
-                    A.mu_ee[m] = (double)ov.e;
-                    A.mu_he[m] = (double)ov.h;
-                }
-            }
+            P ov;
+            if constexpr (FIRST) ov = yv;
+            else ov = cheb_combine<T, C>(yv, pc[k], false);
+            if constexpr (CBDG_NT_OUT) st_nt<T, C>(ao + s * Bp + b, ov);
+            else st<T, C>(ao + s * Bp + b, ov);
+            const bool hit = s == my_site;
+            found = found || hit;
+            mval = hit ? ov : mval;
         }
+    };
+    for (int y = y0; y < y1 - 1; ++y) {
+        const uint32_t nm = load_row(nx, y + 2);
+        if constexpr (!FIRST) load_prev2(pn, y + 1);
+        compute_row(y);
+        apply_mask(nx, nm);
 #pragma unroll
-        for (int k = 0; k < W + 2; ++k) { up[k] = cur[k]; cur[k] = dn[k]; }
+        for (int k = 0; k < W + 2; ++k) { up[k] = cur[k]; cur[k] = dn[k]; dn[k] = nx[k]; }
+        if constexpr (!FIRST) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) pc[k] = pn[k];
+        }
+    }
+    compute_row(y1 - 1);
+
+    if (found) {
+        const int64_t m = (int64_t)b * A.N + A.n;
+        if constexpr (C) {
+            A.mu_ee[m] = (double)mval.er;
+            A.mu_he[2 * m] = (double)mval.hr;
+            A.mu_he[2 * m + 1] = (double)mval.hi;
+        } else {
+            A.mu_ee[m] = (double)mval.e;
+            A.mu_he[m] = (double)mval.h;
+        }
     }
 }
 
@@ -170,26 +238,75 @@ __global__ void k_seed(typename Storage<T, C>::type *a0, int64_t Bp, int Bt, int
     else mu_he[m] = 0.0;
 }
 
+// Strip width W and row-segment length YS per vector type (register window
+// of 6W + 8 Nambu pairs per lane).  Chosen by measurement on MI355X: wider
+// strips issue fewer halo requests per output and win even at 2 waves/SIMD
+// (FP64: W = 2/4/8 -> 727/665/623 us per 1024-vector step at 256x256).
+#ifndef CBDG_W_D
+#define CBDG_W_D 8
+#endif
+#ifndef CBDG_YS_D
+#define CBDG_YS_D 64
+#endif
+#ifndef CBDG_W_F
+#define CBDG_W_F 8
+#endif
+#ifndef CBDG_YS_F
+#define CBDG_YS_F 32
+#endif
+#ifndef CBDG_W_Z
+#define CBDG_W_Z 4
+#endif
+#ifndef CBDG_YS_Z
+#define CBDG_YS_Z 32
+#endif
+#ifndef CBDG_W_C
+#define CBDG_W_C 4
+#endif
+#ifndef CBDG_YS_C
+#define CBDG_YS_C 32
+#endif
 template <typename T, bool C> struct StepShape;
-template <> struct StepShape<double, false> { static constexpr int W = 8, YS = 32; };
-template <> struct StepShape<float, false> { static constexpr int W = 8, YS = 32; };
-template <> struct StepShape<double, true> { static constexpr int W = 4, YS = 32; };
-template <> struct StepShape<float, true> { static constexpr int W = 8, YS = 32; };
+template <> struct StepShape<double, false> { static constexpr int W = CBDG_W_D, YS = CBDG_YS_D; };
+template <> struct StepShape<float, false> { static constexpr int W = CBDG_W_F, YS = CBDG_YS_F; };
+template <> struct StepShape<double, true> { static constexpr int W = CBDG_W_Z, YS = CBDG_YS_Z; };
+template <> struct StepShape<float, true> { static constexpr int W = CBDG_W_C, YS = CBDG_YS_C; };
 
-template <typename T, bool C, bool GEN>
-static int launch_step(StepArgs A, hipStream_t st)
+template <typename T, bool C, bool GEN, int W>
+static int launch_step_w(StepArgs A, hipStream_t st)
 {
-    constexpr int W = StepShape<T, C>::W, YS = StepShape<T, C>::YS;
-    A.n_strips = (int)ceil_div(A.Lx, W);
+    constexpr int YS = StepShape<T, C>::YS;
+    A.n_strips = A.Lx / W;
     A.n_segs = (int)ceil_div(A.Ly, YS);
     const int n_chunks = (int)ceil_div(A.Bt, kBlock);
     const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
     A.nblocks = (int)nb;
-    hipLaunchKernelGGL((k_cheb_step<T, C, GEN, W, YS>), dim3(A.nblocks), dim3(kBlock), 0, st, A);
+    const auto *a1 = reinterpret_cast<const typename Storage<T, C>::type *>(A.prev1);
+    const auto *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
+    if (A.first)
+        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, YS>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
+                           a1, ons, A.bonds);
+    else
+        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, YS>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
+                           a1, ons, A.bonds);
     CBDG_CHECK_LAUNCH("k_cheb_step");
     return CBDG_OK;
 }
+
+// The strip width is the largest of {W, 2, 1} that divides Lx.
+template <typename T, bool C, bool GEN>
+static int launch_step(StepArgs A, hipStream_t st)
+{
+    constexpr int W = StepShape<T, C>::W;
+    if (A.Lx % W == 0) return launch_step_w<T, C, GEN, W>(A, st);
+    if (W > 2 && A.Lx % 2 == 0) return launch_step_w<T, C, GEN, (W > 2 ? 2 : 1)>(A, st);
+    return launch_step_w<T, C, GEN, 1>(A, st);
+}
+
+// Lane stride of a tile of B vectors: B rounded up to the wavefront, plus
+// the stride padding.
+static int64_t lane_stride(int64_t B) { return round_up(B, kWave) + CBDG_LANE_PAD; }
 
 template <typename T, bool C>
 static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start, int N, int tile,
@@ -197,7 +314,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
 {
     using S = typename Storage<T, C>::type;
     const int64_t L2 = op->L2;
-    const int64_t Bp_max = round_up(tile, kWave);
+    const int64_t Bp_max = lane_stride(tile);
     S *bufA = reinterpret_cast<S *>(ws);
     S *bufB = bufA + L2 * Bp_max;
     const void *onsite = std::is_same<T, double>::value ? (const void *)op->onsite64 : (const void *)op->onsite32;
@@ -205,7 +322,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
     const int he_mult = C ? 2 : 1;
     for (int64_t t0 = 0; t0 < n_start; t0 += tile) {
         const int Bt = (int)std::min<int64_t>(tile, n_start - t0);
-        const int64_t Bp = round_up(Bt, kWave);
+        const int64_t Bp = lane_stride(Bt);
         double *mee = mu_ee + t0 * N;
         double *mhe = mu_he + t0 * N * he_mult;
         const int32_t *ts = sites + t0;
@@ -272,7 +389,7 @@ extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int3
     if (tile < 1) return fail(CBDG_EINVAL, "moments_workspace_size: tile must be >= 1");
     if (precision != CBDG_FP64 && precision != CBDG_FP32_ACC64)
         return fail(CBDG_EINVAL, "moments_workspace_size: unknown precision %d", precision);
-    *bytes = 2 * (size_t)op->L2 * (size_t)round_up(tile, kWave) * pair_bytes(op->scalar, precision);
+    *bytes = 2 * (size_t)op->L2 * (size_t)lane_stride(tile) * pair_bytes(op->scalar, precision);
     return CBDG_OK;
 }
 

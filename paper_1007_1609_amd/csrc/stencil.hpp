@@ -26,6 +26,19 @@ template <typename T, bool C> __device__ __forceinline__ Pair<T, C> zero_pair()
     return p;
 }
 
+// v with every bit cleared when mask == 0 (mask is 0 or ~0u): zeroes halo
+// values without a branch and independently of their content.
+template <typename T, bool C>
+__device__ __forceinline__ Pair<T, C> masked(const Pair<T, C> &v, uint32_t mask)
+{
+    constexpr int n = sizeof(Pair<T, C>) / 4;
+    struct Words { uint32_t w[n]; };
+    Words u = __builtin_bit_cast(Words, v);
+#pragma unroll
+    for (int i = 0; i < n; ++i) u.w[i] &= mask;
+    return __builtin_bit_cast(Pair<T, C>, u);
+}
+
 template <typename T, bool C>
 __device__ __forceinline__ Pair<T, C> ld(const typename Storage<T, C>::type *p)
 {
@@ -44,6 +57,46 @@ __device__ __forceinline__ Pair<T, C> ld(const typename Storage<T, C>::type *p)
         r.e = u.x; r.h = u.y;
     }
     return r;
+}
+
+// Streaming (nontemporal) variants: data read or written once per step is
+// marked so it does not displace the halo rows other strips still need.
+template <typename T, int N> using Vec = T __attribute__((ext_vector_type(N)));
+
+template <typename T, bool C>
+__device__ __forceinline__ Pair<T, C> ld_nt(const typename Storage<T, C>::type *p)
+{
+    Pair<T, C> r;
+    if constexpr (C) {
+        if constexpr (sizeof(T) == 8) {
+            const Vec<double, 2> *q = reinterpret_cast<const Vec<double, 2> *>(p);
+            Vec<double, 2> u = __builtin_nontemporal_load(q), v = __builtin_nontemporal_load(q + 1);
+            r.er = u.x; r.ei = u.y; r.hr = v.x; r.hi = v.y;
+        } else {
+            Vec<float, 4> u = __builtin_nontemporal_load(reinterpret_cast<const Vec<float, 4> *>(p));
+            r.er = u.x; r.ei = u.y; r.hr = u.z; r.hi = u.w;
+        }
+    } else {
+        Vec<T, 2> u = __builtin_nontemporal_load(reinterpret_cast<const Vec<T, 2> *>(p));
+        r.e = u.x; r.h = u.y;
+    }
+    return r;
+}
+
+template <typename T, bool C>
+__device__ __forceinline__ void st_nt(typename Storage<T, C>::type *p, const Pair<T, C> &v)
+{
+    if constexpr (C) {
+        if constexpr (sizeof(T) == 8) {
+            Vec<double, 2> *q = reinterpret_cast<Vec<double, 2> *>(p);
+            __builtin_nontemporal_store(Vec<double, 2>{v.er, v.ei}, q);
+            __builtin_nontemporal_store(Vec<double, 2>{v.hr, v.hi}, q + 1);
+        } else {
+            __builtin_nontemporal_store(Vec<float, 4>{v.er, v.ei, v.hr, v.hi}, reinterpret_cast<Vec<float, 4> *>(p));
+        }
+    } else {
+        __builtin_nontemporal_store(Vec<T, 2>{v.e, v.h}, reinterpret_cast<Vec<T, 2> *>(p));
+    }
 }
 
 template <typename T, bool C>
