@@ -1,15 +1,277 @@
-// Reverse-mode derivative of the batched recursion (placeholder until the
-// checkpointed adjoint kernels land).
-#include "common.hpp"
+// Reverse-mode derivative of the batched recursion (real FP64 operators).
+//
+// For a loss L = sum_n <w_n, a_n>, where w_n is nonzero only at the start
+// site of each vector (w_n = dL/dmu_ee_n |s,e> + dL/dmu_he_n |s,h>), the
+// adjoint vectors obey the transposed recursion
+//     lam_n = w_n + 2 Ht^T lam_{n+1} - lam_{n+2},   lam_N = lam_{N+1} = 0,
+// and the derivative with respect to an operator parameter theta is
+//     dL/dtheta = sum_{n>=1} c_n <lam_n, (dHt/dtheta) a_{n-1}>,
+// c_1 = 1 (a_1 = Ht a_0 carries no factor 2) and c_n = 2 otherwise.  For a
+// real operator Ht^T = Ht, so the adjoint step is the forward stencil.  With
+// dHt/deps_j = (|j,e><j,e| - |j,h><j,h|)/a and
+// dHt/dDelta_j = (|j,e><j,h| + |j,h><j,e|)/a the per-site terms are
+//     g_eps(j)   += c_n/a sum_b [lam(j,e) a(j,e) - lam(j,h) a(j,h)]
+//     g_delta(j) += c_n/a sum_b [lam(j,e) a(j,h) + lam(j,h) a(j,e)].
+//
+// Memory: a_{n-1} is needed in reverse order.  A forward pass stores the
+// pairs (a_{jk}, a_{jk+1}) every k steps (k = ceil(sqrt(N)) by default);
+// each segment is recomputed from its pair just before the adjoint walks
+// through it.  Per tile: 2*ceil((N-1)/k) + max(k-2, 2) + 2 vectors.
+//
+// The sum over the tile's vectors is a wavefront reduction per site; each
+// (64-vector chunk, site) partial is owned by one wavefront, accumulated over
+// n without atomics and summed over chunks in a fixed order, so results are
+// bitwise reproducible.
+#include "step.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace cbdg {
+
+struct AdjArgs {
+    const void *lam1;    // lam_{n+1} (HAS1)
+    const void *lam2;    // lam_{n+2} (HAS2)
+    void *out;           // lam_n (aliases lam2 when HAS2)
+    const void *aprev;   // a_{n-1}
+    double th;           // t/a
+    int Lx, Ly, bcx, bcy;
+    int Bp, Bt;
+    int n, N;
+    const int32_t *sites;   // tile's start sites
+    const double *dmu_ee;   // tile rows, or null
+    const double *dmu_he;   // tile rows, or null
+    double cscale;          // c_n / a
+    double *gpart;          // [Bp/64][L2][2]
+    int64_t L2;
+    int n_strips, n_segs, nblocks;
+};
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <bool HAS1, bool HAS2, int W, int YS>
+__global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *__restrict__ lam1,
+                                                     const OnSite<double> *__restrict__ ons,
+                                                     const double2 *__restrict__ aprev)
+{
+    using P = Pair<double, false>;
+    using S = double2;
+    const int lb = xcd_remap(blockIdx.x, A.nblocks);
+    const int strip = lb % A.n_strips;
+    const int rest = lb / A.n_strips;
+    const int seg = rest % A.n_segs;
+    const int chunk = rest / A.n_segs;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int wave_base = chunk * kBlock + wave * kWave;
+    // whole wavefronts beyond the tile leave; partially filled ones stay for
+    // the reductions, their spare lanes contribute zero
+    if (wave_base >= A.Bt) return;
+    const uint32_t b = wave_base + lane;
+    const bool active = b < (uint32_t)A.Bt;
+    const int c64 = wave_base / kWave;
+
+    const int Lx = A.Lx, Ly = A.Ly;
+    const int x0 = strip * W;
+    const int y0 = seg * YS;
+    const int y1 = min(y0 + YS, Ly);
+    const int64_t Bp = A.Bp;
+    const S *l2 = reinterpret_cast<const S *>(A.lam2);
+    S *lo = reinterpret_cast<S *>(A.out);
+    const double th = A.th;
+    const int my_site = active ? A.sites[b] : -1;
+    const double we = (active && A.dmu_ee) ? A.dmu_ee[(int64_t)b * A.N + A.n] : 0.0;
+    const double wh = (active && A.dmu_he) ? A.dmu_he[(int64_t)b * A.N + A.n] : 0.0;
+    double *gp = A.gpart + (int64_t)c64 * A.L2 * 2;
+
+    int cx[W + 2];
+    uint32_t cm[W + 2];
+#pragma unroll
+    for (int k = 0; k < W + 2; ++k) {
+        const int x = x0 - 1 + k;
+        bool ok;
+        if (x < 0) { ok = A.bcx != 0; cx[k] = A.bcx ? x + Lx : 0; }
+        else if (x >= Lx) { ok = A.bcx && x == Lx; cx[k] = ok ? 0 : Lx - 1; }
+        else { ok = true; cx[k] = x; }
+        cm[k] = ok ? ~0u : 0u;
+    }
+    auto load_row = [&](P *row, int y) -> uint32_t {
+        bool ok = true;
+        int yy = y;
+        if (y < 0) { ok = A.bcy != 0; yy = A.bcy ? y + Ly : 0; }
+        else if (y >= Ly) { ok = A.bcy != 0; yy = A.bcy ? y - Ly : Ly - 1; }
+        const int64_t rbase = (int64_t)yy * Lx;
+#pragma unroll
+        for (int k = 0; k < W + 2; ++k) row[k] = ld<double, false>(lam1 + (rbase + cx[k]) * Bp + b);
+        return ok ? ~0u : 0u;
+    };
+    auto apply_mask = [&](P *row, uint32_t rm) {
+#pragma unroll
+        for (int k = 0; k < W + 2; ++k) row[k] = masked<double, false>(row[k], rm & cm[k]);
+    };
+    auto load_own = [&](const S *base_ptr, P *row, int y, bool nt) {
+        const int64_t rbase = (int64_t)y * Lx;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const S *q = base_ptr + (rbase + x0 + k) * Bp + b;
+            row[k] = nt ? ld_nt<double, false>(q) : ld<double, false>(q);
+        }
+    };
+
+    P up[W + 2], cur[W + 2], dn[W + 2], nx[W + 2];
+    P pc[W], pn[W], ac[W], an[W];
+    if constexpr (HAS1) {
+        apply_mask(up, load_row(up, y0 - 1));
+        apply_mask(cur, load_row(cur, y0));
+        apply_mask(dn, load_row(dn, y0 + 1));
+    }
+    if constexpr (HAS2) load_own(l2, pc, y0, true);
+    load_own(aprev, ac, y0, true);
+
+    auto compute_row = [&](int y) {
+        const int64_t srow = (int64_t)y * Lx;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int64_t s = srow + x0 + k;
+            P lam = zero_pair<double, false>();
+            if constexpr (HAS1) {
+                const OnSite<double> o = ons[s];
+                const P yv = apply_uniform<double, false>(o, th, cur[k + 1], cur[k], cur[k + 2], up[k + 1], dn[k + 1]);
+                lam.e = 2.0 * yv.e;
+                lam.h = 2.0 * yv.h;
+            }
+            if constexpr (HAS2) {
+                lam.e -= pc[k].e;
+                lam.h -= pc[k].h;
+            }
+            const bool hit = s == my_site;
+            lam.e += hit ? we : 0.0;
+            lam.h += hit ? wh : 0.0;
+            st_nt<double, false>(lo + s * Bp + b, lam);
+            double ge = active ? (lam.e * ac[k].e - lam.h * ac[k].h) : 0.0;
+            double gd = active ? (lam.e * ac[k].h + lam.h * ac[k].e) : 0.0;
+            ge = wave_sum_f64(ge);
+            gd = wave_sum_f64(gd);
+            if (lane == 0) {
+                gp[2 * s] += A.cscale * ge;
+                gp[2 * s + 1] += A.cscale * gd;
+            }
+        }
+    };
+
+    for (int y = y0; y < y1 - 1; ++y) {
+        uint32_t nm = 0;
+        if constexpr (HAS1) nm = load_row(nx, y + 2);
+        if constexpr (HAS2) load_own(l2, pn, y + 1, true);
+        load_own(aprev, an, y + 1, true);
+        compute_row(y);
+        if constexpr (HAS1) {
+            apply_mask(nx, nm);
+#pragma unroll
+            for (int k = 0; k < W + 2; ++k) { up[k] = cur[k]; cur[k] = dn[k]; dn[k] = nx[k]; }
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) { pc[k] = pn[k]; ac[k] = an[k]; }
+    }
+    compute_row(y1 - 1);
+}
+
+__global__ void k_fill_f64(double *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// grad[j] += sum over chunks (in chunk order) of the partials of site j
+__global__ void k_grad_reduce(const double *gpart, int nchunk, int64_t L2, double *grad_eps, double *grad_delta)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < L2; j += (int64_t)gridDim.x * blockDim.x) {
+        double ge = 0.0, gd = 0.0;
+        for (int c = 0; c < nchunk; ++c) {
+            ge += gpart[(c * L2 + j) * 2];
+            gd += gpart[(c * L2 + j) * 2 + 1];
+        }
+        if (grad_eps) grad_eps[j] += ge;
+        if (grad_delta) grad_delta[j] += gd;
+    }
+}
+
+constexpr int kAdjW = 4, kAdjYS = 64;
+
+template <bool HAS1, bool HAS2, int W>
+static int launch_adj_w(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
+{
+    A.n_strips = A.Lx / W;
+    A.n_segs = (int)ceil_div(A.Ly, kAdjYS);
+    const int n_chunks = (int)ceil_div(A.Bt, kBlock);
+    const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
+    if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments_backward: launch grid too large");
+    A.nblocks = (int)nb;
+    hipLaunchKernelGGL((k_adj_step<HAS1, HAS2, W, kAdjYS>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
+                       reinterpret_cast<const double2 *>(A.lam1), ons, reinterpret_cast<const double2 *>(A.aprev));
+    CBDG_CHECK_LAUNCH("k_adj_step");
+    return CBDG_OK;
+}
+
+template <bool HAS1, bool HAS2>
+static int launch_adj(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
+{
+    if (A.Lx % kAdjW == 0) return launch_adj_w<HAS1, HAS2, kAdjW>(A, ons, st);
+    if (A.Lx % 2 == 0) return launch_adj_w<HAS1, HAS2, 2>(A, ons, st);
+    return launch_adj_w<HAS1, HAS2, 1>(A, ons, st);
+}
+
+struct Plan {
+    int k;           // checkpoint stride
+    int J;           // segments
+    int nscratch;    // segment / scratch vectors
+    int64_t Bp;      // lane stride for the widest tile
+};
+
+static Plan make_plan(int N, int tile, int ckpt_stride)
+{
+    Plan p;
+    p.k = ckpt_stride > 0 ? ckpt_stride : std::max(1, (int)std::ceil(std::sqrt((double)N)));
+    p.J = N > 1 ? (int)ceil_div(N - 1, p.k) : 1;
+    p.nscratch = std::max(p.k - 2, 2);
+    p.Bp = lane_stride(tile);
+    return p;
+}
+
+static size_t plan_bytes(const Plan &p, int64_t L2)
+{
+    const size_t vec = (size_t)L2 * (size_t)p.Bp * sizeof(double2);
+    const size_t gpart = (size_t)(p.Bp / kWave) * (size_t)L2 * 2 * sizeof(double);
+    return (size_t)(2 * p.J + p.nscratch + 2) * vec + gpart;
+}
+
+}  // namespace cbdg
 
 using namespace cbdg;
 
-extern "C" int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
-                                            int32_t ckpt_stride, size_t *bytes)
+static int check_backward_op(const cbdg_op *op, const char *who)
+{
+    if (!op) return fail(CBDG_EINVAL, "%s: op must not be NULL", who);
+    if (op->scalar != CBDG_REAL || op->general)
+        return fail(CBDG_EUNSUPPORTED, "%s: the adjoint is implemented for real operators with uniform "
+                    "hopping and on-site pairing only", who);
+    return CBDG_OK;
+}
+
+extern "C" int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N, int32_t ckpt_stride,
+                                            size_t *bytes)
 {
     clear_error();
-    (void)op; (void)tile; (void)N; (void)ckpt_stride; (void)bytes;
-    return fail(CBDG_EUNSUPPORTED, "backward_workspace_size: not implemented yet");
+    int rc = check_backward_op(op, "backward_workspace_size");
+    if (rc) return rc;
+    if (!bytes || tile < 1 || N < 1 || ckpt_stride < 0)
+        return fail(CBDG_EINVAL, "backward_workspace_size: need bytes, tile >= 1, N >= 1, ckpt_stride >= 0");
+    *bytes = plan_bytes(make_plan(N, tile, ckpt_stride), op->L2);
+    return CBDG_OK;
 }
 
 extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t *start_sites,
@@ -20,8 +282,109 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
                                                double *grad_delta, void *stream)
 {
     clear_error();
-    (void)op; (void)start_sites; (void)n_start; (void)N; (void)tile; (void)ckpt_stride;
-    (void)dmu_ee; (void)dmu_he; (void)workspace; (void)workspace_bytes; (void)grad_eps;
-    (void)grad_delta; (void)stream;
-    return fail(CBDG_EUNSUPPORTED, "chebyshev_moments_backward: not implemented yet");
+    int rc = check_backward_op(op, "chebyshev_moments_backward");
+    if (rc) return rc;
+    if (n_start < 0 || N < 1 || tile < 1 || ckpt_stride < 0)
+        return fail(CBDG_EINVAL, "chebyshev_moments_backward: need n_start >= 0, N >= 1, tile >= 1, ckpt_stride >= 0");
+    if (n_start == 0 || N == 1 || (!dmu_ee && !dmu_he)) return CBDG_OK;  // nothing depends on eps or Delta
+    if (!start_sites || !workspace || (!grad_eps && !grad_delta))
+        return fail(CBDG_EINVAL, "chebyshev_moments_backward: start_sites, workspace and a gradient output are required");
+    const int eff_tile = (int)std::min<int64_t>(tile, n_start);
+    const Plan plan = make_plan(N, eff_tile, ckpt_stride);
+    const size_t need = plan_bytes(plan, op->L2);
+    if (workspace_bytes < need)
+        return fail(CBDG_EINVAL, "chebyshev_moments_backward: workspace of %zu bytes is smaller than the %zu needed",
+                    workspace_bytes, need);
+    hipStream_t st = as_stream(stream);
+    const int64_t L2 = op->L2;
+    const int64_t vec = L2 * plan.Bp;  // pairs per vector slot
+    double2 *base = reinterpret_cast<double2 *>(workspace);
+    auto C0 = [&](int j) { return base + (int64_t)j * vec; };
+    auto C1 = [&](int j) { return base + (int64_t)(plan.J + j) * vec; };
+    auto SC = [&](int i) { return base + (int64_t)(2 * plan.J + i) * vec; };
+    double2 *LA = base + (int64_t)(2 * plan.J + plan.nscratch) * vec;
+    double2 *LB = LA + vec;
+    double *gpart = reinterpret_cast<double *>(LB + vec);
+    const int k = plan.k;
+
+    for (int64_t t0 = 0; t0 < n_start; t0 += eff_tile) {
+        const int Bt = (int)std::min<int64_t>(eff_tile, n_start - t0);
+        const int64_t Bp = lane_stride(Bt);
+        const int nchunk = (int)(Bp / kWave);
+        const int32_t *ts = start_sites + t0;
+        const double *tee = dmu_ee ? dmu_ee + t0 * N : nullptr;
+        const double *the = dmu_he ? dmu_he + t0 * N : nullptr;
+
+        // forward: a_0 .. a_{N-2}, keeping the checkpoint pairs
+        rc = seed_tile_f64_real(C0(0), L2, Bt, ts, nullptr, nullptr, N, st);
+        if (rc) return rc;
+        StepArgs S{};
+        S.th = op->t / op->bounds.a;
+        S.Lx = op->Lx; S.Ly = op->Ly; S.bcx = op->bc_x; S.bcy = op->bc_y;
+        S.Bp = (int)Bp; S.Bt = Bt; S.N = N; S.sites = ts; S.mu_ee = nullptr; S.mu_he = nullptr;
+        const double2 *p2 = nullptr, *p1 = C0(0);
+        for (int n = 1; n <= N - 2; ++n) {
+            double2 *dest;
+            if (n % k == 0) dest = C0(n / k);
+            else if (k > 1 && n % k == 1) dest = C1(n / k);
+            else if (p2 == SC(0) || p2 == SC(1)) dest = const_cast<double2 *>(p2);
+            else dest = (p1 == SC(0)) ? SC(1) : SC(0);
+            S.first = n == 1;
+            S.n = n;
+            S.prev1 = p1;
+            S.prev2 = p2 ? p2 : p1;
+            S.out = dest;
+            rc = run_step(op, CBDG_FP64, S, st);
+            if (rc) return rc;
+            p2 = p1;
+            p1 = dest;
+        }
+
+        // backward over the segments in reverse
+        const int64_t ng = (int64_t)nchunk * L2 * 2;
+        hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>(ceil_div(ng, kBlock), 4096)), dim3(kBlock), 0,
+                           st, gpart, ng);
+        CBDG_CHECK_LAUNCH("k_fill_f64");
+        AdjArgs A{};
+        A.th = op->t / op->bounds.a;
+        A.Lx = op->Lx; A.Ly = op->Ly; A.bcx = op->bc_x; A.bcy = op->bc_y;
+        A.Bp = (int)Bp; A.Bt = Bt; A.N = N; A.sites = ts; A.dmu_ee = tee; A.dmu_he = the;
+        A.gpart = gpart; A.L2 = L2;
+        auto lam = [&](int n) { return ((N - 1 - n) % 2 == 0) ? LA : LB; };
+        for (int j = plan.J - 1; j >= 0; --j) {
+            const int s0 = j * k, e0 = std::min(s0 + k - 1, N - 2);
+            auto vec_of = [&](int m) -> const double2 * {
+                if (m == s0) return C0(j);
+                if (m == s0 + 1) return C1(j);
+                return SC(m - s0 - 2);
+            };
+            for (int m = s0 + 2; m <= e0; ++m) {
+                S.first = 0;
+                S.n = m;
+                S.prev1 = vec_of(m - 1);
+                S.prev2 = vec_of(m - 2);
+                S.out = SC(m - s0 - 2);
+                rc = run_step(op, CBDG_FP64, S, st);
+                if (rc) return rc;
+            }
+            for (int n = e0 + 1; n >= s0 + 1; --n) {
+                const bool has1 = n + 1 <= N - 1, has2 = n + 2 <= N - 1;
+                A.n = n;
+                A.lam1 = has1 ? lam(n + 1) : nullptr;
+                A.lam2 = has2 ? lam(n + 2) : nullptr;
+                A.out = lam(n);
+                A.aprev = vec_of(n - 1);
+                A.cscale = (n == 1 ? 1.0 : 2.0) / op->bounds.a;
+                const OnSite<double> *ons = op->onsite64;
+                if (has1 && has2) rc = launch_adj<true, true>(A, ons, st);
+                else if (has1) rc = launch_adj<true, false>(A, ons, st);
+                else rc = launch_adj<false, false>(A, ons, st);
+                if (rc) return rc;
+            }
+        }
+        hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)std::min<int64_t>(ceil_div(L2, kBlock), 4096)), dim3(kBlock), 0,
+                           st, gpart, nchunk, L2, grad_eps, grad_delta);
+        CBDG_CHECK_LAUNCH("k_grad_reduce");
+    }
+    return CBDG_OK;
 }

@@ -16,7 +16,7 @@
 //     is read about once (plus the strip's x halo and the segment's y halo,
 //     which neighbouring strips on the same XCD fetch at nearly the same time);
 //   - a_{n-2} is read and a_n written by the same lane at the same address.
-#include "stencil.hpp"
+#include "step.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -44,23 +44,6 @@ namespace cbdg {
 #define CBDG_LANE_PAD 0
 #endif
 
-struct StepArgs {
-    const void *prev1;   // a_{n-1}
-    const void *prev2;   // a_{n-2} (unused on the first step)
-    void *out;           // a_n (may alias prev2)
-    const void *onsite;  // OnSite<T>[L2]
-    const void *bonds;   // BondsR<T>/BondsC<T>[L2] (general operators)
-    double th;           // t/a (uniform operators)
-    int Lx, Ly, bcx, bcy;
-    int Bp;              // lane stride of the tile layout
-    int Bt;              // vectors in the tile
-    int first;           // 1: a_1 = Ht a_0
-    int n, N;            // moment index produced, moments per row
-    const int32_t *sites;  // [Bt] start sites of the tile
-    double *mu_ee;       // tile's first row
-    double *mu_he;       // tile's first row (complex interleaved for C)
-    int n_strips, n_segs, nblocks;
-};
 
 template <typename T, bool C, bool GEN, bool FIRST, int W, int YS>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
@@ -189,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     }
     compute_row(y1 - 1);
 
-    if (found) {
+    if (found && A.mu_ee) {
         const int64_t m = (int64_t)b * A.N + A.n;
         if constexpr (C) {
             A.mu_ee[m] = (double)mval.er;
@@ -222,6 +205,7 @@ __global__ void k_seed(typename Storage<T, C>::type *a0, int64_t Bp, int Bt, int
     const int64_t s = sites[b];
     const int64_t m = (int64_t)b * N;
     if (s < 0 || s >= L2) {
+        if (!mu_ee) return;
         const double nan = __builtin_nan("");
         for (int n = 0; n < N; ++n) {
             mu_ee[m + n] = nan;
@@ -233,6 +217,7 @@ __global__ void k_seed(typename Storage<T, C>::type *a0, int64_t Bp, int Bt, int
     Pair<T, C> one = zero_pair<T, C>();
     if constexpr (C) one.er = T(1); else one.e = T(1);
     st<T, C>(a0 + s * Bp + b, one);
+    if (!mu_ee) return;
     mu_ee[m] = 1.0;
     if (C) { mu_he[2 * m] = 0.0; mu_he[2 * m + 1] = 0.0; }
     else mu_he[m] = 0.0;
@@ -304,9 +289,34 @@ static int launch_step(StepArgs A, hipStream_t st)
     return launch_step_w<T, C, GEN, 1>(A, st);
 }
 
-// Lane stride of a tile of B vectors: B rounded up to the wavefront, plus
-// the stride padding.
-static int64_t lane_stride(int64_t B) { return round_up(B, kWave) + CBDG_LANE_PAD; }
+int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st)
+{
+    const bool f64 = precision == CBDG_FP64;
+    const bool cplx = op->scalar == CBDG_COMPLEX;
+    A.onsite = f64 ? (const void *)op->onsite64 : (const void *)op->onsite32;
+    A.bonds = f64 ? op->bonds64 : op->bonds32;
+    if (f64) {
+        if (cplx) return op->general ? launch_step<double, true, true>(A, st) : launch_step<double, true, false>(A, st);
+        return op->general ? launch_step<double, false, true>(A, st) : launch_step<double, false, false>(A, st);
+    }
+    if (cplx) return op->general ? launch_step<float, true, true>(A, st) : launch_step<float, true, false>(A, st);
+    return op->general ? launch_step<float, false, true>(A, st) : launch_step<float, false, false>(A, st);
+}
+
+int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, double *mu_ee, double *mu_he, int N,
+                       hipStream_t st)
+{
+    using S = Storage<double, false>::type;
+    const int64_t Bp = lane_stride(Bt);
+    const int64_t nz = L2 * Bp;
+    hipLaunchKernelGGL((k_zero<double, false>), dim3((unsigned)std::min<int64_t>(ceil_div(nz, kBlock), 8192)),
+                       dim3(kBlock), 0, st, reinterpret_cast<S *>(a0), nz);
+    CBDG_CHECK_LAUNCH("k_zero");
+    hipLaunchKernelGGL((k_seed<double, false>), dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st,
+                       reinterpret_cast<S *>(a0), Bp, Bt, L2, sites, mu_ee, mu_he, N);
+    CBDG_CHECK_LAUNCH("k_seed");
+    return CBDG_OK;
+}
 
 template <typename T, bool C>
 static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start, int N, int tile,

@@ -1,0 +1,45 @@
+// Internal interface of the recursion step, shared by the forward moments
+// and the checkpointed adjoint.
+#pragma once
+
+#include "stencil.hpp"
+
+#ifndef CBDG_LANE_PAD
+#define CBDG_LANE_PAD 0
+#endif
+
+namespace cbdg {
+
+struct StepArgs {
+    const void *prev1;   // a_{n-1}
+    const void *prev2;   // a_{n-2} (unused on the first step)
+    void *out;           // a_n (may alias prev2)
+    const void *onsite;  // OnSite<T>[L2]
+    const void *bonds;   // BondsR<T>/BondsC<T>[L2] (general operators)
+    double th;           // t/a (uniform operators)
+    int Lx, Ly, bcx, bcy;
+    int Bp;              // lane stride of the tile layout
+    int Bt;              // vectors in the tile
+    int first;           // 1: a_1 = Ht a_0
+    int n, N;            // moment index produced, moments per row
+    const int32_t *sites;  // [Bt] start sites of the tile
+    double *mu_ee;       // tile's first row
+    double *mu_he;       // tile's first row (complex interleaved for C)
+    int n_strips, n_segs, nblocks;
+};
+
+// Lane stride of a tile of B vectors: B rounded up to the wavefront, plus
+// the stride padding.
+inline int64_t lane_stride(int64_t B) { return round_up(B, kWave) + CBDG_LANE_PAD; }
+
+// One recursion step (A.first: a_1 = Ht a_0) on the stream; A.onsite/A.bonds
+// are filled from the operator.  prev1 must not alias out; prev2 may.
+// mu_ee == nullptr skips the moment extraction.
+int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st);
+
+// a_0 = |s_b,e> for the tile's vectors (FP64 real layout); writes mu_0 when
+// mu_ee is not null.
+int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, double *mu_ee, double *mu_he, int N,
+                       hipStream_t st);
+
+}  // namespace cbdg

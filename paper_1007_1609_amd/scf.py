@@ -67,3 +67,157 @@ def plain_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int
             break
     torch.cuda.synchronize()
     return ScfResult(delta, it, r, hist, time.perf_counter() - t0, it)
+
+
+def _gmres(matvec, rhs, tol, restart=30, maxiter=60):
+    """Restarted GMRES (modified Gram-Schmidt Arnoldi, Givens rotations) on
+    host FP64 vectors of the size of Delta; matvec runs on the device."""
+    import numpy as np
+    n = rhs.size
+    x = np.zeros(n)
+    bnorm = np.linalg.norm(rhs)
+    if bnorm == 0.0:
+        return x, 0
+    used = 0
+    r = rhs.copy()
+    while used < maxiter:
+        beta = np.linalg.norm(r)
+        if beta <= tol * bnorm:
+            break
+        m = min(restart, maxiter - used)
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        k_used = 0
+        for k in range(m):
+            w = matvec(V[k])
+            used += 1
+            for i in range(k + 1):
+                H[i, k] = np.dot(V[i], w)
+                w = w - H[i, k] * V[i]
+            H[k + 1, k] = np.linalg.norm(w)
+            if H[k + 1, k] > 0:
+                V[k + 1] = w / H[k + 1, k]
+            for i in range(k):
+                t = cs[i] * H[i, k] + sn[i] * H[i + 1, k]
+                H[i + 1, k] = -sn[i] * H[i, k] + cs[i] * H[i + 1, k]
+                H[i, k] = t
+            den = np.hypot(H[k, k], H[k + 1, k])
+            cs[k], sn[k] = (1.0, 0.0) if den == 0 else (H[k, k] / den, H[k + 1, k] / den)
+            H[k, k] = cs[k] * H[k, k] + sn[k] * H[k + 1, k]
+            H[k + 1, k] = 0.0
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            k_used = k + 1
+            if abs(g[k + 1]) <= tol * bnorm or H[k, k] == 0:
+                break
+        y = np.linalg.solve(np.triu(H[:k_used, :k_used]), g[:k_used])
+        x = x + V[:k_used].T @ y
+        if abs(g[k_used]) <= tol * bnorm:
+            break
+        r = rhs - matvec(x)
+        used += 1
+    return x, used
+
+
+def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
+                  tol: float = 1e-6, max_newton: int = 30, jv: str = "vjp", fd_step: float = 1e-7,
+                  gmres_tol: float = 1e-2, warmup_tol: float = 1e-2, max_warmup: int = 100,
+                  kernel: str = "jackson", callback=None) -> ScfResult:
+    """Solve F(Delta) = Delta with inexact Newton steps (J_F - I) d = -(F - Delta).
+
+    The gap map has more than one fixed point (Delta -> -Delta, and the
+    trivial Delta = 0), so the solve first runs plain-mixing iterations until
+    max|F - Delta| < warmup_tol, which keeps it on the branch plain mixing
+    selects, then takes Newton steps with a backtracking line search on
+    ||F(Delta) - Delta||_2.
+
+    J_F v is one reverse pass (the gap map's Jacobian is symmetric for a real
+    operator with uniform U, so the vector-Jacobian product J_F^T v equals
+    J_F v), or a forward finite difference (jv="fd").  The residual test is
+    the one of plain mixing: max|F(Delta) - Delta| < tol.  counts["F"] is
+    the number of gap-map evaluations, counts["J"] the Jacobian products.
+    """
+    import numpy as np
+    from .api import backward_workspace_bytes, chebyshev_moments_backward, gap_update_backward
+    if op.is_complex:
+        raise L.CbdgError(L.CBDG_EUNSUPPORTED, "newton_krylov", "real operators only")
+    dev = delta0.device
+    sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
+    w = op.weights(kernel)
+    ws = workspace(moments_workspace_bytes(op, min(tile, op.L2), L.CBDG_FP64), dev)
+    mu_ee = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
+    mu_he = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
+    resid = torch.empty(1, dtype=torch.float64, device=dev)
+    counts = {"F": 0, "J": 0, "warmup": 0, "newton": 0}
+    bw_ws = {}
+
+    def F(delta_t):
+        op.update_delta(delta_t)
+        chebyshev_moments(op, sites, N, tile, L.CBDG_FP64, ws=ws, out=(mu_ee, mu_he))
+        new, _ = gap_update(mu_he, w, U, delta_t, 1.0, resid=resid)
+        counts["F"] += 1
+        return new
+
+    t0 = time.perf_counter()
+    delta = delta0.clone()
+    hist: List[float] = []
+    Fd = F(delta)
+    g = Fd - delta
+    r = float(torch.max(torch.abs(g)).item())
+    hist.append(r)
+    # plain mixing into the basin of the branch it converges to
+    while r >= max(tol, warmup_tol) and counts["warmup"] < max_warmup:
+        delta = Fd
+        Fd = F(delta)
+        g = Fd - delta
+        r = float(torch.max(torch.abs(g)).item())
+        hist.append(r)
+        counts["warmup"] += 1
+    for _ in range(max_newton):
+        if callback is not None:
+            callback(len(hist), r)
+        if not (r == r):
+            raise L.CbdgError(L.CBDG_EBOUNDS, "newton_krylov", "non-finite residual")
+        if r < tol:
+            break
+        counts["newton"] += 1
+        op.update_delta(delta)
+        if jv != "fd" and "ws" not in bw_ws:
+            bw_ws["ws"] = workspace(backward_workspace_bytes(op, min(tile, op.L2), N), dev)
+        Fd_now, delta_now = Fd, delta
+
+        def matvec(v_np):
+            v = torch.as_tensor(v_np, dtype=torch.float64, device=dev)
+            counts["J"] += 1
+            if jv == "fd":
+                h = fd_step / max(1e-300, float(np.max(np.abs(v_np))))
+                Fp = F(delta_now + h * v)
+                counts["F"] -= 1
+                jvv = (Fp - Fd_now) / h
+            else:
+                d_mu, _ = gap_update_backward(v, N, w, U, 1.0, want_delta_in=False)
+                _, jvv = chebyshev_moments_backward(op, sites, N, tile, None, d_mu, ws=bw_ws["ws"])
+            return (jvv - v).cpu().numpy()
+
+        d_np, _ = _gmres(matvec, -g.cpu().numpy(), gmres_tol)
+        d = torch.as_tensor(d_np, dtype=torch.float64, device=dev)
+        g2 = float(torch.linalg.norm(g).item())
+        lam = 1.0
+        while True:
+            trial = delta + lam * d
+            Ft = F(trial)
+            gt = Ft - trial
+            if float(torch.linalg.norm(gt).item()) <= (1.0 - 1e-4 * lam) * g2 or lam < 1.0 / 64:
+                break
+            lam *= 0.5
+        delta, Fd, g = trial, Ft, gt
+        r = float(torch.max(torch.abs(g)).item())
+        hist.append(r)
+    torch.cuda.synchronize()
+    res = ScfResult(delta, len(hist), r, hist, time.perf_counter() - t0, counts["F"] + counts["J"])
+    res.counts = dict(counts)
+    return res
