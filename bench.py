@@ -116,6 +116,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 2 GiB device copy instead (HBM calibration)")
+    ap.add_argument("--form", choices=["scf-step", "complex", "adjoint", "scf"], default="scf-step",
+                    help="scf-step (default): one SCF iteration of the 256x256 workload; complex: "
+                         "512x512 Peierls/d-wave LDOS workload; adjoint: 128x128 gradients and "
+                         "Newton-Krylov; scf: full self-consistent solve of the 256x256 workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
@@ -132,6 +136,12 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy_probe:
         copy_probe(dev)
+        return
+    if args.form != "scf-step":
+        import bench_forms
+        line = {"complex": bench_forms.complex_form, "adjoint": bench_forms.adjoint_form,
+                "scf": bench_forms.scf_form}[args.form](args, dev)
+        print(json.dumps(line), flush=True)
         return
     N = 1024 if args.precision == "fp64" else 2048
     w = W.config1(N=N) if args.precision == "fp64" else W.config2()
@@ -252,6 +262,9 @@ def main():
         "wall_s_timed": wall,
     }
     log("timed steps done: %.1f ms/step, %.3g moments/s, %.0f GB/s" % (ms_per_step, value, achieved))
+    if args.precision == "fp32":
+        import bench_forms
+        line["accuracy"] = bench_forms.fp32_accuracy(w, op, mu_ee, mu_he, energies, dev)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
         line["cpu_baseline"] = cpu_baseline(w, a, b, args.cpu_sites, threads)

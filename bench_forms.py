@@ -1,0 +1,221 @@
+"""Measurements of the forms beside the default benchmark step (imported by
+bench.py).  Each returns one JSON-able dict.
+
+fp32_accuracy  FP32 recursion vs the FP64 recursion on the same operator:
+               moments, one-step Delta and LDOS errors (the FP64 path itself is
+               held to the oracle by the parity tests)
+complex_form   512x512 Peierls + d-wave lattice, 4096 start sites, N = 2048,
+               complex128 and complex64 recursion, LDOS at 512 energies
+adjoint_form   128x128 workload with 64 impurities, N = 512: forward pass,
+               reverse pass for dSum(Delta)/dV, dLDOS(0)/dV at the centre, and
+               the self-consistent solve by plain mixing and by Newton-Krylov
+scf_form       256x256 workload solved self-consistently to max|dDelta| < 1e-6
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+import paper_1007_1609_amd as P
+import workloads as W
+from paper_1007_1609_amd import scf
+
+METRIC = "Chebyshev moments/sec and HBM GB/s (FP64 vs FP32); self-consistent solve time"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _timed(fn):
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    out = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1) / 1e3
+
+
+def fp32_accuracy(w, op, mu_ee32, mu_he32, energies, dev, n_rows=2048):
+    """FP32-recursion results vs the FP64 recursion for the first n_rows
+    start sites at the initial Delta."""
+    d0 = torch.as_tensor(w.delta, device=dev)
+    op.update_delta(d0)
+    sites = torch.arange(n_rows, dtype=torch.int32, device=dev)
+    m32 = P.chebyshev_moments(op, sites, w.N, w.tile, P.CBDG_FP32_ACC64)
+    m64 = P.chebyshev_moments(op, sites, w.N, w.tile, P.CBDG_FP64)
+    wt = op.weights()
+    d32, _ = P.gap_update(m32[1], wt, w.U, d0[:n_rows].contiguous())
+    d64, _ = P.gap_update(m64[1], wt, w.U, d0[:n_rows].contiguous())
+    l32 = P.ldos(m32[0], wt, energies)
+    l64 = P.ldos(m64[0], wt, energies)
+    torch.cuda.synchronize()
+    mom = max(float((m32[0] - m64[0]).abs().max()), float((m32[1] - m64[1]).abs().max()))
+    return {"reference": "FP64 recursion on the GPU (held to the oracle at 1e-10 by the parity tests)",
+            "rows": n_rows, "N": w.N,
+            "moments_max_abs_err": mom,
+            "delta_one_step_max_abs_err": float((d32 - d64).abs().max()),
+            "ldos_max_err_rel_to_max": float((l32 - l64).abs().max() / l64.abs().max()),
+            "bars": {"delta": 1e-6, "ldos_rel": 1e-5}}
+
+
+def _moments_pass(op, sites, N, tile, prec, ws, out):
+    """All tiles, one call per tile with HIP events; returns per-launch us."""
+    stream = torch.cuda.current_stream()
+    n = sites.numel()
+    ev = []
+    for t0 in range(0, n, tile):
+        t1 = min(n, t0 + tile)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.chebyshev_moments(op, sites[t0:t1], N, tile, prec, ws=ws, out=(out[0][t0:t1], out[1][t0:t1]))
+        e1.record(stream)
+        ev.append((e0, e1, t1 - t0))
+    torch.cuda.synchronize()
+    total = sum(a.elapsed_time(b) for a, b, _ in ev) / 1e3
+    return total, ev
+
+
+def complex_form(args, dev):
+    w = W.config3()
+    N, tile = w.N, w.tile
+    op = P.Operator.from_workload(w, dev)
+    sites = torch.as_tensor(w.start_sites, device=dev)
+    n = sites.numel()
+    E = torch.as_tensor(w.energies, device=dev)
+    wt = op.weights()
+    res = {}
+    ldos = {}
+    for name, prec, s_bytes in (("complex128", P.CBDG_FP64, 8), ("complex64", P.CBDG_FP32_ACC64, 4)):
+        ws = P.workspace(P.moments_workspace_bytes(op, tile, prec), dev)
+        out = (torch.empty((n, N), dtype=torch.float64, device=dev),
+               torch.empty((n, N), dtype=torch.complex128, device=dev))
+        # warm-up on one tile, then the timed pass over all 4 tiles
+        P.chebyshev_moments(op, sites[:64], N, 64, prec, ws=ws)
+        torch.cuda.synchronize()
+        t, ev = _moments_pass(op, sites, N, tile, prec, ws, out)
+        ld, t_ldos = _timed(lambda: P.ldos(out[0], wt, E))
+        ldos[name] = ld
+        launches = sum(N - 1 for _ in ev)
+        alg = sum((N - 1) * 3.0 * w.D * 2 * s_bytes * ((bt + 63) // 64 * 64) for _, _, bt in ev)
+        gbs = alg / t / 1e9
+        res[name] = {"moments_per_s": n * N / (t + t_ldos), "seconds_moments": t, "seconds_ldos": t_ldos,
+                     "avg_launch_us": t / launches * 1e6, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+                     "moments_bounded": bool(P.check_moments(out[0], out[1], 1e-9 if s_bytes == 8 else 1e-4))}
+        log("%s: %.2f s moments, %.0f GB/s" % (name, t, gbs))
+        del ws, out
+        torch.cuda.empty_cache()
+    err = float((ldos["complex64"] - ldos["complex128"]).abs().max() / ldos["complex128"].abs().max())
+    op.close()
+    line = {"metric": METRIC, "value": res["complex128"]["moments_per_s"], "unit": "moments/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "complex128 (and complex64)",
+            "data": "synthetic",
+            "config": {"workload": "%s: 512x512 open lattice, Peierls flux 1/256 per plaquette, d-wave bond "
+                                   "pairing with four phase windings, N=%d, 4096 start sites (stride-8 grid) "
+                                   "in tiles of %d, LDOS at 512 energies" % (w.name, N, tile)},
+            "forms": res, "complex64_ldos_err_rel_to_max": err,
+            "roofline": {"kernel": "k_cheb_step<complex double>", "bound": "hbm",
+                         "achieved": res["complex128"]["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": res["complex128"]["frac"], "traffic": None}}
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+        a, b = oracle.workload_bounds(w)[2:]
+        H = oracle.workload_csr(w, a, b)
+        Nc = 256
+        sample = w.start_sites[np.linspace(0, n - 1, threads).astype(int)]
+        t0 = time.perf_counter()
+        oracle.moments(H, sample, Nc, n_threads=threads)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": len(sample) * Nc / dt, "unit": "moments/s", "cores": oracle.max_threads(),
+                                "kind": "oracle",
+                                "sample": "%d start sites of the same 512x512 complex lattice, N=%d, "
+                                          "%.1f s" % (len(sample), Nc, dt)}
+    return line
+
+
+def adjoint_form(args, dev):
+    from paper_1007_1609_amd import autograd as AG
+    w = W.config4()
+    N, tile = w.N, w.tile
+    op = P.Operator.from_workload(w, dev)
+    a, b = op.bounds.a, op.bounds.b
+    op.close()
+    geom = AG.Geometry.of(w, a, b)
+    sites = torch.as_tensor(w.start_sites, device=dev)
+    wt = P.weights(a, b)
+
+    def forward_backward():
+        eps = torch.as_tensor(w.eps, device=dev).requires_grad_(True)
+        delta = torch.as_tensor(w.delta, device=dev).requires_grad_(True)
+        mu_ee, mu_he = AG.moments(eps, delta, geom, sites, N, tile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = AG.gap_map(mu_he, delta, w.U, wt).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        return eps.grad, time.perf_counter() - t0
+
+    forward_backward()  # warm-up (allocates the checkpoint workspace)
+    eps0 = torch.as_tensor(w.eps, device=dev)
+    d0 = torch.as_tensor(w.delta, device=dev)
+    (_, _), t_fwd = _timed(lambda: AG.moments(eps0, d0, geom, sites, N, tile))
+    g_sum, t_bwd = forward_backward()
+    # dLDOS(0)/dV at the centre site: one start vector
+    s0 = w.notes["centre_site"]
+    eps = torch.as_tensor(w.eps, device=dev).requires_grad_(True)
+    t0 = time.perf_counter()
+    mu_ee, _ = AG.moments(eps, d0, geom, torch.tensor([s0], dtype=torch.int32, device=dev), N, 64)
+    AG.local_dos(mu_ee, torch.zeros(1, dtype=torch.float64, device=dev), wt).sum().backward()
+    torch.cuda.synchronize()
+    t_ldos = time.perf_counter() - t0
+    log("adjoint: forward %.2f s, reverse %.2f s" % (t_fwd, t_bwd))
+    # self-consistency: plain mixing vs Newton-Krylov (both to 1e-6)
+    out = {}
+    op = P.Operator.from_workload(w, dev)
+    r = scf.plain_mixing(op, w.U, d0, N, tile, tol=1e-6, max_iter=300)
+    out["plain_mixing"] = {"iterations": r.iterations, "gap_map_evaluations": r.iterations,
+                           "seconds": r.seconds, "residual": r.residual}
+    ref = r.delta
+    op.close()
+    log("plain mixing: %d iterations, %.1f s" % (r.iterations, r.seconds))
+    for jv in ("vjp", "fd"):
+        op = P.Operator.from_workload(w, dev)
+        r = scf.newton_krylov(op, w.U, d0, N, tile, tol=1e-6, jv=jv)
+        op.close()
+        out["newton_krylov_" + jv] = {"newton_steps": r.counts["newton"], "warmup_iterations": r.counts["warmup"],
+                                      "gap_map_evaluations": r.counts["F"], "jacobian_products": r.counts["J"],
+                                      "seconds": r.seconds, "residual": r.residual,
+                                      "max_abs_diff_vs_plain": float((r.delta - ref).abs().max())}
+        log("newton-krylov %s: %s, %.1f s" % (jv, r.counts, r.seconds))
+    n_moments = w.L2 * N
+    return {"metric": METRIC, "value": n_moments / t_fwd, "unit": "moments/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "%s: 128x128 open lattice, 64 impurities V~U[0,4] (seed 4), t=1 mu=-0.5 "
+                                   "U=2, N=%d, all 16384 start sites in tiles of %d, sqrt(N) checkpoints"
+                                   % (w.name, N, tile)},
+            "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd,
+            "reverse_over_forward": t_bwd / t_fwd, "seconds_dldos0_dV_centre": t_ldos,
+            "grad_norm_inf": float(g_sum.abs().max()), "scf": out}
+
+
+def scf_form(args, dev):
+    w = W.config1()
+    op = P.Operator.from_workload(w, dev)
+    d0 = torch.as_tensor(w.delta, device=dev)
+    r = scf.plain_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60,
+                         callback=lambda it, res: log("iteration %d residual %.3e" % (it, res)))
+    op.close()
+    return {"metric": METRIC, "value": r.seconds, "unit": "s (self-consistent solve)", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "%s: 256x256 open lattice, 655 disordered sites, U=2.5, N=1024, "
+                                   "all 65536 sites, plain mixing (alpha=1) to max|dDelta| < 1e-6" % w.name},
+            "iterations": r.iterations, "residual": r.residual, "history": r.history,
+            "seconds_per_iteration": r.seconds / r.iterations,
+            "moments_per_s": w.L2 * w.N * r.iterations / r.seconds}

@@ -45,6 +45,7 @@ struct AdjArgs {
     double *gpart;          // [Bp/64][L2][2]
     int64_t L2;
     int n_strips, n_segs, nblocks;
+    int ys;               // rows per segment
 };
 
 __device__ __forceinline__ double wave_sum_f64(double v)
@@ -54,7 +55,7 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
-template <bool HAS1, bool HAS2, int W, int YS>
+template <bool HAS1, bool HAS2, int W>
 __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *__restrict__ lam1,
                                                      const OnSite<double> *__restrict__ ons,
                                                      const double2 *__restrict__ aprev)
@@ -77,8 +78,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
 
     const int Lx = A.Lx, Ly = A.Ly;
     const int x0 = strip * W;
-    const int y0 = seg * YS;
-    const int y1 = min(y0 + YS, Ly);
+    const int y0 = seg * A.ys;
+    const int y1 = min(y0 + A.ys, Ly);
     const int64_t Bp = A.Bp;
     const S *l2 = reinterpret_cast<const S *>(A.lam2);
     S *lo = reinterpret_cast<S *>(A.out);
@@ -163,6 +164,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
         }
     };
 
+    // one row per trip: unrolling would duplicate the register window
+#pragma unroll 1
     for (int y = y0; y < y1 - 1; ++y) {
         uint32_t nm = 0;
         if constexpr (HAS1) nm = load_row(nx, y + 2);
@@ -206,12 +209,14 @@ template <bool HAS1, bool HAS2, int W>
 static int launch_adj_w(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
 {
     A.n_strips = A.Lx / W;
-    A.n_segs = (int)ceil_div(A.Ly, kAdjYS);
     const int n_chunks = (int)ceil_div(A.Bt, kBlock);
+    A.ys = kAdjYS;
+    while (A.ys > 8 && (int64_t)A.n_strips * n_chunks * ceil_div(A.Ly, A.ys) < 2048) A.ys /= 2;
+    A.n_segs = (int)ceil_div(A.Ly, A.ys);
     const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments_backward: launch grid too large");
     A.nblocks = (int)nb;
-    hipLaunchKernelGGL((k_adj_step<HAS1, HAS2, W, kAdjYS>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
+    hipLaunchKernelGGL((k_adj_step<HAS1, HAS2, W>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
                        reinterpret_cast<const double2 *>(A.lam1), ons, reinterpret_cast<const double2 *>(A.aprev));
     CBDG_CHECK_LAUNCH("k_adj_step");
     return CBDG_OK;

@@ -45,7 +45,7 @@ namespace cbdg {
 #endif
 
 
-template <typename T, bool C, bool GEN, bool FIRST, int W, int YS>
+template <typename T, bool C, bool GEN, bool FIRST, int W, bool PF>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
     StepArgs A, const typename Storage<T, C>::type *__restrict__ a1,
     const OnSite<T> *__restrict__ ons, const void *__restrict__ bonds)
@@ -62,8 +62,8 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
 
     const int Lx = A.Lx, Ly = A.Ly;
     const int x0 = strip * W;
-    const int y0 = seg * YS;
-    const int y1 = min(y0 + YS, Ly);
+    const int y0 = seg * A.ys;
+    const int y1 = min(y0 + A.ys, Ly);
     const int64_t Bp = A.Bp;
     // a1 (a_{n-1}) is never written by this launch -- out aliases a_{n-2}
     // only -- and the coefficients are read-only, which lets the wave-uniform
@@ -122,13 +122,14 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     // latency overlaps the arithmetic and the stores of row y.  The lane's own
     // moment is captured with a select and stored once at the end, so the
     // loop body issues a fixed number of memory operations.
-    P up[W + 2], cur[W + 2], dn[W + 2], nx[W + 2], pc[W], pn[W];
+    P up[W + 2], cur[W + 2], dn[W + 2], nx[W + 2], pc[W];
+    [[maybe_unused]] P pn[PF ? W : 1];
     P mval = zero_pair<T, C>();
     bool found = false;
     apply_mask(up, load_row(up, y0 - 1));
     apply_mask(cur, load_row(cur, y0));
     apply_mask(dn, load_row(dn, y0 + 1));
-    if constexpr (!FIRST) load_prev2(pc, y0);
+    if constexpr (!FIRST && PF) load_prev2(pc, y0);
 
     auto compute_row = [&](int y) {
         const int64_t srow = (int64_t)y * Lx;
@@ -155,21 +156,27 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
             else st<T, C>(ao + s * Bp + b, ov);
             const bool hit = s == my_site;
             found = found || hit;
-            mval = hit ? ov : mval;
+            mval = select_pair<T, C>(hit, ov, mval);
         }
     };
+    // one row per trip: unrolling would duplicate the register window
+#pragma unroll 1
     for (int y = y0; y < y1 - 1; ++y) {
+        // without the a_{n-2} prefetch its loads go first, so waiting for
+        // them does not wait for the next row of a_{n-1}
+        if constexpr (!FIRST && !PF) load_prev2(pc, y);
         const uint32_t nm = load_row(nx, y + 2);
-        if constexpr (!FIRST) load_prev2(pn, y + 1);
+        if constexpr (!FIRST && PF) load_prev2(pn, y + 1);
         compute_row(y);
         apply_mask(nx, nm);
 #pragma unroll
         for (int k = 0; k < W + 2; ++k) { up[k] = cur[k]; cur[k] = dn[k]; dn[k] = nx[k]; }
-        if constexpr (!FIRST) {
+        if constexpr (!FIRST && PF) {
 #pragma unroll
             for (int k = 0; k < W; ++k) pc[k] = pn[k];
         }
     }
+    if constexpr (!FIRST && !PF) load_prev2(pc, y1 - 1);
     compute_row(y1 - 1);
 
     if (found && A.mu_ee) {
@@ -223,70 +230,78 @@ __global__ void k_seed(typename Storage<T, C>::type *a0, int64_t Bp, int Bt, int
     else mu_he[m] = 0.0;
 }
 
-// Strip width W and row-segment length YS per vector type (register window
-// of 6W + 8 Nambu pairs per lane).  Chosen by measurement on MI355X: wider
-// strips issue fewer halo requests per output and win even at 2 waves/SIMD
-// (FP64: W = 2/4/8 -> 727/665/623 us per 1024-vector step at 256x256).
-#ifndef CBDG_W_D
-#define CBDG_W_D 8
-#endif
-#ifndef CBDG_YS_D
-#define CBDG_YS_D 64
-#endif
-#ifndef CBDG_W_F
-#define CBDG_W_F 8
-#endif
-#ifndef CBDG_YS_F
-#define CBDG_YS_F 32
-#endif
-#ifndef CBDG_W_Z
-#define CBDG_W_Z 4
-#endif
-#ifndef CBDG_YS_Z
-#define CBDG_YS_Z 32
-#endif
-#ifndef CBDG_W_C
-#define CBDG_W_C 4
-#endif
-#ifndef CBDG_YS_C
-#define CBDG_YS_C 32
-#endif
+// Launch shapes per vector type, chosen by measurement on MI355X (one
+// 1024-vector step):
+//   W   strip width in sites (W + 2 columns of a_{n-1} per row in registers)
+//   PF  rows of a_{n-2} prefetched one row ahead (more registers) or loaded at
+//       the top of their own row
+//   YS  longest row segment; shortened at launch until the grid fills the GPU
+// "big" is used when W_BIG divides Lx and the grid has at least 2048
+// workgroups at 16-row segments, "small" otherwise.  FP64 at 256x256:
+// W8+PF 508 us, W8 541, W4+PF 565, W4 556; at 128x128: W4 126, W8+PF 141.
+// complex128 at 512x512: W2+PF 5.27 ms, W4 5.33, W1+PF 5.80; complex64:
+// W8 2.20 ms, W4+PF 2.32.
 template <typename T, bool C> struct StepShape;
-template <> struct StepShape<double, false> { static constexpr int W = CBDG_W_D, YS = CBDG_YS_D; };
-template <> struct StepShape<float, false> { static constexpr int W = CBDG_W_F, YS = CBDG_YS_F; };
-template <> struct StepShape<double, true> { static constexpr int W = CBDG_W_Z, YS = CBDG_YS_Z; };
-template <> struct StepShape<float, true> { static constexpr int W = CBDG_W_C, YS = CBDG_YS_C; };
+template <> struct StepShape<double, false> {
+    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 64;
+    static constexpr bool PF_BIG = true, PF_SMALL = false;
+};
+template <> struct StepShape<float, false> {
+    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 32;
+    static constexpr bool PF_BIG = true, PF_SMALL = false;
+};
+template <> struct StepShape<double, true> {
+    static constexpr int W_BIG = 2, W_SMALL = 2, YS = 32;
+    static constexpr bool PF_BIG = true, PF_SMALL = true;
+};
+template <> struct StepShape<float, true> {
+    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 32;
+    static constexpr bool PF_BIG = false, PF_SMALL = false;
+};
 
-template <typename T, bool C, bool GEN, int W>
+// Row-segment length: the longest of YS, YS/2, ... (not below 8) that still
+// gives every CU several workgroups; shorter segments cost extra halo rows.
+static int segment_rows(int Ly, int64_t other_blocks, int ys_max)
+{
+    constexpr int64_t kTargetBlocks = 2048;
+    int ys = ys_max;
+    while (ys > 8 && other_blocks * ceil_div(Ly, ys) < kTargetBlocks) ys /= 2;
+    return ys;
+}
+
+template <typename T, bool C, bool GEN, int W, bool PF>
 static int launch_step_w(StepArgs A, hipStream_t st)
 {
-    constexpr int YS = StepShape<T, C>::YS;
     A.n_strips = A.Lx / W;
-    A.n_segs = (int)ceil_div(A.Ly, YS);
     const int n_chunks = (int)ceil_div(A.Bt, kBlock);
+    A.ys = segment_rows(A.Ly, (int64_t)A.n_strips * n_chunks, StepShape<T, C>::YS);
+    A.n_segs = (int)ceil_div(A.Ly, A.ys);
     const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
     A.nblocks = (int)nb;
     const auto *a1 = reinterpret_cast<const typename Storage<T, C>::type *>(A.prev1);
     const auto *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
     if (A.first)
-        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, YS>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
+        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
                            a1, ons, A.bonds);
     else
-        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, YS>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
+        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
                            a1, ons, A.bonds);
     CBDG_CHECK_LAUNCH("k_cheb_step");
     return CBDG_OK;
 }
 
-// The strip width is the largest of {W, 2, 1} that divides Lx.
+// Strip width: the shape table's choice, else 2 or 1 so that W divides Lx.
 template <typename T, bool C, bool GEN>
 static int launch_step(StepArgs A, hipStream_t st)
 {
-    constexpr int W = StepShape<T, C>::W;
-    if (A.Lx % W == 0) return launch_step_w<T, C, GEN, W>(A, st);
-    if (W > 2 && A.Lx % 2 == 0) return launch_step_w<T, C, GEN, (W > 2 ? 2 : 1)>(A, st);
-    return launch_step_w<T, C, GEN, 1>(A, st);
+    using SH = StepShape<T, C>;
+    const int64_t n_chunks = ceil_div(A.Bt, kBlock);
+    if (A.Lx % SH::W_BIG == 0 && (A.Lx / SH::W_BIG) * n_chunks * ceil_div(A.Ly, 16) >= 2048)
+        return launch_step_w<T, C, GEN, SH::W_BIG, SH::PF_BIG>(A, st);
+    if (A.Lx % SH::W_SMALL == 0) return launch_step_w<T, C, GEN, SH::W_SMALL, SH::PF_SMALL>(A, st);
+    if (A.Lx % 2 == 0) return launch_step_w<T, C, GEN, 2, false>(A, st);
+    return launch_step_w<T, C, GEN, 1, false>(A, st);
 }
 
 int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st)

@@ -28,15 +28,39 @@ template <typename T, bool C> __device__ __forceinline__ Pair<T, C> zero_pair()
 
 // v with every bit cleared when mask == 0 (mask is 0 or ~0u): zeroes halo
 // values without a branch and independently of their content.
+__device__ __forceinline__ double mask_bits(double v, uint32_t m)
+{
+    const unsigned long long mm = ((unsigned long long)m << 32) | m;
+    return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(v) & mm));
+}
+__device__ __forceinline__ float mask_bits(float v, uint32_t m) { return __uint_as_float(__float_as_uint(v) & m); }
+
+// c ? a : b component by component (a select of whole structs would be
+// lowered through stack memory)
+template <typename T, bool C>
+__device__ __forceinline__ Pair<T, C> select_pair(bool c, const Pair<T, C> &a, const Pair<T, C> &b)
+{
+    Pair<T, C> r;
+    if constexpr (C) {
+        r.er = c ? a.er : b.er; r.ei = c ? a.ei : b.ei;
+        r.hr = c ? a.hr : b.hr; r.hi = c ? a.hi : b.hi;
+    } else {
+        r.e = c ? a.e : b.e; r.h = c ? a.h : b.h;
+    }
+    return r;
+}
+
 template <typename T, bool C>
 __device__ __forceinline__ Pair<T, C> masked(const Pair<T, C> &v, uint32_t mask)
 {
-    constexpr int n = sizeof(Pair<T, C>) / 4;
-    struct Words { uint32_t w[n]; };
-    Words u = __builtin_bit_cast(Words, v);
-#pragma unroll
-    for (int i = 0; i < n; ++i) u.w[i] &= mask;
-    return __builtin_bit_cast(Pair<T, C>, u);
+    Pair<T, C> r;
+    if constexpr (C) {
+        r.er = mask_bits(v.er, mask); r.ei = mask_bits(v.ei, mask);
+        r.hr = mask_bits(v.hr, mask); r.hi = mask_bits(v.hi, mask);
+    } else {
+        r.e = mask_bits(v.e, mask); r.h = mask_bits(v.h, mask);
+    }
+    return r;
 }
 
 template <typename T, bool C>

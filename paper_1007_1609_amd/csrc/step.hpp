@@ -26,6 +26,7 @@ struct StepArgs {
     double *mu_ee;       // tile's first row
     double *mu_he;       // tile's first row (complex interleaved for C)
     int n_strips, n_segs, nblocks;
+    int ys;              // rows per segment
 };
 
 // Lane stride of a tile of B vectors: B rounded up to the wavefront, plus

@@ -208,3 +208,22 @@ def test_fp32_complex_error_is_small():
     e = max(maxdiff(g_ee, o_ee), maxdiff(g_he, o_he))
     print("complex64 recursion, 24x20 N=256: max error %.2e" % e)
     assert e < 2e-5
+
+
+def test_fp32_form_error_vs_oracle_at_full_size():
+    """The FP32 form on the full 256x256 lattice at N = 2048: moments of
+    sampled start sites, their one-step Delta and LDOS against the FP64
+    oracle (reported; bars: Delta 1e-6, LDOS 1e-5 relative to max)."""
+    w = W.config2()
+    sites = np.array([0, 257, 30000, 65535], dtype=np.int32)
+    op, g_ee, g_he = gpu_moments(w, sites=sites, tile=1024, precision=1)
+    a, b = op.bounds.a, op.bounds.b
+    op.close()
+    o_ee, o_he = oracle.workload_moments(w, a, b, sites=sites)
+    E = np.linspace(-1.0, 1.0, 64)
+    d_err = maxdiff(oracle.gap_map(g_he, w.U, a=a, b=b).real, oracle.gap_map(o_he, w.U, a=a, b=b).real)
+    lo = oracle.ldos(o_ee, E, a, b)
+    l_err = maxdiff(oracle.ldos(g_ee, E, a, b), lo) / np.max(np.abs(lo))
+    print("fp32 form 256x256 N=2048: moments err %.2e, Delta err %.2e, LDOS rel err %.2e" % (
+        max(maxdiff(g_ee, o_ee), maxdiff(g_he, o_he)), d_err, l_err))
+    assert d_err < 1e-6 and l_err < 1e-5
