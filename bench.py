@@ -9,10 +9,13 @@ V ~ U[-2, 2], N = 1024 Jackson-damped moments, all 65536 sites in tiles of
   equation with mixing and residual -> LDOS of every site at 64 energies.
 
 Prints one JSON line.  `value` is moments/s (start vectors x N per second)
-with every input resident in HBM.  `roofline` reports the recursion step
-kernel: algorithmic bytes per launch (3 * D * B * 16 B: read a_{n-1}, read
-a_{n-2}, write a_n) over its average launch duration, measured with HIP
-events on the launch stream; `traffic` comes from rocprofv3 counters stored
+with every input resident in HBM.  The moments come from moment doubling
+(N/2 recursion launches per tile, each followed by a small FP64 reduction of
+the dot products) unless --algorithm direct asks for N - 1 launches.
+`roofline` reports the recursion step kernel: algorithmic bytes per launch
+(3 * D * B * 16 B: read a_{n-1}, read a_{n-2}, write a_n) over its average
+launch duration, measured with HIP events on the launch stream (the tile's
+clear, seed and reduction kernels are charged to the step kernel); `traffic` comes from rocprofv3 counters stored
 under profiles/ (null when they were taken on a different kernel source).
 `cpu_baseline` times the CPU oracle on a bounded sample of start vectors.
 """
@@ -111,6 +114,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--algorithm", choices=["auto", "direct", "doubling"], default="auto")
     ap.add_argument("--tiles", type=int, default=0, help="limit the number of tiles (0: whole lattice)")
     ap.add_argument("--cpu-sites", type=int, default=0, help="oracle sample size (0: sized to about 15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -156,7 +160,10 @@ def main():
     a, b = op.bounds.a, op.bounds.b
     wts = op.weights()
     sites = torch.arange(n_sites, dtype=torch.int32, device=dev)
-    ws = P.workspace(P.moments_workspace_bytes(op, tile, prec), dev)
+    alg = {"auto": P.CBDG_ALG_AUTO, "direct": P.CBDG_ALG_DIRECT, "doubling": P.CBDG_ALG_DOUBLING}[args.algorithm]
+    doubling = alg == P.CBDG_ALG_DOUBLING or (alg == P.CBDG_ALG_AUTO and b == 0.0 and N >= 3)
+    steps_per_tile = N // 2 if doubling else N - 1
+    ws = P.workspace(P.moments_workspace_bytes(op, tile, prec, alg), dev)
     mu_ee = torch.empty((n_sites, N), dtype=torch.float64, device=dev)
     mu_he = torch.empty((n_sites, N), dtype=torch.float64, device=dev)
     full = n_sites == w.L2
@@ -178,7 +185,8 @@ def main():
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            P.chebyshev_moments(op, sites[lo:hi], N, tile, prec, ws=ws, out=(mu_ee[lo:hi], mu_he[lo:hi]))
+            P.chebyshev_moments(op, sites[lo:hi], N, tile, prec, ws=ws, out=(mu_ee[lo:hi], mu_he[lo:hi]),
+                                algorithm=alg)
             if record:
                 e1.record(stream)
                 tile_events.append((e0, e1, hi - lo))
@@ -208,17 +216,18 @@ def main():
     moments_per_step = n_sites * N
     value = moments_per_step * args.steps / (ms_total / 1e3)
 
-    # dominant kernel: the recursion step; one tile call = N-1 step launches
-    # (plus a buffer clear and a seed kernel, counted against the step kernel)
+    # dominant kernel: the recursion step; one tile call = steps_per_tile step
+    # launches (plus a buffer clear, a seed kernel and, with doubling, one
+    # reduction per step, all counted against the step kernel)
     launches = 0
     kern_ms = 0.0
     alg_bytes = 0.0
     D = 2 * w.L2
     for e0, e1, bt in tile_events:
         kern_ms += e0.elapsed_time(e1)
-        launches += N - 1
+        launches += steps_per_tile
         bp = (bt + 63) // 64 * 64
-        alg_bytes += (N - 1) * 3.0 * D * bp * s_bytes
+        alg_bytes += steps_per_tile * 3.0 * D * bp * s_bytes
     avg_launch_ms = kern_ms / launches
     bytes_per_launch = alg_bytes / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
@@ -245,6 +254,7 @@ def main():
                         % (w.name, N, n_sites, tile, ),
             "lattice": [w.Lx, w.Ly], "N": N, "start_sites": n_sites, "tile": tile,
             "precision": args.precision, "bounds_a": a,
+            "algorithm": "doubling" if doubling else "direct", "recursion_launches_per_tile": steps_per_tile,
         },
         "roofline": {
             "kernel": "k_cheb_step<%s>" % ("double" if s_bytes == 8 else "float"),
@@ -264,7 +274,7 @@ def main():
     log("timed steps done: %.1f ms/step, %.3g moments/s, %.0f GB/s" % (ms_per_step, value, achieved))
     if args.precision == "fp32":
         import bench_forms
-        line["accuracy"] = bench_forms.fp32_accuracy(w, op, mu_ee, mu_he, energies, dev)
+        line["accuracy"] = bench_forms.fp32_accuracy(w, op, mu_ee, mu_he, energies, dev, algorithm=alg)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
         line["cpu_baseline"] = cpu_baseline(w, a, b, args.cpu_sites, threads)

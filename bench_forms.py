@@ -42,14 +42,14 @@ def _timed(fn):
     return out, e0.elapsed_time(e1) / 1e3
 
 
-def fp32_accuracy(w, op, mu_ee32, mu_he32, energies, dev, n_rows=2048):
+def fp32_accuracy(w, op, mu_ee32, mu_he32, energies, dev, n_rows=2048, algorithm=0):
     """FP32-recursion results vs the FP64 recursion for the first n_rows
-    start sites at the initial Delta."""
+    start sites at the initial Delta (both with the same moment algorithm)."""
     d0 = torch.as_tensor(w.delta, device=dev)
     op.update_delta(d0)
     sites = torch.arange(n_rows, dtype=torch.int32, device=dev)
-    m32 = P.chebyshev_moments(op, sites, w.N, w.tile, P.CBDG_FP32_ACC64)
-    m64 = P.chebyshev_moments(op, sites, w.N, w.tile, P.CBDG_FP64)
+    m32 = P.chebyshev_moments(op, sites, w.N, w.tile, P.CBDG_FP32_ACC64, algorithm=algorithm)
+    m64 = P.chebyshev_moments(op, sites, w.N, w.tile, P.CBDG_FP64, algorithm=algorithm)
     wt = op.weights()
     d32, _ = P.gap_update(m32[1], wt, w.U, d0[:n_rows].contiguous())
     d64, _ = P.gap_update(m64[1], wt, w.U, d0[:n_rows].contiguous())
@@ -65,7 +65,15 @@ def fp32_accuracy(w, op, mu_ee32, mu_he32, energies, dev, n_rows=2048):
             "bars": {"delta": 1e-6, "ldos_rel": 1e-5}}
 
 
-def _moments_pass(op, sites, N, tile, prec, ws, out):
+def _algorithm(args, op, N):
+    """(ABI algorithm, recursion launches per tile) for --algorithm."""
+    alg = {"auto": P.CBDG_ALG_AUTO, "direct": P.CBDG_ALG_DIRECT,
+           "doubling": P.CBDG_ALG_DOUBLING}[getattr(args, "algorithm", "auto")]
+    dbl = alg == P.CBDG_ALG_DOUBLING or (alg == P.CBDG_ALG_AUTO and op.bounds.b == 0.0 and N >= 3)
+    return alg, (N // 2 if dbl else N - 1)
+
+
+def _moments_pass(op, sites, N, tile, prec, ws, out, alg=0):
     """All tiles, one call per tile with HIP events; returns per-launch us."""
     stream = torch.cuda.current_stream()
     n = sites.numel()
@@ -74,7 +82,8 @@ def _moments_pass(op, sites, N, tile, prec, ws, out):
         t1 = min(n, t0 + tile)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        P.chebyshev_moments(op, sites[t0:t1], N, tile, prec, ws=ws, out=(out[0][t0:t1], out[1][t0:t1]))
+        P.chebyshev_moments(op, sites[t0:t1], N, tile, prec, ws=ws, out=(out[0][t0:t1], out[1][t0:t1]),
+                            algorithm=alg)
         e1.record(stream)
         ev.append((e0, e1, t1 - t0))
     torch.cuda.synchronize()
@@ -92,19 +101,20 @@ def complex_form(args, dev):
     wt = op.weights()
     res = {}
     ldos = {}
+    alg, steps = _algorithm(args, op, N)
     for name, prec, s_bytes in (("complex128", P.CBDG_FP64, 8), ("complex64", P.CBDG_FP32_ACC64, 4)):
-        ws = P.workspace(P.moments_workspace_bytes(op, tile, prec), dev)
+        ws = P.workspace(P.moments_workspace_bytes(op, tile, prec, alg), dev)
         out = (torch.empty((n, N), dtype=torch.float64, device=dev),
                torch.empty((n, N), dtype=torch.complex128, device=dev))
         # warm-up on one tile, then the timed pass over all 4 tiles
-        P.chebyshev_moments(op, sites[:64], N, 64, prec, ws=ws)
+        P.chebyshev_moments(op, sites[:64], N, 64, prec, ws=ws, algorithm=alg)
         torch.cuda.synchronize()
-        t, ev = _moments_pass(op, sites, N, tile, prec, ws, out)
+        t, ev = _moments_pass(op, sites, N, tile, prec, ws, out, alg)
         ld, t_ldos = _timed(lambda: P.ldos(out[0], wt, E))
         ldos[name] = ld
-        launches = sum(N - 1 for _ in ev)
-        alg = sum((N - 1) * 3.0 * w.D * 2 * s_bytes * ((bt + 63) // 64 * 64) for _, _, bt in ev)
-        gbs = alg / t / 1e9
+        launches = steps * len(ev)
+        nbytes = sum(steps * 3.0 * w.D * 2 * s_bytes * ((bt + 63) // 64 * 64) for _, _, bt in ev)
+        gbs = nbytes / t / 1e9
         res[name] = {"moments_per_s": n * N / (t + t_ldos), "seconds_moments": t, "seconds_ldos": t_ldos,
                      "avg_launch_us": t / launches * 1e6, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
                      "moments_bounded": bool(P.check_moments(out[0], out[1], 1e-9 if s_bytes == 8 else 1e-4))}
@@ -118,7 +128,8 @@ def complex_form(args, dev):
             "data": "synthetic",
             "config": {"workload": "%s: 512x512 open lattice, Peierls flux 1/256 per plaquette, d-wave bond "
                                    "pairing with four phase windings, N=%d, 4096 start sites (stride-8 grid) "
-                                   "in tiles of %d, LDOS at 512 energies" % (w.name, N, tile)},
+                                   "in tiles of %d, LDOS at 512 energies" % (w.name, N, tile),
+                       "recursion_launches_per_tile": steps},
             "forms": res, "complex64_ldos_err_rel_to_max": err,
             "roofline": {"kernel": "k_cheb_step<complex double>", "bound": "hbm",
                          "achieved": res["complex128"]["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -66,6 +66,19 @@ enum cbdg_bc { CBDG_BC_OPEN = 0, CBDG_BC_PERIODIC = 1 };
 enum cbdg_scalar { CBDG_REAL = 0, CBDG_COMPLEX = 1 };
 enum cbdg_precision { CBDG_FP64 = 0, CBDG_FP32_ACC64 = 1 };
 enum cbdg_kernel { CBDG_KERNEL_JACKSON = 0, CBDG_KERNEL_LORENTZ = 1 };
+/* How cbdg_chebyshev_moments gets moments 2..N-1 (both give the same moments
+ * up to rounding):
+ *   DIRECT    N - 1 recursion steps, moment n read off a_n at the start site.
+ *   DOUBLING  ceil((N-1)/2) steps: the product rule of Chebyshev polynomials,
+ *             2 T_m T_n = T_{m+n} + T_{|m-n|} (the Chebyshev expansion of
+ *             section II), with the particle-hole symmetry of the BdG
+ *             operator gives mu_ee[2n] = 2<a_n|a_n> - mu_ee[0],
+ *             mu_ee[2n-1] = 2 Re<a_n|a_{n-1}> - mu_ee[1],
+ *             mu_he[2n-1] = 2 (-1)^n sum_i (u_n(i) v_{n-1}(i) - v_n(i) u_{n-1}(i)) - mu_he[1],
+ *             mu_he[2n] = 0, where a = (u, v) on the (e, h) components.
+ *             Needs b == 0 (a spectrum centred by the rescaling).
+ *   AUTO      DOUBLING when b == 0 and N >= 3, else DIRECT. */
+enum cbdg_algorithm { CBDG_ALG_AUTO = 0, CBDG_ALG_DIRECT = 1, CBDG_ALG_DOUBLING = 2 };
 
 /* Lattice geometry and number type (host struct).
  * Periodic directions need at least 3 sites. */
@@ -150,9 +163,10 @@ int cbdg_op_destroy(cbdg_op *op);
 int cbdg_op_bounds(const cbdg_op *op, cbdg_bounds *out);
 
 /* Bytes of workspace cbdg_chebyshev_moments needs for tiles of `tile` start
- * vectors at `precision` (host out). */
+ * vectors at `precision` with `algorithm` (host out): two vector buffers,
+ * plus FP64 partial sums for DOUBLING.  EINVAL for DOUBLING when b != 0. */
 int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision,
-                                size_t *bytes);
+                                int32_t algorithm, size_t *bytes);
 
 /*
  * Chebyshev moments of eqs. (coeff1)/(coeff2) through the vector recursion
@@ -166,13 +180,15 @@ int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precisi
  *   tile         start vectors per tile, >= 1
  *   precision    CBDG_FP64, or CBDG_FP32_ACC64: recursion vectors and
  *                coefficients in FP32 (complex64 for COMPLEX), moments
- *                widened exactly to FP64
- *   workspace    >= cbdg_moments_workspace_size(op, tile, precision) bytes
+ *                widened exactly to FP64 (doubling sums in FP64)
+ *   algorithm    enum cbdg_algorithm; DOUBLING with b != 0 is EINVAL
+ *   workspace    >= cbdg_moments_workspace_size(op, tile, precision,
+ *                algorithm) bytes
  *   mu_ee        out [n_start*N] FP64
  *   mu_he        out [n_start*N] FP64 (REAL) or complex128 (COMPLEX)
  */
 int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
-                           int32_t N, int32_t tile, int32_t precision,
+                           int32_t N, int32_t tile, int32_t precision, int32_t algorithm,
                            void *workspace, size_t workspace_bytes,
                            double *mu_ee, void *mu_he, void *stream);
 

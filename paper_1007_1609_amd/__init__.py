@@ -9,7 +9,8 @@ ImportError when it has not been built.
 """
 from . import _lib
 from ._lib import (CbdgError, CBDG_FP64, CBDG_FP32_ACC64, CBDG_REAL, CBDG_COMPLEX,
-                   CBDG_BC_OPEN, CBDG_BC_PERIODIC)
+                   CBDG_BC_OPEN, CBDG_BC_PERIODIC, CBDG_ALG_AUTO, CBDG_ALG_DIRECT,
+                   CBDG_ALG_DOUBLING)
 
 _lib.load()
 
@@ -20,7 +21,7 @@ from .api import (Operator, Bounds, weights, chebyshev_moments, check_moments,  
 
 __all__ = [
     "CbdgError", "CBDG_FP64", "CBDG_FP32_ACC64", "CBDG_REAL", "CBDG_COMPLEX", "CBDG_BC_OPEN",
-    "CBDG_BC_PERIODIC", "Operator", "Bounds", "weights", "chebyshev_moments", "check_moments",
+    "CBDG_BC_PERIODIC", "CBDG_ALG_AUTO", "CBDG_ALG_DIRECT", "CBDG_ALG_DOUBLING", "Operator", "Bounds", "weights", "chebyshev_moments", "check_moments",
     "gap_update", "ldos", "gap_update_backward", "ldos_backward", "chebyshev_moments_backward",
     "moments_workspace_bytes", "backward_workspace_bytes", "workspace",
 ]

@@ -22,6 +22,7 @@ CBDG_BC_OPEN, CBDG_BC_PERIODIC = 0, 1
 CBDG_REAL, CBDG_COMPLEX = 0, 1
 CBDG_FP64, CBDG_FP32_ACC64 = 0, 1
 CBDG_KERNEL_JACKSON, CBDG_KERNEL_LORENTZ = 0, 1
+CBDG_ALG_AUTO, CBDG_ALG_DIRECT, CBDG_ALG_DOUBLING = 0, 1, 2
 
 _NAMES = {CBDG_EINVAL: "EINVAL", CBDG_ENOMEM: "ENOMEM", CBDG_EHIP: "EHIP",
           CBDG_EBOUNDS: "EBOUNDS", CBDG_EUNSUPPORTED: "EUNSUPPORTED"}
@@ -58,8 +59,8 @@ SIGNATURES = {
     "cbdg_op_update_delta": [_vp, _vp, _vp, _vp],
     "cbdg_op_destroy": [_vp],
     "cbdg_op_bounds": [_vp, C.POINTER(cbdg_bounds)],
-    "cbdg_moments_workspace_size": [_vp, _i32, _i32, C.POINTER(_sz)],
-    "cbdg_chebyshev_moments": [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp],
+    "cbdg_moments_workspace_size": [_vp, _i32, _i32, _i32, C.POINTER(_sz)],
+    "cbdg_chebyshev_moments": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp],
     "cbdg_check_moments": [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _vp],
     "cbdg_gap_update": [_vp, _i64, _i32, _i32, C.POINTER(cbdg_weights), _f64, _vp, _vp,
                         _f64, _vp, _vp, _vp],

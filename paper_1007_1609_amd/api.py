@@ -115,9 +115,10 @@ class Operator:
             pass
 
 
-def moments_workspace_bytes(op: Operator, tile: int, precision: int = L.CBDG_FP64) -> int:
+def moments_workspace_bytes(op: Operator, tile: int, precision: int = L.CBDG_FP64,
+                            algorithm: int = L.CBDG_ALG_AUTO) -> int:
     n = C.c_size_t()
-    L.cbdg_moments_workspace_size(op.handle, int(tile), int(precision), C.byref(n))
+    L.cbdg_moments_workspace_size(op.handle, int(tile), int(precision), int(algorithm), C.byref(n))
     return n.value
 
 
@@ -127,11 +128,12 @@ def workspace(nbytes: int, device="cuda") -> torch.Tensor:
 
 def chebyshev_moments(op: Operator, sites: torch.Tensor, N: int, tile: int,
                       precision: int = L.CBDG_FP64, ws: Optional[torch.Tensor] = None,
-                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None):
+                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                      algorithm: int = L.CBDG_ALG_AUTO):
     """mu_ee [n, N] float64 and mu_he [n, N] (float64 or complex128)."""
     n = int(sites.numel())
     eff = max(1, min(int(tile), n))
-    need = moments_workspace_bytes(op, eff, precision)
+    need = moments_workspace_bytes(op, eff, precision, algorithm)
     if ws is None or ws.numel() < need:
         ws = workspace(need, sites.device)
     if out is None:
@@ -141,7 +143,7 @@ def chebyshev_moments(op: Operator, sites: torch.Tensor, N: int, tile: int,
     else:
         mu_ee, mu_he = out
     L.cbdg_chebyshev_moments(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N), int(tile),
-                             int(precision), _ptr(ws, None, "workspace"), ws.numel(),
+                             int(precision), int(algorithm), _ptr(ws, None, "workspace"), ws.numel(),
                              _ptr(mu_ee, torch.float64, "mu_ee"), _ptr(mu_he, None, "mu_he"),
                              _stream())
     return mu_ee, mu_he

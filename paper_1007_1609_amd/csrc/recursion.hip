@@ -45,7 +45,7 @@ namespace cbdg {
 #endif
 
 
-template <typename T, bool C, bool GEN, bool FIRST, int W, bool PF>
+template <typename T, bool C, bool GEN, bool FIRST, int W, bool PF, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
     StepArgs A, const typename Storage<T, C>::type *__restrict__ a1,
     const OnSite<T> *__restrict__ ons, const void *__restrict__ bonds)
@@ -126,6 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     [[maybe_unused]] P pn[PF ? W : 1];
     P mval = zero_pair<T, C>();
     bool found = false;
+    // moment doubling: per-lane partial sums over this block's sites of
+    // <a_n|a_n>, Re<a_n|a_{n-1}> and the bilinear form
+    // B(a_n, a_{n-1}) = sum_i u_n(i) v_{n-1}(i) - v_n(i) u_{n-1}(i), in FP64
+    double d_nn = 0.0, d_nm = 0.0, d_br = 0.0, d_bi = 0.0;
     apply_mask(up, load_row(up, y0 - 1));
     apply_mask(cur, load_row(cur, y0));
     apply_mask(dn, load_row(dn, y0 + 1));
@@ -157,6 +161,22 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
             const bool hit = s == my_site;
             found = found || hit;
             mval = select_pair<T, C>(hit, ov, mval);
+            if constexpr (DOT) {
+                const P &c = cur[k + 1];
+                if constexpr (C) {
+                    const double er = ov.er, ei = ov.ei, hr = ov.hr, hi = ov.hi;
+                    const double cer = c.er, cei = c.ei, chr = c.hr, chi = c.hi;
+                    d_nn += (er * er + ei * ei) + (hr * hr + hi * hi);
+                    d_nm += (er * cer + ei * cei) + (hr * chr + hi * chi);
+                    d_br += (er * chr - ei * chi) - (hr * cer - hi * cei);
+                    d_bi += (er * chi + ei * chr) - (hr * cei + hi * cer);
+                } else {
+                    const double e = ov.e, h = ov.h, ce = c.e, ch = c.h;
+                    d_nn += e * e + h * h;
+                    d_nm += e * ce + h * ch;
+                    d_br += e * ch - h * ce;
+                }
+            }
         }
     };
     // one row per trip: unrolling would duplicate the register window
@@ -179,6 +199,15 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     if constexpr (!FIRST && !PF) load_prev2(pc, y1 - 1);
     compute_row(y1 - 1);
 
+    if constexpr (DOT) {
+        constexpr int K = C ? 4 : 3;
+        const int64_t region = strip + (int64_t)A.n_strips * seg;
+        double *pp = A.part + region * K * Bp + b;
+        pp[0] = d_nn;
+        pp[Bp] = d_nm;
+        pp[2 * Bp] = d_br;
+        if constexpr (C) pp[3 * Bp] = d_bi;
+    }
     if (found && A.mu_ee) {
         const int64_t m = (int64_t)b * A.N + A.n;
         if constexpr (C) {
@@ -269,39 +298,172 @@ static int segment_rows(int Ly, int64_t other_blocks, int ys_max)
     return ys;
 }
 
+struct Shape {
+    int W;
+    bool PF;
+    int ys, n_strips, n_segs;
+};
+
+// Strip width from the shape table (else 2 or 1 so that W divides Lx), then
+// the row-segment length for that width.
+template <typename T, bool C>
+static Shape choose_shape(int Lx, int Ly, int64_t n_chunks)
+{
+    using SH = StepShape<T, C>;
+    Shape sh;
+    if (Lx % SH::W_BIG == 0 && (Lx / SH::W_BIG) * n_chunks * ceil_div(Ly, 16) >= 2048) {
+        sh.W = SH::W_BIG; sh.PF = SH::PF_BIG;
+    } else if (Lx % SH::W_SMALL == 0) {
+        sh.W = SH::W_SMALL; sh.PF = SH::PF_SMALL;
+    } else {
+        sh.W = (Lx % 2 == 0) ? 2 : 1; sh.PF = false;
+    }
+    sh.n_strips = Lx / sh.W;
+    sh.ys = segment_rows(Ly, (int64_t)sh.n_strips * n_chunks, SH::YS);
+    sh.n_segs = (int)ceil_div(Ly, sh.ys);
+    return sh;
+}
+
+// Largest number of (strip, segment) regions any tile of up to `tile`
+// vectors launches with: the size of the moment-doubling partials.
+template <typename T, bool C>
+static int64_t max_regions(int Lx, int Ly, int tile)
+{
+    int64_t r = 0;
+    for (int64_t c = 1; c <= ceil_div(tile, kBlock); ++c) {
+        const Shape sh = choose_shape<T, C>(Lx, Ly, c);
+        r = std::max<int64_t>(r, (int64_t)sh.n_strips * sh.n_segs);
+    }
+    return r;
+}
+
 template <typename T, bool C, bool GEN, int W, bool PF>
 static int launch_step_w(StepArgs A, hipStream_t st)
 {
-    A.n_strips = A.Lx / W;
     const int n_chunks = (int)ceil_div(A.Bt, kBlock);
-    A.ys = segment_rows(A.Ly, (int64_t)A.n_strips * n_chunks, StepShape<T, C>::YS);
-    A.n_segs = (int)ceil_div(A.Ly, A.ys);
     const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
     A.nblocks = (int)nb;
     const auto *a1 = reinterpret_cast<const typename Storage<T, C>::type *>(A.prev1);
     const auto *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
-    if (A.first)
-        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
-                           a1, ons, A.bonds);
-    else
-        hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
-                           a1, ons, A.bonds);
+    const dim3 g(A.nblocks), bl(kBlock);
+    if (A.part) {
+        if (A.first) hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF, true>), g, bl, 0, st, A, a1, ons, A.bonds);
+        else hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF, true>), g, bl, 0, st, A, a1, ons, A.bonds);
+    } else {
+        if (A.first) hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF, false>), g, bl, 0, st, A, a1, ons, A.bonds);
+        else hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF, false>), g, bl, 0, st, A, a1, ons, A.bonds);
+    }
     CBDG_CHECK_LAUNCH("k_cheb_step");
     return CBDG_OK;
 }
 
-// Strip width: the shape table's choice, else 2 or 1 so that W divides Lx.
 template <typename T, bool C, bool GEN>
 static int launch_step(StepArgs A, hipStream_t st)
 {
     using SH = StepShape<T, C>;
-    const int64_t n_chunks = ceil_div(A.Bt, kBlock);
-    if (A.Lx % SH::W_BIG == 0 && (A.Lx / SH::W_BIG) * n_chunks * ceil_div(A.Ly, 16) >= 2048)
-        return launch_step_w<T, C, GEN, SH::W_BIG, SH::PF_BIG>(A, st);
-    if (A.Lx % SH::W_SMALL == 0) return launch_step_w<T, C, GEN, SH::W_SMALL, SH::PF_SMALL>(A, st);
-    if (A.Lx % 2 == 0) return launch_step_w<T, C, GEN, 2, false>(A, st);
+    const Shape sh = choose_shape<T, C>(A.Lx, A.Ly, ceil_div(A.Bt, kBlock));
+    A.n_strips = sh.n_strips;
+    A.ys = sh.ys;
+    A.n_segs = sh.n_segs;
+    if (sh.W == SH::W_BIG && sh.PF == SH::PF_BIG) return launch_step_w<T, C, GEN, SH::W_BIG, SH::PF_BIG>(A, st);
+    if (sh.W == SH::W_SMALL && sh.PF == SH::PF_SMALL) return launch_step_w<T, C, GEN, SH::W_SMALL, SH::PF_SMALL>(A, st);
+    if (sh.W == 2) return launch_step_w<T, C, GEN, 2, false>(A, st);
     return launch_step_w<T, C, GEN, 1, false>(A, st);
+}
+
+// Moments 2n-1 and 2n of every vector from the partial sums of step n:
+//   mu_ee[2n]   = 2 <a_n|a_n> - mu_ee[0]
+//   mu_ee[2n-1] = 2 Re<a_n|a_{n-1}> - mu_ee[1]
+//   mu_he[2n-1] = 2 (-1)^n B(a_n, a_{n-1}) - mu_he[1]
+//   mu_he[2n]   = 0
+// (C(u,v) = (-v*, u*) anticommutes with Ht when b = 0, so T_m(Ht) C =
+// (-1)^m C T_m(Ht), and the hole start vector is C applied to the electron
+// one.)  The per-region partials are summed in two passes, both in a fixed
+// order so that the bits do not depend on scheduling: k_doubling_groups adds
+// runs of consecutive regions (one thread per vector and run, enough
+// workgroups to spread over the GPU), then k_doubling_reduce adds the runs
+// (one workgroup per 64 vectors; wave w takes runs w, w + 16, ..., wave 0
+// adds the 16 wave sums in order) and writes the moments.  Rows of invalid
+// start sites keep their NaN.
+constexpr int kRedWaves = 16;
+constexpr int kMaxGroups = 256;
+
+// Regions per run and number of runs for R regions (at most kMaxGroups runs).
+static inline void doubling_groups(int64_t R, int64_t *per, int64_t *groups)
+{
+    *per = std::max<int64_t>(4, ceil_div(R, kMaxGroups));
+    *groups = ceil_div(R, *per);
+}
+
+template <bool C>
+__global__ __launch_bounds__(kBlock) void k_doubling_groups(
+    const double *__restrict__ part, int64_t regions, int64_t per, int64_t Bp, int Bt,
+    double *__restrict__ out)
+{
+    constexpr int K = C ? 4 : 3;
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= Bt) return;
+    const int64_t g = blockIdx.y;
+    const int64_t r0 = g * per, r1 = std::min<int64_t>(regions, r0 + per);
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double *pp = part + r * K * Bp + b;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += pp[k * Bp];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[(g * K + k) * Bp + b] = acc[k];
+}
+
+template <bool C>
+__global__ __launch_bounds__(kRedWaves * kWave) void k_doubling_reduce(
+    const double *__restrict__ part, int64_t regions, int64_t Bp, int Bt, int n, int N,
+    double *__restrict__ mu_ee, double *__restrict__ mu_he)
+{
+    constexpr int K = C ? 4 : 3;
+    __shared__ double red[kRedWaves][K][kWave];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int b = blockIdx.x * kWave + lane;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    if (b < Bt) {
+#pragma unroll 2
+        for (int64_t r = wv; r < regions; r += kRedWaves) {
+            const double *pp = part + r * K * Bp + b;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += pp[k * Bp];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[wv][k][lane] = acc[k];
+    __syncthreads();
+    if (wv != 0 || b >= Bt) return;
+#pragma unroll 1
+    for (int w = 1; w < kRedWaves; ++w) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += red[w][k][lane];
+    }
+    const int64_t m = (int64_t)b * N;
+    if (!(mu_ee[m] == mu_ee[m])) return;
+    const double sgn = (n & 1) ? -2.0 : 2.0;
+    if (2 * n < N) {
+        mu_ee[m + 2 * n] = 2.0 * acc[0] - mu_ee[m];
+        if constexpr (C) { mu_he[2 * (m + 2 * n)] = 0.0; mu_he[2 * (m + 2 * n) + 1] = 0.0; }
+        else mu_he[m + 2 * n] = 0.0;
+    }
+    if (n >= 2 && 2 * n - 1 < N) {
+        mu_ee[m + 2 * n - 1] = 2.0 * acc[1] - mu_ee[m + 1];
+        if constexpr (C) {
+            mu_he[2 * (m + 2 * n - 1)] = sgn * acc[2] - mu_he[2 * (m + 1)];
+            mu_he[2 * (m + 2 * n - 1) + 1] = sgn * acc[3] - mu_he[2 * (m + 1) + 1];
+        } else {
+            mu_he[m + 2 * n - 1] = sgn * acc[2] - mu_he[m + 1];
+        }
+    }
 }
 
 int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st)
@@ -333,15 +495,22 @@ int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, doubl
     return CBDG_OK;
 }
 
+// Direct: steps n = 1 .. N-1, each capturing moment n of every vector.
+// Doubling: steps n = 1 .. ceil((N-1)/2); step 1 captures moment 1 and every
+// step's partial sums give moments 2n-1 and 2n.  The partials sit after the
+// two vector buffers in the workspace.
 template <typename T, bool C>
 static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start, int N, int tile,
-                       void *ws, double *mu_ee, double *mu_he, hipStream_t st)
+                       bool doubling, void *ws, double *mu_ee, double *mu_he, hipStream_t st)
 {
     using S = typename Storage<T, C>::type;
     const int64_t L2 = op->L2;
     const int64_t Bp_max = lane_stride(tile);
     S *bufA = reinterpret_cast<S *>(ws);
     S *bufB = bufA + L2 * Bp_max;
+    // doubling partials: [regions][K][Bp], then [runs][K][Bp]
+    double *part = reinterpret_cast<double *>(bufB + L2 * Bp_max);
+    double *part2 = part + (doubling ? max_regions<T, C>(op->Lx, op->Ly, tile) * (C ? 4 : 3) * Bp_max : 0);
     const void *onsite = std::is_same<T, double>::value ? (const void *)op->onsite64 : (const void *)op->onsite32;
     const void *bonds = std::is_same<T, double>::value ? op->bonds64 : op->bonds32;
     const int he_mult = C ? 2 : 1;
@@ -366,14 +535,29 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         A.Bp = (int)Bp; A.Bt = Bt; A.N = N;
         A.sites = ts; A.mu_ee = mee; A.mu_he = mhe;
         S *buf[2] = {bufA, bufB};
-        for (int n = 1; n < N; ++n) {
+        const int n_steps = doubling ? N / 2 : N - 1;
+        const Shape sh = choose_shape<T, C>(op->Lx, op->Ly, ceil_div(Bt, kBlock));
+        const int64_t regions = (int64_t)sh.n_strips * sh.n_segs;
+        int64_t per = 0, groups = 0;
+        doubling_groups(regions, &per, &groups);
+        for (int n = 1; n <= n_steps; ++n) {
             A.first = n == 1;
             A.n = n;
             A.prev1 = buf[(n - 1) & 1];
             A.prev2 = buf[n & 1];
             A.out = buf[n & 1];
+            A.part = doubling ? part : nullptr;
+            A.mu_ee = (!doubling || n == 1) ? mee : nullptr;
             int rc = op->general ? launch_step<T, C, true>(A, st) : launch_step<T, C, false>(A, st);
             if (rc) return rc;
+            if (doubling) {
+                hipLaunchKernelGGL((k_doubling_groups<C>), dim3((unsigned)ceil_div(Bt, kBlock), (unsigned)groups),
+                                   dim3(kBlock), 0, st, part, regions, per, Bp, Bt, part2);
+                CBDG_CHECK_LAUNCH("k_doubling_groups");
+                hipLaunchKernelGGL((k_doubling_reduce<C>), dim3((unsigned)ceil_div(Bt, kWave)),
+                                   dim3(kRedWaves * kWave), 0, st, part2, groups, Bp, Bt, n, N, mee, mhe);
+                CBDG_CHECK_LAUNCH("k_doubling_reduce");
+            }
         }
     }
     return CBDG_OK;
@@ -406,7 +590,34 @@ __global__ void k_check(const double *mu_ee, const double *mu_he, int64_t n, int
 
 using namespace cbdg;
 
-extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision,
+// Resolves CBDG_ALG_AUTO; fails for doubling with b != 0 (the particle-hole
+// partner of a_n is then no longer (-1)^n-related to it).
+static int resolve_algorithm(const cbdg_op *op, int32_t algorithm, int32_t N, const char *who, bool *doubling)
+{
+    const bool centred = op->bounds.b == 0.0;
+    switch (algorithm) {
+    case CBDG_ALG_AUTO: *doubling = centred && N >= 3; return CBDG_OK;
+    case CBDG_ALG_DIRECT: *doubling = false; return CBDG_OK;
+    case CBDG_ALG_DOUBLING:
+        if (!centred) return fail(CBDG_EINVAL, "%s: moment doubling needs a spectrum centred at b = 0 (b = %g)", who, op->bounds.b);
+        *doubling = N >= 3;
+        return CBDG_OK;
+    default: return fail(CBDG_EINVAL, "%s: unknown algorithm %d", who, algorithm);
+    }
+}
+
+static int64_t doubling_partial_bytes(const cbdg_op *op, int tile, int precision)
+{
+    const bool cplx = op->scalar == CBDG_COMPLEX;
+    const int K = cplx ? 4 : 3;
+    int64_t R;
+    if (precision == CBDG_FP64) R = cplx ? max_regions<double, true>(op->Lx, op->Ly, tile) : max_regions<double, false>(op->Lx, op->Ly, tile);
+    else R = cplx ? max_regions<float, true>(op->Lx, op->Ly, tile) : max_regions<float, false>(op->Lx, op->Ly, tile);
+    const int64_t G = std::min<int64_t>(kMaxGroups, ceil_div(R, 4));
+    return (R + G) * K * lane_stride(tile) * (int64_t)sizeof(double);
+}
+
+extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision, int32_t algorithm,
                                            size_t *bytes)
 {
     clear_error();
@@ -414,13 +625,19 @@ extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int3
     if (tile < 1) return fail(CBDG_EINVAL, "moments_workspace_size: tile must be >= 1");
     if (precision != CBDG_FP64 && precision != CBDG_FP32_ACC64)
         return fail(CBDG_EINVAL, "moments_workspace_size: unknown precision %d", precision);
+    bool doubling = false;
+    // sized for any N: the partials are included whenever doubling may run
+    int rc = resolve_algorithm(op, algorithm, 3, "moments_workspace_size", &doubling);
+    if (rc) return rc;
     *bytes = 2 * (size_t)op->L2 * (size_t)lane_stride(tile) * pair_bytes(op->scalar, precision);
+    if (doubling) *bytes += (size_t)doubling_partial_bytes(op, tile, precision);
     return CBDG_OK;
 }
 
 extern "C" int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
-                                      int32_t N, int32_t tile, int32_t precision, void *workspace,
-                                      size_t workspace_bytes, double *mu_ee, void *mu_he, void *stream)
+                                      int32_t N, int32_t tile, int32_t precision, int32_t algorithm,
+                                      void *workspace, size_t workspace_bytes, double *mu_ee, void *mu_he,
+                                      void *stream)
 {
     clear_error();
     if (!op) return fail(CBDG_EINVAL, "chebyshev_moments: op must not be NULL");
@@ -429,24 +646,27 @@ extern "C" int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_si
     if (tile < 1) return fail(CBDG_EINVAL, "chebyshev_moments: tile must be >= 1");
     if (precision != CBDG_FP64 && precision != CBDG_FP32_ACC64)
         return fail(CBDG_EINVAL, "chebyshev_moments: unknown precision %d", precision);
+    bool doubling = false;
+    int rc = resolve_algorithm(op, algorithm, N, "chebyshev_moments", &doubling);
+    if (rc) return rc;
     if (n_start == 0) return CBDG_OK;
     if (!start_sites || !mu_ee || !mu_he || !workspace)
         return fail(CBDG_EINVAL, "chebyshev_moments: start_sites, mu_ee, mu_he and workspace must not be NULL");
     const int64_t eff_tile = std::min<int64_t>(tile, n_start);
-    size_t need = 0;
-    int rc = cbdg_moments_workspace_size(op, (int32_t)eff_tile, precision, &need);
-    if (rc) return rc;
+    size_t need = 2 * (size_t)op->L2 * (size_t)lane_stride(eff_tile) * pair_bytes(op->scalar, precision);
+    if (doubling) need += (size_t)doubling_partial_bytes(op, (int)eff_tile, precision);
     if (workspace_bytes < need)
         return fail(CBDG_EINVAL, "chebyshev_moments: workspace of %zu bytes is smaller than the %zu needed",
                     workspace_bytes, need);
     hipStream_t st = as_stream(stream);
     double *mhe = reinterpret_cast<double *>(mu_he);
     const bool cplx = op->scalar == CBDG_COMPLEX;
+    const int et = (int)eff_tile;
     if (precision == CBDG_FP64)
-        return cplx ? run_moments<double, true>(op, start_sites, n_start, N, (int)eff_tile, workspace, mu_ee, mhe, st)
-                    : run_moments<double, false>(op, start_sites, n_start, N, (int)eff_tile, workspace, mu_ee, mhe, st);
-    return cplx ? run_moments<float, true>(op, start_sites, n_start, N, (int)eff_tile, workspace, mu_ee, mhe, st)
-                : run_moments<float, false>(op, start_sites, n_start, N, (int)eff_tile, workspace, mu_ee, mhe, st);
+        return cplx ? run_moments<double, true>(op, start_sites, n_start, N, et, doubling, workspace, mu_ee, mhe, st)
+                    : run_moments<double, false>(op, start_sites, n_start, N, et, doubling, workspace, mu_ee, mhe, st);
+    return cplx ? run_moments<float, true>(op, start_sites, n_start, N, et, doubling, workspace, mu_ee, mhe, st)
+                : run_moments<float, false>(op, start_sites, n_start, N, et, doubling, workspace, mu_ee, mhe, st);
 }
 
 extern "C" int cbdg_check_moments(const double *mu_ee, const void *mu_he, int64_t n_rows, int32_t N,

@@ -27,6 +27,7 @@ struct StepArgs {
     double *mu_he;       // tile's first row (complex interleaved for C)
     int n_strips, n_segs, nblocks;
     int ys;              // rows per segment
+    double *part;        // moment-doubling partials [regions][K][Bp], or null
 };
 
 // Lane stride of a tile of B vectors: B rounded up to the wavefront, plus

@@ -9,13 +9,14 @@ DEV = torch.device("cuda:0") if torch.cuda.is_available() else None
 TOL_MOMENT = 1e-10  # |mu| <= 1, so this is relative as well
 
 
-def gpu_moments(w, sites=None, N=None, tile=None, precision=0, fixed=None):
+def gpu_moments(w, sites=None, N=None, tile=None, precision=0, fixed=None, algorithm=0):
     import paper_1007_1609_amd as P
     op = P.Operator.from_workload(w, DEV, fixed=fixed)
     s = w.start_sites if sites is None else np.asarray(sites, dtype=np.int32)
     st = torch.as_tensor(s, dtype=torch.int32, device=DEV)
     mu_ee, mu_he = P.chebyshev_moments(op, st, w.N if N is None else N,
-                                       (w.tile if tile is None else tile), precision)
+                                       (w.tile if tile is None else tile), precision,
+                                       algorithm=algorithm)
     torch.cuda.synchronize()
     return op, mu_ee.cpu().numpy(), mu_he.cpu().numpy()
 

@@ -78,8 +78,8 @@ def test_host_validation_without_gpu():
     assert "eta" in L.cbdg_last_error()
     # moments: NULL op, bad N
     n = C.c_size_t()
-    assert lib.cbdg_moments_workspace_size(None, 64, 0, C.byref(n)) == L.CBDG_EINVAL
-    assert lib.cbdg_chebyshev_moments(None, None, 0, 8, 8, 0, None, 0, None, None, None) == L.CBDG_EINVAL
+    assert lib.cbdg_moments_workspace_size(None, 64, 0, 0, C.byref(n)) == L.CBDG_EINVAL
+    assert lib.cbdg_chebyshev_moments(None, None, 0, 8, 8, 0, 0, None, 0, None, None, None) == L.CBDG_EINVAL
     # gap update: bad N, bad kernel, finite temperature, E = 0 outside the interval
     w = L.cbdg_weights(0, 0.0, 0.0, 0.0, 2.0, 0.0)
     assert lib.cbdg_gap_update(None, 4, 0, 0, C.byref(w), 1.0, None, None, 1.0, None, 8, None) == L.CBDG_EINVAL
@@ -98,5 +98,5 @@ def test_host_validation_without_gpu():
 def test_python_errors_carry_message():
     L = _ensure_lib()
     with pytest.raises(L.CbdgError) as e:
-        L.cbdg_moments_workspace_size(None, 0, 0, None)
+        L.cbdg_moments_workspace_size(None, 0, 0, 0, None)
     assert e.value.code == L.CBDG_EINVAL and "moments_workspace_size" in str(e.value)

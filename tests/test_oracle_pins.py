@@ -438,3 +438,40 @@ def test_scf_matches_ed_self_consistency_with_same_filter():
     assert np.max(np.abs(ref - delta)) < 1e-9
     # the impurity suppresses the gap locally
     assert delta[W.site(16, 8, 8)] < delta[W.site(16, 2, 2)]
+
+
+# ----------------------------------------------- moment doubling identities
+def _vectors(H, s, K):
+    """a_0..a_K of one start vector through the oracle's explicit matrix."""
+    import scipy.sparse as sp
+    A = H.to_scipy()
+    a = [np.zeros(H.D, dtype=np.complex128)]
+    a[0][2 * s] = 1.0
+    a.append(A @ a[0])
+    for n in range(2, K + 1):
+        a.append(2 * (A @ a[-1]) - a[-2])
+    return a
+
+
+@pytest.mark.parametrize("case", [dict(), dict(complex_=True, bond=True, flux=0.2)])
+def test_moment_doubling_identities(case):
+    """With b = 0 and C(u,v) = (-v*, u*) anticommuting with Ht:
+    mu_ee[2n] = 2<a_n|a_n> - mu_0, mu_ee[2n-1] = 2<a_n|a_{n-1}> - mu_ee[1],
+    mu_he[2n-1] = 2(-1)^n B(a_n, a_{n-1}) - mu_he[1], mu_he[2n] = 0,
+    with the bilinear form B(a, b) = sum_i u_a(i) v_b(i) - v_a(i) u_b(i)."""
+    w = _small(**case)
+    _, _, a, b = oracle.workload_bounds(w)
+    assert b == 0.0
+    K = 30
+    H = oracle.workload_csr(w, a, b)
+    for s in (0, 7, w.L2 - 1):
+        mu_ee, mu_he = oracle.moments(H, [s], 2 * K + 1, force_complex=True)
+        vec = _vectors(H, s, K)
+        for n in range(1, K + 1):
+            an, am = vec[n], vec[n - 1]
+            assert abs(2 * np.vdot(an, an).real - mu_ee[0, 0] - mu_ee[0, 2 * n]) < 1e-13
+            assert abs(2 * np.vdot(an, am).real - mu_ee[0, 1] - mu_ee[0, 2 * n - 1]) < 1e-13
+            u_n, v_n, u_m, v_m = an[0::2], an[1::2], am[0::2], am[1::2]
+            B = np.sum(u_n * v_m - v_n * u_m)
+            assert abs(2 * (-1) ** n * B - mu_he[0, 1] - mu_he[0, 2 * n - 1]) < 1e-13
+            assert abs(mu_he[0, 2 * n]) < 1e-13
