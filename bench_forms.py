@@ -32,6 +32,27 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def cone_site_steps(sites, Lx, Ly, bc_x, bc_y, n_steps):
+    """(lattice sites the recursion launches of one tile process, summed over
+    its steps) and (the same without light-cone clipping): step 1 covers the
+    lattice, step n >= 2 the box of the tile's start sites widened by n in
+    each open direction (x at site granularity: exact for tiles made of whole
+    lattice rows, as in every workload here)."""
+    sites = np.asarray(sites)
+    sites = sites[(sites >= 0) & (sites < Lx * Ly)]
+    full = Lx * Ly * n_steps
+    if n_steps < 1:
+        return 0, 0
+    done = Lx * Ly
+    if sites.size == 0:
+        return done, full
+    x, y = sites % Lx, sites // Lx
+    n = np.arange(2, n_steps + 1)
+    rows = np.full(n.shape, Ly) if bc_y else np.minimum(Ly - 1, y.max() + n) - np.maximum(0, y.min() - n) + 1
+    cols = np.full(n.shape, Lx) if bc_x else np.minimum(Lx - 1, x.max() + n) - np.maximum(0, x.min() - n) + 1
+    return done + int(np.sum(rows * cols)), full
+
+
 def _timed(fn):
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -113,10 +134,17 @@ def complex_form(args, dev):
         ld, t_ldos = _timed(lambda: P.ldos(out[0], wt, E))
         ldos[name] = ld
         launches = steps * len(ev)
-        nbytes = sum(steps * 3.0 * w.D * 2 * s_bytes * ((bt + 63) // 64 * 64) for _, _, bt in ev)
+        nbytes = nfull = 0.0
+        sites_np = w.start_sites
+        for k, (_, _, bt) in enumerate(ev):
+            done, full = cone_site_steps(sites_np[k * tile:k * tile + bt], w.Lx, w.Ly, w.bc_x, w.bc_y, steps)
+            unit = 3.0 * 2 * 2 * s_bytes * ((bt + 63) // 64 * 64)  # 3 streams x (e,h) x (re,im)
+            nbytes += done * unit
+            nfull += full * unit
         gbs = nbytes / t / 1e9
         res[name] = {"moments_per_s": n * N / (t + t_ldos), "seconds_moments": t, "seconds_ldos": t_ldos,
                      "avg_launch_us": t / launches * 1e6, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+                     "effective_GBps_full_lattice": nfull / t / 1e9, "light_cone_fraction": nbytes / nfull,
                      "moments_bounded": bool(P.check_moments(out[0], out[1], 1e-9 if s_bytes == 8 else 1e-4))}
         log("%s: %.2f s moments, %.0f GB/s" % (name, t, gbs))
         del ws, out

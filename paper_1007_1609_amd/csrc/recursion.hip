@@ -62,9 +62,39 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
 
     const int Lx = A.Lx, Ly = A.Ly;
     const int x0 = strip * W;
-    const int y0 = seg * A.ys;
-    const int y1 = min(y0 + A.ys, Ly);
+    int y0 = seg * A.ys;
+    int y1 = min(y0 + A.ys, Ly);
     const int64_t Bp = A.Bp;
+    // Light cone: H has nearest-neighbour range, so a_n vanishes farther than
+    // n sites (in x or y) from every start site; a_{n-2} (the output buffer)
+    // vanishes there too, so those strips and rows are left as they are.  The
+    // rows inside the cone are shared out evenly over the launch's segments
+    // (at least 4 rows each), so early steps still spread over the GPU.  The
+    // first step writes every site (its output buffer is not cleared).
+    if constexpr (!FIRST) {
+        if (A.cone) {
+            const int n = A.n;
+            bool skip = false;
+            if (!A.bcx) skip = x0 + W - 1 < A.cone[0] - n || x0 > A.cone[1] + n;
+            if (!A.bcy) {
+                const int ylo = max(0, A.cone[2] - n), yhi = min(Ly - 1, A.cone[3] + n);
+                const int rows = yhi - ylo + 1;
+                const int per = max(4, (rows + A.n_segs - 1) / A.n_segs);
+                y0 = ylo + seg * per;
+                y1 = min(y0 + per, yhi + 1);
+                skip = skip || rows <= 0 || y0 >= y1;
+            }
+            if (skip) {
+                if constexpr (DOT) {
+                    constexpr int K = C ? 4 : 3;
+                    double *pp = A.part + (strip + (int64_t)A.n_strips * seg) * K * Bp + b;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) pp[k * Bp] = 0.0;
+                }
+                return;
+            }
+        }
+    }
     // a1 (a_{n-1}) is never written by this launch -- out aliases a_{n-2}
     // only -- and the coefficients are read-only, which lets the wave-uniform
     // coefficient reads become scalar loads.  Addresses are a wave-uniform
@@ -259,6 +289,36 @@ __global__ void k_seed(typename Storage<T, C>::type *a0, int64_t Bp, int Bt, int
     else mu_he[m] = 0.0;
 }
 
+// Bounding box {x_min, x_max, y_min, y_max} of the tile's valid start sites
+// (an empty tile gives x_min > x_max).  One workgroup of kBlock threads.
+__global__ __launch_bounds__(kBlock) void k_tile_cone(const int32_t *sites, int Bt, int Lx, int64_t L2,
+                                                     int32_t *cone)
+{
+    __shared__ int red[4][kBlock];
+    int v[4] = {INT32_MAX, -1, INT32_MAX, -1};
+    for (int b = threadIdx.x; b < Bt; b += kBlock) {
+        const int64_t s = sites[b];
+        if (s < 0 || s >= L2) continue;
+        const int x = (int)(s % Lx), y = (int)(s / Lx);
+        v[0] = min(v[0], x); v[1] = max(v[1], x);
+        v[2] = min(v[2], y); v[3] = max(v[3], y);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) {
+            const int o = threadIdx.x + h;
+            red[0][threadIdx.x] = min(red[0][threadIdx.x], red[0][o]);
+            red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][o]);
+            red[2][threadIdx.x] = min(red[2][threadIdx.x], red[2][o]);
+            red[3][threadIdx.x] = max(red[3][threadIdx.x], red[3][o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) cone[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // Launch shapes per vector type, chosen by measurement on MI355X (one
 // 1024-vector step):
 //   W   strip width in sites (W + 2 columns of a_{n-1} per row in registers)
@@ -387,6 +447,7 @@ static int launch_step(StepArgs A, hipStream_t st)
 // adds the 16 wave sums in order) and writes the moments.  Rows of invalid
 // start sites keep their NaN.
 constexpr int kRedWaves = 16;
+constexpr int64_t kConeDoubles = 32;  // workspace slot of the tile's bounding box (256 B)
 constexpr int kMaxGroups = 256;
 
 // Regions per run and number of runs for R regions (at most kMaxGroups runs).
@@ -508,8 +569,10 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
     const int64_t Bp_max = lane_stride(tile);
     S *bufA = reinterpret_cast<S *>(ws);
     S *bufB = bufA + L2 * Bp_max;
-    // doubling partials: [regions][K][Bp], then [runs][K][Bp]
-    double *part = reinterpret_cast<double *>(bufB + L2 * Bp_max);
+    // tile bounding box, then the doubling partials: [regions][K][Bp], then
+    // [runs][K][Bp]
+    int32_t *cone = reinterpret_cast<int32_t *>(bufB + L2 * Bp_max);
+    double *part = reinterpret_cast<double *>(bufB + L2 * Bp_max) + kConeDoubles;
     double *part2 = part + (doubling ? max_regions<T, C>(op->Lx, op->Ly, tile) * (C ? 4 : 3) * Bp_max : 0);
     const void *onsite = std::is_same<T, double>::value ? (const void *)op->onsite64 : (const void *)op->onsite32;
     const void *bonds = std::is_same<T, double>::value ? op->bonds64 : op->bonds32;
@@ -527,7 +590,10 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         hipLaunchKernelGGL((k_seed<T, C>), dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st,
                            bufA, Bp, Bt, L2, ts, mee, mhe, N);
         CBDG_CHECK_LAUNCH("k_seed");
+        hipLaunchKernelGGL(k_tile_cone, dim3(1), dim3(kBlock), 0, st, ts, Bt, op->Lx, L2, cone);
+        CBDG_CHECK_LAUNCH("k_tile_cone");
         StepArgs A{};
+        A.cone = cone;
         A.onsite = onsite;
         A.bonds = bonds;
         A.th = op->t / op->bounds.a;
@@ -629,7 +695,8 @@ extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int3
     // sized for any N: the partials are included whenever doubling may run
     int rc = resolve_algorithm(op, algorithm, 3, "moments_workspace_size", &doubling);
     if (rc) return rc;
-    *bytes = 2 * (size_t)op->L2 * (size_t)lane_stride(tile) * pair_bytes(op->scalar, precision);
+    *bytes = 2 * (size_t)op->L2 * (size_t)lane_stride(tile) * pair_bytes(op->scalar, precision) +
+             kConeDoubles * sizeof(double);
     if (doubling) *bytes += (size_t)doubling_partial_bytes(op, tile, precision);
     return CBDG_OK;
 }
@@ -653,7 +720,8 @@ extern "C" int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_si
     if (!start_sites || !mu_ee || !mu_he || !workspace)
         return fail(CBDG_EINVAL, "chebyshev_moments: start_sites, mu_ee, mu_he and workspace must not be NULL");
     const int64_t eff_tile = std::min<int64_t>(tile, n_start);
-    size_t need = 2 * (size_t)op->L2 * (size_t)lane_stride(eff_tile) * pair_bytes(op->scalar, precision);
+    size_t need = 2 * (size_t)op->L2 * (size_t)lane_stride(eff_tile) * pair_bytes(op->scalar, precision) +
+                  kConeDoubles * sizeof(double);
     if (doubling) need += (size_t)doubling_partial_bytes(op, (int)eff_tile, precision);
     if (workspace_bytes < need)
         return fail(CBDG_EINVAL, "chebyshev_moments: workspace of %zu bytes is smaller than the %zu needed",

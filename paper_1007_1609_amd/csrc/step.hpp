@@ -28,6 +28,9 @@ struct StepArgs {
     int n_strips, n_segs, nblocks;
     int ys;              // rows per segment
     double *part;        // moment-doubling partials [regions][K][Bp], or null
+    const int32_t *cone; // {x_min, x_max, y_min, y_max} of the tile's valid start
+                         // sites, or null: steps n >= 2 skip strips and rows
+                         // farther than n from that box (a_n is zero there)
 };
 
 // Lane stride of a tile of B vectors: B rounded up to the wavefront, plus

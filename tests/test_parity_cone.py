@@ -1,0 +1,82 @@
+"""Light-cone clipping of the recursion steps (a_n vanishes farther than n
+sites from the tile's start sites, so those strips and rows are skipped):
+tiles whose bounding box is small, sits in a corner, follows a tile with a
+larger box, mixes in invalid sites, or lies on a periodic direction, all
+against the oracle with both moment algorithms."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_common import TOL_MOMENT, gpu_moments, maxdiff
+
+pytestmark = pytest.mark.gpu
+
+ALGS = [1, 2]  # direct, doubling
+
+
+def _check(w, sites, tile, alg, N=None):
+    op, g_ee, g_he = gpu_moments(w, sites=sites, N=N, tile=tile, algorithm=alg)
+    a, b = op.bounds.a, op.bounds.b
+    op.close()
+    valid = (sites >= 0) & (sites < w.L2)
+    o_ee, o_he = oracle.workload_moments(w, a, b, sites=sites[valid], N=N)
+    assert maxdiff(g_ee[valid], o_ee) <= TOL_MOMENT
+    assert maxdiff(g_he[valid], o_he) <= TOL_MOMENT
+    assert np.all(np.isnan(g_ee[~valid]))
+
+
+def _block(Lx, x0, x1, y0, y1):
+    return np.array([y * Lx + x for y in range(y0, y1) for x in range(x0, x1)], dtype=np.int32)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_corner_tile_on_a_long_lattice(alg):
+    # 48x80, sites in a 5x3 corner block: the cone covers the lattice only
+    # after ~75 steps (direct) or ~40 steps (doubling) of N = 96
+    w = W.small_random(48, 80, N=96, seed=21)
+    _check(w, _block(48, 0, 5, 0, 3), 64, alg)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_small_tile_after_large_tiles(alg):
+    # tile 1: spread over the lattice; tile 2: one site far from everything;
+    # tile 3: a block at the other end -- stale values of earlier tiles must
+    # not leak into the skipped rows
+    w = W.small_random(40, 64, N=80, seed=22)
+    spread = np.arange(0, w.L2, 97, dtype=np.int32)[:26]
+    one = np.array([63 * 40 + 39], dtype=np.int32)
+    blk = _block(40, 30, 36, 60, 64)[:26]
+    sites = np.concatenate([spread, np.repeat(one, 26), blk])
+    _check(w, sites, 26, alg)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_column_of_sites_clips_strips(alg):
+    # every row, x in 0..2: the box is narrow in x, full in y
+    w = W.small_random(64, 24, N=64, seed=23)
+    _check(w, _block(64, 0, 3, 0, 24), 128, alg)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+@pytest.mark.parametrize("bc", [dict(bc_x=W.PERIODIC), dict(bc_y=W.PERIODIC),
+                                dict(bc_x=W.PERIODIC, bc_y=W.PERIODIC)])
+def test_periodic_directions_are_not_clipped(alg, bc):
+    w = W.small_random(32, 40, N=72, seed=24, **bc)
+    _check(w, _block(32, 0, 4, 0, 4), 16, alg)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_invalid_sites_do_not_widen_or_empty_the_box(alg):
+    w = W.small_random(32, 48, N=64, seed=25)
+    sites = np.concatenate([_block(32, 10, 14, 20, 22), np.array([-5, w.L2, 10 ** 6], np.int32)])
+    _check(w, sites, 64, alg)
+    # a tile of invalid sites only, followed by a valid corner tile
+    sites = np.concatenate([np.full(8, -1, np.int32), _block(32, 0, 2, 0, 4)])
+    _check(w, sites, 8, alg)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+def test_complex_bond_operator_corner(alg):
+    w = W.small_random(36, 44, N=70, seed=26, complex_=True, bond=True, flux=0.2)
+    _check(w, _block(36, 30, 36, 40, 44), 32, alg)
