@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("stencil.hpp", "recursion.hip", "common.hpp"):
+    for f in ("stencil.hpp", "step.hpp", "recursion.hip", "common.hpp"):
         with open(os.path.join(ROOT, "paper_1007_1609_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -124,6 +124,8 @@ def main():
                     help="scf-step (default): one SCF iteration of the 256x256 workload; complex: "
                          "512x512 Peierls/d-wave LDOS workload; adjoint: 128x128 gradients and "
                          "Newton-Krylov; scf: full self-consistent solve of the 256x256 workload")
+    ap.add_argument("--scf-method", choices=["plain", "nk-fd"], default="plain",
+                    help="--form scf: plain mixing, or Newton-Krylov with finite-difference products")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "
