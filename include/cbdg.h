@@ -245,7 +245,7 @@ int cbdg_ldos_backward(const double *d_ldos, int64_t n_rows, int32_t N,
 /* Bytes of workspace cbdg_chebyshev_moments_backward needs (host out).
  * ckpt_stride 0 selects k = ceil(sqrt(N)). */
 int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
-                                 int32_t ckpt_stride, size_t *bytes);
+                                 int32_t ckpt_stride, int32_t algorithm, size_t *bytes);
 
 /*
  * Reverse-mode derivative of the moments for a REAL FP64 operator with
@@ -258,14 +258,21 @@ int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
  * runs over them, accumulating sum_{n>=1} c_n <lam_n, dHt/dtheta a_{n-1}>
  * (c_1 = 1, c_n = 2).  The sum over start vectors is reduced in a fixed
  * order, so repeated calls give identical bits.
+ *   ckpt_stride  k; 0: ceil(sqrt(N)) (DIRECT) or ceil(sqrt(N/2 + 1)) (DOUBLING)
+ *   algorithm    enum cbdg_algorithm.  DOUBLING (AUTO when b == 0, N >= 3)
+ *                differentiates the doubling formulas instead: forward and
+ *                adjoint run over a_0 .. a_{N/2} only, the cotangent of a_m
+ *                being a whole vector built from a_{m-1}, a_m, a_{m+1}; the
+ *                gradient is the same up to rounding.  DOUBLING with b != 0
+ *                is EINVAL.
  *   dmu_ee, dmu_he  [n_start*N] FP64 (either may be NULL: zero)
  *   grad_eps, grad_delta  [L2] FP64, accumulated into (caller zeroes)
  * COMPLEX operators, bond pairing or Peierls phases return EUNSUPPORTED.
  */
 int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t *start_sites,
                                     int64_t n_start, int32_t N, int32_t tile,
-                                    int32_t ckpt_stride, const double *dmu_ee,
-                                    const double *dmu_he, void *workspace,
+                                    int32_t ckpt_stride, int32_t algorithm,
+                                    const double *dmu_ee, const double *dmu_he, void *workspace,
                                     size_t workspace_bytes, double *grad_eps,
                                     double *grad_delta, void *stream);
 

@@ -68,8 +68,8 @@ SIGNATURES = {
     "cbdg_gap_update_backward": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _f64, _vp, _f64,
                                  _vp, _vp, _vp],
     "cbdg_ldos_backward": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _vp, _i32, _vp, _vp],
-    "cbdg_backward_workspace_size": [_vp, _i32, _i32, _i32, C.POINTER(_sz)],
-    "cbdg_chebyshev_moments_backward": [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz,
+    "cbdg_backward_workspace_size": [_vp, _i32, _i32, _i32, _i32, C.POINTER(_sz)],
+    "cbdg_chebyshev_moments_backward": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _sz,
                                         _vp, _vp, _vp],
 }
 

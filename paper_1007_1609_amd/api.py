@@ -210,9 +210,10 @@ def ldos_backward(d_ldos: torch.Tensor, N: int, w: L.cbdg_weights, energies: tor
     return d_mu
 
 
-def backward_workspace_bytes(op: Operator, tile: int, N: int, ckpt_stride: int = 0) -> int:
+def backward_workspace_bytes(op: Operator, tile: int, N: int, ckpt_stride: int = 0,
+                             algorithm: int = L.CBDG_ALG_AUTO) -> int:
     n = C.c_size_t()
-    L.cbdg_backward_workspace_size(op.handle, int(tile), int(N), int(ckpt_stride), C.byref(n))
+    L.cbdg_backward_workspace_size(op.handle, int(tile), int(N), int(ckpt_stride), int(algorithm), C.byref(n))
     return n.value
 
 
@@ -220,10 +221,10 @@ def chebyshev_moments_backward(op: Operator, sites: torch.Tensor, N: int, tile: 
                                dmu_ee: Optional[torch.Tensor], dmu_he: Optional[torch.Tensor],
                                ckpt_stride: int = 0, grad_eps: Optional[torch.Tensor] = None,
                                grad_delta: Optional[torch.Tensor] = None,
-                               ws: Optional[torch.Tensor] = None):
+                               ws: Optional[torch.Tensor] = None, algorithm: int = L.CBDG_ALG_AUTO):
     n = int(sites.numel())
     eff = max(1, min(int(tile), n))
-    need = backward_workspace_bytes(op, eff, N, ckpt_stride)
+    need = backward_workspace_bytes(op, eff, N, ckpt_stride, algorithm)
     if ws is None or ws.numel() < need:
         ws = workspace(need, sites.device)
     if grad_eps is None:
@@ -231,7 +232,7 @@ def chebyshev_moments_backward(op: Operator, sites: torch.Tensor, N: int, tile: 
     if grad_delta is None:
         grad_delta = torch.zeros(op.L2, dtype=torch.float64, device=sites.device)
     L.cbdg_chebyshev_moments_backward(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N),
-                                      int(tile), int(ckpt_stride),
+                                      int(tile), int(ckpt_stride), int(algorithm),
                                       _ptr(dmu_ee, torch.float64, "dmu_ee"),
                                       _ptr(dmu_he, torch.float64, "dmu_he"),
                                       _ptr(ws, None, "workspace"), ws.numel(),

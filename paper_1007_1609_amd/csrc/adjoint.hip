@@ -18,6 +18,21 @@
 // each segment is recomputed from its pair just before the adjoint walks
 // through it.  Per tile: 2*ceil((N-1)/k) + max(k-2, 2) + 2 vectors.
 //
+// With moment doubling (b = 0) the moments are functions of a_0 .. a_M only,
+// M = floor(N/2):  mu_ee[2m] = 2<a_m|a_m> - 1,
+// mu_ee[2m-1] = 2<a_m|a_{m-1}> - mu_ee[1],
+// mu_he[2m-1] = 2(-1)^m B(a_m, a_{m-1}) - mu_he[1], mu_he[2m] = 0, with
+// B(x, y) = sum_i x_e(i) y_h(i) - x_h(i) y_e(i).  Their cotangent on a_m is a
+// whole vector,
+//   w_m = 4 g_ee[2m] a_m + 2 g_ee[2m+1] a_{m+1} + 2 g_ee[2m-1] a_{m-1}
+//       + 2(-1)^{m+1} g_he[2m+1] (-a_{m+1,h}, a_{m+1,e})
+//       + 2(-1)^m g_he[2m-1] (a_{m-1,h}, -a_{m-1,e})
+// (each term only where its moment index lies in 2..N-1), plus at m = 1 the
+// start-site terms of mu_ee[1] and mu_he[1], whose cotangents collect
+// g[1] - sum_{m>=2} g[2m-1].  The same transposed recursion then runs over
+// m = M .. 1 only: half the forward and adjoint steps, at the price of two
+// more vector reads per adjoint step.
+//
 // The sum over the tile's vectors is a wavefront reduction per site; each
 // (64-vector chunk, site) partial is owned by one wavefront, accumulated over
 // n without atomics and summed over chunks in a fixed order, so results are
@@ -46,6 +61,9 @@ struct AdjArgs {
     int64_t L2;
     int n_strips, n_segs, nblocks;
     int ys;               // rows per segment
+    const void *acur;     // a_m (doubling)
+    const void *anext;    // a_{m+1} (doubling, when a moment 2m+1 <= N-1 exists)
+    const double *d1;     // [Bt][2] start-site cotangents of mu_ee[1], mu_he[1] (doubling)
 };
 
 __device__ __forceinline__ double wave_sum_f64(double v)
@@ -55,7 +73,7 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
-template <bool HAS1, bool HAS2, int W>
+template <bool HAS1, bool HAS2, int W, bool DBL, bool NXT>
 __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *__restrict__ lam1,
                                                      const OnSite<double> *__restrict__ ons,
                                                      const double2 *__restrict__ aprev)
@@ -85,8 +103,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
     S *lo = reinterpret_cast<S *>(A.out);
     const double th = A.th;
     const int my_site = active ? A.sites[b] : -1;
-    const double we = (active && A.dmu_ee) ? A.dmu_ee[(int64_t)b * A.N + A.n] : 0.0;
-    const double wh = (active && A.dmu_he) ? A.dmu_he[(int64_t)b * A.N + A.n] : 0.0;
+    double we = 0.0, wh = 0.0;
+    // doubling: w_m = cA a_m + cP a_{m+1} + cQ (-a_{m+1,h}, a_{m+1,e})
+    //               + cR a_{m-1} + cS (a_{m-1,h}, -a_{m-1,e})
+    [[maybe_unused]] double cA = 0.0, cP = 0.0, cQ = 0.0, cR = 0.0, cS = 0.0;
+    if constexpr (DBL) {
+        const int m = A.n, N = A.N;
+        const int64_t row = (int64_t)b * N;
+        auto gee = [&](int i) { return (active && A.dmu_ee && i >= 2 && i < N) ? A.dmu_ee[row + i] : 0.0; };
+        auto ghe = [&](int i) { return (active && A.dmu_he && i >= 2 && i < N) ? A.dmu_he[row + i] : 0.0; };
+        const double sg = (m & 1) ? -2.0 : 2.0;  // 2(-1)^m
+        cA = 4.0 * gee(2 * m);
+        cP = 2.0 * gee(2 * m + 1);
+        cQ = -sg * ghe(2 * m + 1);
+        if (m >= 2) { cR = 2.0 * gee(2 * m - 1); cS = sg * ghe(2 * m - 1); }
+        if (m == 1 && active) { we = A.d1[2 * b]; wh = A.d1[2 * b + 1]; }
+    } else {
+        we = (active && A.dmu_ee) ? A.dmu_ee[(int64_t)b * A.N + A.n] : 0.0;
+        wh = (active && A.dmu_he) ? A.dmu_he[(int64_t)b * A.N + A.n] : 0.0;
+    }
+    const S *am = reinterpret_cast<const S *>(A.acur);
+    const S *ap = reinterpret_cast<const S *>(A.anext);
     double *gp = A.gpart + (int64_t)c64 * A.L2 * 2;
 
     int cx[W + 2];
@@ -125,6 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
 
     P up[W + 2], cur[W + 2], dn[W + 2], nx[W + 2];
     P pc[W], pn[W], ac[W], an[W];
+    [[maybe_unused]] P mc[DBL ? W : 1], mn[DBL ? W : 1], qc[NXT ? W : 1], qn[NXT ? W : 1];
     if constexpr (HAS1) {
         apply_mask(up, load_row(up, y0 - 1));
         apply_mask(cur, load_row(cur, y0));
@@ -132,6 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
     }
     if constexpr (HAS2) load_own(l2, pc, y0, true);
     load_own(aprev, ac, y0, true);
+    if constexpr (DBL) load_own(am, mc, y0, true);
+    if constexpr (NXT) load_own(ap, qc, y0, true);
 
     auto compute_row = [&](int y) {
         const int64_t srow = (int64_t)y * Lx;
@@ -148,6 +188,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
             if constexpr (HAS2) {
                 lam.e -= pc[k].e;
                 lam.h -= pc[k].h;
+            }
+            if constexpr (DBL) {
+                lam.e += cA * mc[k].e + cR * ac[k].e + cS * ac[k].h;
+                lam.h += cA * mc[k].h + cR * ac[k].h - cS * ac[k].e;
+            }
+            if constexpr (NXT) {
+                lam.e += cP * qc[k].e - cQ * qc[k].h;
+                lam.h += cP * qc[k].h + cQ * qc[k].e;
             }
             const bool hit = s == my_site;
             lam.e += hit ? we : 0.0;
@@ -171,6 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
         if constexpr (HAS1) nm = load_row(nx, y + 2);
         if constexpr (HAS2) load_own(l2, pn, y + 1, true);
         load_own(aprev, an, y + 1, true);
+        if constexpr (DBL) load_own(am, mn, y + 1, true);
+        if constexpr (NXT) load_own(ap, qn, y + 1, true);
         compute_row(y);
         if constexpr (HAS1) {
             apply_mask(nx, nm);
@@ -179,8 +229,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
         }
 #pragma unroll
         for (int k = 0; k < W; ++k) { pc[k] = pn[k]; ac[k] = an[k]; }
+        if constexpr (DBL) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) mc[k] = mn[k];
+        }
+        if constexpr (NXT) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) qc[k] = qn[k];
+        }
     }
     compute_row(y1 - 1);
+}
+
+// Start-site cotangents of mu_ee[1] and mu_he[1] under doubling: every odd
+// moment 2m-1 >= 3 subtracts mu[1], so d1 = g[1] - sum_{m=2..M} g[2m-1].
+__global__ void k_adj_d1(const double *dmu_ee, const double *dmu_he, int Bt, int N, double *d1)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bt) return;
+    const int64_t row = (int64_t)b * N;
+    double e = 0.0, h = 0.0;
+    for (int i = 3; i < N; i += 2) {
+        if (dmu_ee) e += dmu_ee[row + i];
+        if (dmu_he) h += dmu_he[row + i];
+    }
+    d1[2 * b] = (dmu_ee && N > 1 ? dmu_ee[row + 1] : 0.0) - e;
+    d1[2 * b + 1] = (dmu_he && N > 1 ? dmu_he[row + 1] : 0.0) - h;
 }
 
 __global__ void k_fill_f64(double *p, int64_t n)
@@ -205,7 +279,7 @@ __global__ void k_grad_reduce(const double *gpart, int nchunk, int64_t L2, doubl
 
 constexpr int kAdjW = 4, kAdjYS = 64;
 
-template <bool HAS1, bool HAS2, int W>
+template <bool HAS1, bool HAS2, int W, bool DBL, bool NXT>
 static int launch_adj_w(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
 {
     A.n_strips = A.Lx / W;
@@ -216,32 +290,58 @@ static int launch_adj_w(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
     const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments_backward: launch grid too large");
     A.nblocks = (int)nb;
-    hipLaunchKernelGGL((k_adj_step<HAS1, HAS2, W>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
+    hipLaunchKernelGGL((k_adj_step<HAS1, HAS2, W, DBL, NXT>), dim3(A.nblocks), dim3(kBlock), 0, st, A,
                        reinterpret_cast<const double2 *>(A.lam1), ons, reinterpret_cast<const double2 *>(A.aprev));
     CBDG_CHECK_LAUNCH("k_adj_step");
     return CBDG_OK;
 }
 
-template <bool HAS1, bool HAS2>
-static int launch_adj(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
+// Strip width of the doubling-form adjoint step (three more register rows
+// than the direct form).  128x128, N = 512, 4 tiles of 1024 on MI355X:
+// W = 2 511 ms, W = 1 510 ms, W = 4 561 ms (256 VGPRs, one wave per SIMD).
+#ifndef CBDG_ADJ_W_DBL
+#define CBDG_ADJ_W_DBL 2
+#endif
+
+template <bool HAS1, bool HAS2, bool DBL, bool NXT>
+static int launch_adj_d(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
 {
-    if (A.Lx % kAdjW == 0) return launch_adj_w<HAS1, HAS2, kAdjW>(A, ons, st);
-    if (A.Lx % 2 == 0) return launch_adj_w<HAS1, HAS2, 2>(A, ons, st);
-    return launch_adj_w<HAS1, HAS2, 1>(A, ons, st);
+    constexpr int WB = DBL ? CBDG_ADJ_W_DBL : kAdjW;
+    if (A.Lx % WB == 0) return launch_adj_w<HAS1, HAS2, WB, DBL, NXT>(A, ons, st);
+    if (A.Lx % 2 == 0) return launch_adj_w<HAS1, HAS2, 2, DBL, NXT>(A, ons, st);
+    return launch_adj_w<HAS1, HAS2, 1, DBL, NXT>(A, ons, st);
+}
+
+template <bool HAS1, bool HAS2>
+static int launch_adj(AdjArgs A, const OnSite<double> *ons, bool dbl, hipStream_t st)
+{
+    if (!dbl) return launch_adj_d<HAS1, HAS2, false, false>(A, ons, st);
+    if (A.anext) return launch_adj_d<HAS1, HAS2, true, true>(A, ons, st);
+    return launch_adj_d<HAS1, HAS2, true, false>(A, ons, st);
 }
 
 struct Plan {
+    bool dbl;        // doubling form
+    int top;         // last forward vector the adjoint reads: N-2 (direct), M (doubling)
+    int mtop;        // first adjoint index: N-1 (direct), M (doubling)
     int k;           // checkpoint stride
     int J;           // segments
     int nscratch;    // segment / scratch vectors
     int64_t Bp;      // lane stride for the widest tile
 };
 
-static Plan make_plan(int N, int tile, int ckpt_stride)
+// Checkpoint stride k = ceil(sqrt(N)) (direct) or ceil(sqrt(M + 1))
+// (doubling) unless given.
+static Plan make_plan(int N, int tile, int ckpt_stride, bool dbl)
 {
     Plan p;
-    p.k = ckpt_stride > 0 ? ckpt_stride : std::max(1, (int)std::ceil(std::sqrt((double)N)));
-    p.J = N > 1 ? (int)ceil_div(N - 1, p.k) : 1;
+    p.dbl = dbl;
+    p.top = dbl ? N / 2 : std::max(N - 2, 0);
+    p.mtop = dbl ? N / 2 : N - 1;
+    const int nvec = p.top + 1;
+    const int kdef = (int)std::ceil(std::sqrt((double)(dbl ? nvec : N)));
+    p.k = ckpt_stride > 0 ? ckpt_stride : std::max(1, kdef);
+    p.J = (int)ceil_div(nvec, p.k);
     p.nscratch = std::max(p.k - 2, 2);
     p.Bp = lane_stride(tile);
     return p;
@@ -251,7 +351,8 @@ static size_t plan_bytes(const Plan &p, int64_t L2)
 {
     const size_t vec = (size_t)L2 * (size_t)p.Bp * sizeof(double2);
     const size_t gpart = (size_t)(p.Bp / kWave) * (size_t)L2 * 2 * sizeof(double);
-    return (size_t)(2 * p.J + p.nscratch + 2) * vec + gpart;
+    const size_t d1 = p.dbl ? (size_t)p.Bp * 2 * sizeof(double) : 0;
+    return (size_t)(2 * p.J + p.nscratch + 2) * vec + gpart + d1;
 }
 
 }  // namespace cbdg
@@ -267,22 +368,41 @@ static int check_backward_op(const cbdg_op *op, const char *who)
     return CBDG_OK;
 }
 
+// Resolves the algorithm of the backward pass (the forward's enum): doubling
+// needs b == 0; N <= 2 always takes the direct form.
+static int backward_algorithm(const cbdg_op *op, int32_t algorithm, int32_t N, const char *who, bool *dbl)
+{
+    const bool centred = op->bounds.b == 0.0;
+    switch (algorithm) {
+    case CBDG_ALG_AUTO: *dbl = centred && N >= 3; return CBDG_OK;
+    case CBDG_ALG_DIRECT: *dbl = false; return CBDG_OK;
+    case CBDG_ALG_DOUBLING:
+        if (!centred) return fail(CBDG_EINVAL, "%s: moment doubling needs a spectrum centred at b = 0 (b = %g)", who, op->bounds.b);
+        *dbl = N >= 3;
+        return CBDG_OK;
+    default: return fail(CBDG_EINVAL, "%s: unknown algorithm %d", who, algorithm);
+    }
+}
+
 extern "C" int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N, int32_t ckpt_stride,
-                                            size_t *bytes)
+                                            int32_t algorithm, size_t *bytes)
 {
     clear_error();
     int rc = check_backward_op(op, "backward_workspace_size");
     if (rc) return rc;
     if (!bytes || tile < 1 || N < 1 || ckpt_stride < 0)
         return fail(CBDG_EINVAL, "backward_workspace_size: need bytes, tile >= 1, N >= 1, ckpt_stride >= 0");
-    *bytes = plan_bytes(make_plan(N, tile, ckpt_stride), op->L2);
+    bool dbl = false;
+    rc = backward_algorithm(op, algorithm, N, "backward_workspace_size", &dbl);
+    if (rc) return rc;
+    *bytes = plan_bytes(make_plan(N, tile, ckpt_stride, dbl), op->L2);
     return CBDG_OK;
 }
 
 extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t *start_sites,
                                                int64_t n_start, int32_t N, int32_t tile,
-                                               int32_t ckpt_stride, const double *dmu_ee,
-                                               const double *dmu_he, void *workspace,
+                                               int32_t ckpt_stride, int32_t algorithm,
+                                               const double *dmu_ee, const double *dmu_he, void *workspace,
                                                size_t workspace_bytes, double *grad_eps,
                                                double *grad_delta, void *stream)
 {
@@ -291,11 +411,14 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
     if (rc) return rc;
     if (n_start < 0 || N < 1 || tile < 1 || ckpt_stride < 0)
         return fail(CBDG_EINVAL, "chebyshev_moments_backward: need n_start >= 0, N >= 1, tile >= 1, ckpt_stride >= 0");
+    bool dbl = false;
+    rc = backward_algorithm(op, algorithm, N, "chebyshev_moments_backward", &dbl);
+    if (rc) return rc;
     if (n_start == 0 || N == 1 || (!dmu_ee && !dmu_he)) return CBDG_OK;  // nothing depends on eps or Delta
     if (!start_sites || !workspace || (!grad_eps && !grad_delta))
         return fail(CBDG_EINVAL, "chebyshev_moments_backward: start_sites, workspace and a gradient output are required");
     const int eff_tile = (int)std::min<int64_t>(tile, n_start);
-    const Plan plan = make_plan(N, eff_tile, ckpt_stride);
+    const Plan plan = make_plan(N, eff_tile, ckpt_stride, dbl);
     const size_t need = plan_bytes(plan, op->L2);
     if (workspace_bytes < need)
         return fail(CBDG_EINVAL, "chebyshev_moments_backward: workspace of %zu bytes is smaller than the %zu needed",
@@ -310,7 +433,9 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
     double2 *LA = base + (int64_t)(2 * plan.J + plan.nscratch) * vec;
     double2 *LB = LA + vec;
     double *gpart = reinterpret_cast<double *>(LB + vec);
+    double *d1 = gpart + (plan.Bp / kWave) * L2 * 2;
     const int k = plan.k;
+    const int top = plan.top, mtop = plan.mtop;
 
     for (int64_t t0 = 0; t0 < n_start; t0 += eff_tile) {
         const int Bt = (int)std::min<int64_t>(eff_tile, n_start - t0);
@@ -320,7 +445,7 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
         const double *tee = dmu_ee ? dmu_ee + t0 * N : nullptr;
         const double *the = dmu_he ? dmu_he + t0 * N : nullptr;
 
-        // forward: a_0 .. a_{N-2}, keeping the checkpoint pairs
+        // forward: a_0 .. a_top, keeping the checkpoint pairs
         rc = seed_tile_f64_real(C0(0), L2, Bt, ts, nullptr, nullptr, N, st);
         if (rc) return rc;
         StepArgs S{};
@@ -328,7 +453,7 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
         S.Lx = op->Lx; S.Ly = op->Ly; S.bcx = op->bc_x; S.bcy = op->bc_y;
         S.Bp = (int)Bp; S.Bt = Bt; S.N = N; S.sites = ts; S.mu_ee = nullptr; S.mu_he = nullptr;
         const double2 *p2 = nullptr, *p1 = C0(0);
-        for (int n = 1; n <= N - 2; ++n) {
+        for (int n = 1; n <= top; ++n) {
             double2 *dest;
             if (n % k == 0) dest = C0(n / k);
             else if (k > 1 && n % k == 1) dest = C1(n / k);
@@ -350,20 +475,28 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
         hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>(ceil_div(ng, kBlock), 4096)), dim3(kBlock), 0,
                            st, gpart, ng);
         CBDG_CHECK_LAUNCH("k_fill_f64");
+        if (dbl) {
+            hipLaunchKernelGGL(k_adj_d1, dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st, tee, the, Bt, N, d1);
+            CBDG_CHECK_LAUNCH("k_adj_d1");
+        }
         AdjArgs A{};
         A.th = op->t / op->bounds.a;
         A.Lx = op->Lx; A.Ly = op->Ly; A.bcx = op->bc_x; A.bcy = op->bc_y;
         A.Bp = (int)Bp; A.Bt = Bt; A.N = N; A.sites = ts; A.dmu_ee = tee; A.dmu_he = the;
-        A.gpart = gpart; A.L2 = L2;
-        auto lam = [&](int n) { return ((N - 1 - n) % 2 == 0) ? LA : LB; };
+        A.gpart = gpart; A.L2 = L2; A.d1 = d1;
+        auto lam = [&](int n) { return ((mtop - n) % 2 == 0) ? LA : LB; };
         for (int j = plan.J - 1; j >= 0; --j) {
-            const int s0 = j * k, e0 = std::min(s0 + k - 1, N - 2);
+            const int s0 = j * k, e0 = std::min(s0 + k - 1, top);
+            // forward vector m: recomputed scratch inside this segment, else a
+            // checkpoint (the adjoint of the doubling form also reads a_{e0+1}
+            // and a_{e0+2}, the next segment's pair)
             auto vec_of = [&](int m) -> const double2 * {
-                if (m == s0) return C0(j);
-                if (m == s0 + 1) return C1(j);
+                if (m % k == 0) return C0(m / k);
+                if (k > 1 && m % k == 1) return C1(m / k);
                 return SC(m - s0 - 2);
             };
             for (int m = s0 + 2; m <= e0; ++m) {
+                if (m % k == 0 || (k > 1 && m % k == 1)) continue;  // a checkpoint already
                 S.first = 0;
                 S.n = m;
                 S.prev1 = vec_of(m - 1);
@@ -372,18 +505,20 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
                 rc = run_step(op, CBDG_FP64, S, st);
                 if (rc) return rc;
             }
-            for (int n = e0 + 1; n >= s0 + 1; --n) {
-                const bool has1 = n + 1 <= N - 1, has2 = n + 2 <= N - 1;
+            for (int n = std::min(e0 + 1, mtop); n >= s0 + 1; --n) {
+                const bool has1 = n + 1 <= mtop, has2 = n + 2 <= mtop;
                 A.n = n;
                 A.lam1 = has1 ? lam(n + 1) : nullptr;
                 A.lam2 = has2 ? lam(n + 2) : nullptr;
                 A.out = lam(n);
                 A.aprev = vec_of(n - 1);
+                A.acur = dbl ? vec_of(n) : nullptr;
+                A.anext = (dbl && 2 * n + 1 <= N - 1) ? vec_of(n + 1) : nullptr;
                 A.cscale = (n == 1 ? 1.0 : 2.0) / op->bounds.a;
                 const OnSite<double> *ons = op->onsite64;
-                if (has1 && has2) rc = launch_adj<true, true>(A, ons, st);
-                else if (has1) rc = launch_adj<true, false>(A, ons, st);
-                else rc = launch_adj<false, false>(A, ons, st);
+                if (has1 && has2) rc = launch_adj<true, true>(A, ons, dbl, st);
+                else if (has1) rc = launch_adj<true, false>(A, ons, dbl, st);
+                else rc = launch_adj<false, false>(A, ons, dbl, st);
                 if (rc) return rc;
             }
         }

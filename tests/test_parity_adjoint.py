@@ -21,69 +21,97 @@ def _rel(x, ref):
     return float(np.max(np.abs(np.asarray(x) - np.asarray(ref))) / max(np.max(np.abs(ref)), 1e-300))
 
 
-def _gpu_backward(w, N, dmu_ee, dmu_he, tile, ckpt=0, sites=None):
+def _gpu_backward(w, N, dmu_ee, dmu_he, tile, ckpt=0, sites=None, algorithm=0, fixed=None):
     P = _P()
-    op = P.Operator.from_workload(w, DEV)
+    op = P.Operator.from_workload(w, DEV, fixed=fixed)
     s = torch.as_tensor(w.start_sites if sites is None else sites, dtype=torch.int32, device=DEV)
     ge, gd = P.chebyshev_moments_backward(
         op, s, N, tile, None if dmu_ee is None else torch.as_tensor(dmu_ee, device=DEV),
-        None if dmu_he is None else torch.as_tensor(dmu_he, device=DEV), ckpt)
+        None if dmu_he is None else torch.as_tensor(dmu_he, device=DEV), ckpt, algorithm=algorithm)
     torch.cuda.synchronize()
     a, b = op.bounds.a, op.bounds.b
     op.close()
     return ge.cpu().numpy(), gd.cpu().numpy(), a, b
 
 
+ALGS = [1, 2]  # direct adjoint, adjoint of the doubling formulas
+
+
+@pytest.mark.parametrize("alg", ALGS)
 @pytest.mark.parametrize("Lx,Ly,N,tile,ckpt,bc", [
-    (12, 10, 40, 64, 0, 0),      # default stride ceil(sqrt(40)) = 7, one tile
+    (12, 10, 40, 64, 0, 0),      # default stride, one tile
     (12, 10, 40, 37, 3, 0),      # ragged tiles, stride 3
     (10, 9, 33, 128, 1, 0),      # stride 1 (every vector a checkpoint), W = 2 strips
     (9, 13, 25, 50, 25, 0),      # one segment, odd width (W = 1)
     (8, 8, 31, 64, 4, 1),        # periodic
     (16, 20, 64, 300, 0, 0),     # several 256-lane chunks of one tile
+    (12, 14, 41, 64, 2, 0),      # stride 2 (pairs only), odd N
+    (12, 14, 44, 64, 5, 0),      # even N, ragged last segment
 ])
-def test_backward_matches_oracle(Lx, Ly, N, tile, ckpt, bc):
+def test_backward_matches_oracle(Lx, Ly, N, tile, ckpt, bc, alg):
     w = W.small_random(Lx, Ly, N=N, seed=Lx + Ly + N, bc_x=bc, bc_y=bc)
     rng = np.random.default_rng(N)
     n = len(w.start_sites)
     dee, dhe = rng.normal(size=(n, N)), rng.normal(size=(n, N))
-    ge, gd, a, b = _gpu_backward(w, N, dee, dhe, tile, ckpt)
+    ge, gd, a, b = _gpu_backward(w, N, dee, dhe, tile, ckpt, algorithm=alg)
     H = oracle.workload_csr(w, a, b)
     oe, od = oracle.moments_backward(H, w.start_sites, N, dee, dhe)
-    print("backward %dx%d N=%d tile=%d k=%d: rel err eps %.2e delta %.2e" % (
-        Lx, Ly, N, tile, ckpt, _rel(ge, oe), _rel(gd, od)))
+    print("backward %dx%d N=%d tile=%d k=%d alg=%d: rel err eps %.2e delta %.2e" % (
+        Lx, Ly, N, tile, ckpt, alg, _rel(ge, oe), _rel(gd, od)))
     assert _rel(ge, oe) < 1e-10 and _rel(gd, od) < 1e-10
 
 
-@pytest.mark.parametrize("N", [2, 3])
-def test_backward_few_moments(N):
+@pytest.mark.parametrize("alg", ALGS)
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_backward_few_moments(N, alg):
     w = W.small_random(6, 5, N=N, seed=3)
     rng = np.random.default_rng(1)
     n = len(w.start_sites)
     dee, dhe = rng.normal(size=(n, N)), rng.normal(size=(n, N))
-    ge, gd, a, b = _gpu_backward(w, N, dee, dhe, 64)
+    ge, gd, a, b = _gpu_backward(w, N, dee, dhe, 64, algorithm=alg)
     oe, od = oracle.moments_backward(oracle.workload_csr(w, a, b), w.start_sites, N, dee, dhe)
     assert _rel(ge, oe) < 1e-12 and _rel(gd, od) < 1e-12
 
 
-def test_only_one_cotangent():
+@pytest.mark.parametrize("alg", ALGS)
+@pytest.mark.parametrize("which", ["ee", "he"])
+def test_only_one_cotangent(which, alg):
     w = W.small_random(8, 7, N=30, seed=4)
     n = len(w.start_sites)
-    dhe = np.random.default_rng(2).normal(size=(n, 30))
-    ge, gd, a, b = _gpu_backward(w, 30, None, dhe, 64)
-    oe, od = oracle.moments_backward(oracle.workload_csr(w, a, b), w.start_sites, 30, np.zeros((n, 30)), dhe)
+    g = np.random.default_rng(2).normal(size=(n, 30))
+    z = np.zeros((n, 30))
+    args = (g, None) if which == "ee" else (None, g)
+    ge, gd, a, b = _gpu_backward(w, 30, *args, 64, algorithm=alg)
+    oargs = (g, z) if which == "ee" else (z, g)
+    oe, od = oracle.moments_backward(oracle.workload_csr(w, a, b), w.start_sites, 30, *oargs)
     assert _rel(ge, oe) < 1e-10 and _rel(gd, od) < 1e-10
 
 
-def test_checkpoint_strides_give_identical_bits():
+@pytest.mark.parametrize("alg", ALGS)
+def test_checkpoint_strides_give_identical_bits(alg):
     w = W.small_random(12, 12, N=50, seed=6)
     rng = np.random.default_rng(3)
     n = len(w.start_sites)
     dee, dhe = rng.normal(size=(n, 50)), rng.normal(size=(n, 50))
-    ref = _gpu_backward(w, 50, dee, dhe, 64, 1)
-    for k in (2, 3, 7, 49, 50):
-        got = _gpu_backward(w, 50, dee, dhe, 64, k)
+    ref = _gpu_backward(w, 50, dee, dhe, 64, 1, algorithm=alg)
+    for k in (2, 3, 7, 25, 26, 49, 50):
+        got = _gpu_backward(w, 50, dee, dhe, 64, k, algorithm=alg)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k
+
+
+def test_doubling_adjoint_needs_centred_rescaling():
+    P = _P()
+    w = W.small_random(8, 8, N=20, seed=7)
+    rng = np.random.default_rng(5)
+    n = len(w.start_sites)
+    dee, dhe = rng.normal(size=(n, 20)), rng.normal(size=(n, 20))
+    with pytest.raises(P.CbdgError) as e:
+        _gpu_backward(w, 20, dee, dhe, 64, algorithm=2, fixed=(7.5, 0.2))
+    assert e.value.code == -1
+    # AUTO falls back to the direct adjoint and matches the oracle
+    ge, gd, a, b = _gpu_backward(w, 20, dee, dhe, 64, algorithm=0, fixed=(7.5, 0.2))
+    oe, od = oracle.moments_backward(oracle.workload_csr(w, 7.5, 0.2), w.start_sites, 20, dee, dhe)
+    assert _rel(ge, oe) < 1e-10 and _rel(gd, od) < 1e-10
 
 
 def test_backward_accumulates_into_outputs():
