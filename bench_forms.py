@@ -32,25 +32,46 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def cone_site_steps(sites, Lx, Ly, bc_x, bc_y, n_steps):
-    """(lattice sites the recursion launches of one tile process, summed over
-    its steps) and (the same without light-cone clipping): step 1 covers the
-    lattice, step n >= 2 the box of the tile's start sites widened by n in
-    each open direction (x at site granularity: exact for tiles made of whole
-    lattice rows, as in every workload here)."""
+def _cone_sites(x, y, Lx, Ly, bc_x, bc_y, n):
+    """Sites inside the box of the start sites widened by n (open directions;
+    x at site granularity, exact for tiles of whole lattice rows)."""
+    if x.size == 0:
+        return 0
+    rows = Ly if bc_y else min(Ly - 1, int(y.max()) + n) - max(0, int(y.min()) - n) + 1
+    cols = Lx if bc_x else min(Lx - 1, int(x.max()) + n) - max(0, int(x.min()) - n) + 1
+    return max(rows, 0) * max(cols, 0)
+
+
+def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step):
+    """Recursion launches of one tile as the library issues them, and the
+    vector elements (site x vector, in units of one Nambu pair per vector)
+    each must move through HBM at minimum:
+      first step   read a_0, write a_1 over the lattice: 2 x L2
+      two-step     read a_{n-2}, a_{n-1}, write a_n, a_{n+1} inside the light
+                   cone of step n+1: 4 x cone(n+1)
+      single step  read a_{n-2}, a_{n-1}, write a_n inside cone(n): 3 x cone(n)
+    Two-step passes cover steps 2.. in pairs on real operators with uniform
+    hopping.  Returns (launches, pair-elements moved, pair-elements of the
+    plain one-step streaming recursion over the whole lattice, 3 x L2 per
+    step)."""
     sites = np.asarray(sites)
     sites = sites[(sites >= 0) & (sites < Lx * Ly)]
-    full = Lx * Ly * n_steps
-    if n_steps < 1:
-        return 0, 0
-    done = Lx * Ly
-    if sites.size == 0:
-        return done, full
     x, y = sites % Lx, sites // Lx
-    n = np.arange(2, n_steps + 1)
-    rows = np.full(n.shape, Ly) if bc_y else np.minimum(Ly - 1, y.max() + n) - np.maximum(0, y.min() - n) + 1
-    cols = np.full(n.shape, Lx) if bc_x else np.minimum(Lx - 1, x.max() + n) - np.maximum(0, x.min() - n) + 1
-    return done + int(np.sum(rows * cols)), full
+    L2 = Lx * Ly
+    if n_steps < 1:
+        return 0, 0, 0
+    launches, moved = 1, 2 * L2
+    n = 2
+    if two_step:
+        while n + 1 <= n_steps:
+            launches += 1
+            moved += 4 * _cone_sites(x, y, Lx, Ly, bc_x, bc_y, n + 1)
+            n += 2
+    while n <= n_steps:
+        launches += 1
+        moved += 3 * _cone_sites(x, y, Lx, Ly, bc_x, bc_y, n)
+        n += 1
+    return launches, moved, 3 * L2 * n_steps
 
 
 def _timed(fn):
@@ -133,18 +154,20 @@ def complex_form(args, dev):
         t, ev = _moments_pass(op, sites, N, tile, prec, ws, out, alg)
         ld, t_ldos = _timed(lambda: P.ldos(out[0], wt, E))
         ldos[name] = ld
-        launches = steps * len(ev)
+        launches = 0
         nbytes = nfull = 0.0
         sites_np = w.start_sites
         for k, (_, _, bt) in enumerate(ev):
-            done, full = cone_site_steps(sites_np[k * tile:k * tile + bt], w.Lx, w.Ly, w.bc_x, w.bc_y, steps)
-            unit = 3.0 * 2 * 2 * s_bytes * ((bt + 63) // 64 * 64)  # 3 streams x (e,h) x (re,im)
-            nbytes += done * unit
+            nl, moved, full = recursion_traffic(sites_np[k * tile:k * tile + bt], w.Lx, w.Ly, w.bc_x, w.bc_y,
+                                                steps, two_step=False)
+            unit = 2 * 2 * s_bytes * ((bt + 63) // 64 * 64)  # (e,h) x (re,im) per vector
+            launches += nl
+            nbytes += moved * unit
             nfull += full * unit
         gbs = nbytes / t / 1e9
         res[name] = {"moments_per_s": n * N / (t + t_ldos), "seconds_moments": t, "seconds_ldos": t_ldos,
                      "avg_launch_us": t / launches * 1e6, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
-                     "effective_GBps_full_lattice": nfull / t / 1e9, "light_cone_fraction": nbytes / nfull,
+                     "effective_GBps_streaming": nfull / t / 1e9,
                      "moments_bounded": bool(P.check_moments(out[0], out[1], 1e-9 if s_bytes == 8 else 1e-4))}
         log("%s: %.2f s moments, %.0f GB/s" % (name, t, gbs))
         del ws, out

@@ -251,6 +251,214 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     }
 }
 
+// Two recursion steps in one pass, for real operators with uniform hopping:
+//     a_n     = 2 Ht a_{n-1} - a_{n-2}   (into A.out)
+//     a_{n+1} = 2 Ht a_n     - a_{n-1}   (into A.out2)
+// from a_{n-2} (A.prev2) and a_{n-1} (a1); the four buffers are distinct.  A
+// lane computes a_n on its strip widened by one column on each side and on
+// one row beyond each end of its segment (reading a_{n-1} two columns and two
+// rows out, a_{n-2} one out), so a_{n+1} needs nothing from other
+// workgroups.  Per two steps the vectors cross HBM four times (read a_{n-2},
+// a_{n-1}; write a_n, a_{n+1}) instead of six; the widened a_n costs extra
+// arithmetic and L2 reads only.
+//
+// Row r of a_n is computed with rows r-1, r, r+1 of a_{n-1} in registers;
+// row r-1 of a_{n+1} follows from rows r-2, r-1, r of a_n.  Columns: a_{n-1}
+// at x0-2 .. x0+W+1 (index k <-> x0-2+k), a_n at x0-1 .. x0+W (k <-> x0-1+k).
+#ifndef CBDG_PF2
+#define CBDG_PF2 0
+#endif
+template <typename T, int W, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_cheb_step2(StepArgs A, const typename Storage<T, false>::type *__restrict__ a1,
+                                                      const OnSite<T> *__restrict__ ons)
+{
+    using P = Pair<T, false>;
+    using S = typename Storage<T, false>::type;
+    constexpr int X = W + 2, Y = W + 4;
+    const int lb = xcd_remap(blockIdx.x, A.nblocks);
+    const int strip = lb % A.n_strips;
+    const int rest = lb / A.n_strips;
+    const int seg = rest % A.n_segs;
+    const int chunk = rest / A.n_segs;
+    const uint32_t b = chunk * kBlock + threadIdx.x;
+    if (b >= (uint32_t)A.Bt) return;
+
+    const int Lx = A.Lx, Ly = A.Ly;
+    const int x0 = strip * W;
+    int y0 = seg * A.ys;
+    int y1 = min(y0 + A.ys, Ly);
+    const int64_t Bp = A.Bp;
+    const int64_t region = strip + (int64_t)A.n_strips * seg;
+    // light cone of a_{n+1} (that of a_n lies inside it); rows inside are
+    // shared out over the segments as in the one-step kernel
+    if (A.cone) {
+        const int m = A.n + 1;
+        bool skip = false;
+        if (!A.bcx) skip = x0 + W - 1 < A.cone[0] - m || x0 > A.cone[1] + m;
+        if (!A.bcy) {
+            const int ylo = max(0, A.cone[2] - m), yhi = min(Ly - 1, A.cone[3] + m);
+            const int rows = yhi - ylo + 1;
+            const int per = max(4, (rows + A.n_segs - 1) / A.n_segs);
+            y0 = ylo + seg * per;
+            y1 = min(y0 + per, yhi + 1);
+            skip = skip || rows <= 0 || y0 >= y1;
+        }
+        if (skip) {
+            if constexpr (DOT) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    A.part[(region * 3 + k) * Bp + b] = 0.0;
+                    A.part_b[(region * 3 + k) * Bp + b] = 0.0;
+                }
+            }
+            return;
+        }
+    }
+    const S *a2 = reinterpret_cast<const S *>(A.prev2);
+    S *ao = reinterpret_cast<S *>(A.out);
+    S *ao2 = reinterpret_cast<S *>(A.out2);
+    const int my_site = A.sites[b];
+    const T th = T(A.th);
+
+    // columns x0-2+k: an in-bounds index and a mask (0 outside an open lattice)
+    int cx[Y];
+    uint32_t cm[Y];
+#pragma unroll
+    for (int k = 0; k < Y; ++k) {
+        const int x = x0 - 2 + k;
+        if (A.bcx) {
+            cx[k] = ((x % Lx) + Lx) % Lx;
+            cm[k] = ~0u;
+        } else {
+            const bool ok = x >= 0 && x < Lx;
+            cx[k] = ok ? x : (x < 0 ? 0 : Lx - 1);
+            cm[k] = ok ? ~0u : 0u;
+        }
+    }
+    // in-bounds row index of y and its mask
+    auto row_of = [&](int y, uint32_t &ok) -> int64_t {
+        if (A.bcy) { ok = ~0u; return (int64_t)(((y % Ly) + Ly) % Ly) * Lx; }
+        const bool in = y >= 0 && y < Ly;
+        ok = in ? ~0u : 0u;
+        return (int64_t)(in ? y : (y < 0 ? 0 : Ly - 1)) * Lx;
+    };
+    auto load_row1 = [&](P *row, int y) -> uint32_t {
+        uint32_t ok;
+        const int64_t rb = row_of(y, ok);
+#pragma unroll
+        for (int k = 0; k < Y; ++k) row[k] = ld<T, false>(a1 + (rb + cx[k]) * Bp + b);
+        return ok;
+    };
+    auto mask_row1 = [&](P *row, uint32_t rm) {
+#pragma unroll
+        for (int k = 0; k < Y; ++k) row[k] = masked<T, false>(row[k], rm & cm[k]);
+    };
+
+    P w0[Y], w1[Y], w2[Y], nx[Y];      // a_{n-1} rows r-1, r, r+1, r+2
+    P m2[X], m1[X], m0[X];             // a_n rows r-2, r-1, r
+    P p2[X];                           // a_{n-2} row r
+    [[maybe_unused]] P p2n[CBDG_PF2 ? X : 1];  // a_{n-2} row r + 1 (prefetch)
+    P mval = zero_pair<T, false>(), mval1 = zero_pair<T, false>();
+    bool found = false, found1 = false;
+    double d_nn = 0.0, d_nm = 0.0, d_b = 0.0, e_nn = 0.0, e_nm = 0.0, e_b = 0.0;
+    mask_row1(w0, load_row1(w0, y0 - 2));
+    mask_row1(w1, load_row1(w1, y0 - 1));
+    mask_row1(w2, load_row1(w2, y0));
+#pragma unroll
+    for (int k = 0; k < X; ++k) { m1[k] = zero_pair<T, false>(); m0[k] = zero_pair<T, false>(); }
+    auto load_row2 = [&](P *row, int y) {
+        uint32_t ok;
+        const int64_t rb = row_of(y, ok);
+#pragma unroll
+        for (int k = 0; k < X; ++k) row[k] = CBDG_NT_A2 ? ld_nt<T, false>(a2 + (rb + cx[k + 1]) * Bp + b)
+                                                        : ld<T, false>(a2 + (rb + cx[k + 1]) * Bp + b);
+    };
+    if constexpr (CBDG_PF2) load_row2(p2, y0 - 1);
+
+#pragma unroll 1
+    for (int r = y0 - 1; r <= y1; ++r) {
+        uint32_t nm = 0;
+        if (r + 2 <= y1 + 1) nm = load_row1(nx, r + 2);
+        if constexpr (CBDG_PF2) {
+            if (r + 1 <= y1) load_row2(p2n, r + 1);
+        } else {
+            load_row2(p2, r);
+        }
+        uint32_t rok;
+        const int64_t rb = row_of(r, rok);
+#pragma unroll
+        for (int k = 0; k < X; ++k) { m2[k] = m1[k]; m1[k] = m0[k]; }
+        // a_n, row r, columns x0-1 .. x0+W
+        const bool own_r = r >= y0 && r < y1;
+#pragma unroll
+        for (int k = 0; k < X; ++k) {
+            const OnSite<T> o = ons[rb + cx[k + 1]];
+            const P yv = apply_uniform<T, false>(o, th, w1[k + 1], w1[k], w1[k + 2], w0[k + 1], w2[k + 1]);
+            m0[k] = masked<T, false>(cheb_combine<T, false>(yv, p2[k], false), rok & cm[k + 1]);
+        }
+        if (own_r) {
+#pragma unroll
+            for (int k = 1; k <= W; ++k) {
+                const int64_t s = rb + x0 + k - 1;
+                const P &v = m0[k];
+                if constexpr (CBDG_NT_OUT) st_nt<T, false>(ao + s * Bp + b, v);
+                else st<T, false>(ao + s * Bp + b, v);
+                const bool hit = s == my_site;
+                found = found || hit;
+                mval = select_pair<T, false>(hit, v, mval);
+                if constexpr (DOT) {
+                    const double e = v.e, h = v.h, ce = w1[k + 1].e, ch = w1[k + 1].h;
+                    d_nn += e * e + h * h;
+                    d_nm += e * ce + h * ch;
+                    d_b += e * ch - h * ce;
+                }
+            }
+        }
+        // a_{n+1}, row r-1, own columns
+        if (r - 1 >= y0) {
+            uint32_t qok;
+            const int64_t qb = row_of(r - 1, qok);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const int64_t s = qb + x0 + k;
+                const OnSite<T> o = ons[s];
+                const P yv = apply_uniform<T, false>(o, th, m1[k + 1], m1[k], m1[k + 2], m2[k + 1], m0[k + 1]);
+                const P v = cheb_combine<T, false>(yv, w0[k + 2], false);
+                if constexpr (CBDG_NT_OUT) st_nt<T, false>(ao2 + s * Bp + b, v);
+                else st<T, false>(ao2 + s * Bp + b, v);
+                const bool hit = s == my_site;
+                found1 = found1 || hit;
+                mval1 = select_pair<T, false>(hit, v, mval1);
+                if constexpr (DOT) {
+                    const double e = v.e, h = v.h, ce = m1[k + 1].e, ch = m1[k + 1].h;
+                    e_nn += e * e + h * h;
+                    e_nm += e * ce + h * ch;
+                    e_b += e * ch - h * ce;
+                }
+            }
+        }
+        if (r + 2 <= y1 + 1) mask_row1(nx, nm);
+#pragma unroll
+        for (int k = 0; k < Y; ++k) { w0[k] = w1[k]; w1[k] = w2[k]; w2[k] = nx[k]; }
+        if constexpr (CBDG_PF2) {
+#pragma unroll
+            for (int k = 0; k < X; ++k) p2[k] = p2n[k];
+        }
+    }
+
+    if constexpr (DOT) {
+        double *pp = A.part + region * 3 * Bp + b;
+        pp[0] = d_nn; pp[Bp] = d_nm; pp[2 * Bp] = d_b;
+        double *qq = A.part_b + region * 3 * Bp + b;
+        qq[0] = e_nn; qq[Bp] = e_nm; qq[2 * Bp] = e_b;
+    }
+    if (A.mu_ee) {
+        const int64_t m = (int64_t)b * A.N + A.n;
+        if (found) { A.mu_ee[m] = (double)mval.e; A.mu_he[m] = (double)mval.h; }
+        if (found1) { A.mu_ee[m + 1] = (double)mval1.e; A.mu_he[m + 1] = (double)mval1.h; }
+    }
+}
+
 // a_0 = |s_b, e> for every lane: zero the buffer ...
 template <typename T, bool C>
 __global__ void k_zero(typename Storage<T, C>::type *p, int64_t n)
@@ -432,6 +640,96 @@ static int launch_step(StepArgs A, hipStream_t st)
     return launch_step_w<T, C, GEN, 1, false>(A, st);
 }
 
+// Two-step passes (k_cheb_step2) for real operators with uniform hopping.
+// Strip width W, longest row segment YS2 and the workgroup count the
+// segments are shortened to reach (TGT2), by measurement on MI355X: one
+// 1024-vector tile of the 256x256 workload, N = 514 by doubling, microseconds
+// per moment index (FP64 / FP32; one-step kernel alone: 268.9 / 135.4):
+//   W = 2: 295.8 / 132.8   W = 4: 219.5 / 122.0   W = 8: 203.9 / 104.7
+//   W = 8, 1024 workgroups: 196.6 / 103.1; 512 workgroups: 193.1 / 102.2
+//   W = 16 (FP32): 133.8; a_{n-2} prefetched a row ahead: no gain.
+// At W = 8 the FP64 kernel holds 256 VGPRs plus AGPRs, one wave per SIMD.
+#ifndef CBDG_TWO_STEP
+#define CBDG_TWO_STEP 1
+#endif
+#ifndef CBDG_W2_F64
+#define CBDG_W2_F64 8
+#endif
+#ifndef CBDG_W2_F32
+#define CBDG_W2_F32 8
+#endif
+#ifndef CBDG_YS2
+#define CBDG_YS2 64
+#endif
+#ifndef CBDG_TGT2
+#define CBDG_TGT2 512
+#endif
+template <typename T> struct Step2Shape;
+template <> struct Step2Shape<double> { static constexpr int W = CBDG_W2_F64, YS = CBDG_YS2; };
+template <> struct Step2Shape<float> { static constexpr int W = CBDG_W2_F32, YS = CBDG_YS2; };
+
+template <typename T>
+static Shape choose_shape2(int Lx, int Ly, int64_t n_chunks)
+{
+    Shape sh;
+    constexpr int WB = Step2Shape<T>::W;
+    sh.W = (Lx % WB == 0) ? WB : (Lx % 4 == 0 ? 4 : (Lx % 2 == 0 ? 2 : 1));
+    sh.PF = false;
+    sh.n_strips = Lx / sh.W;
+    int ys = Step2Shape<T>::YS;
+    while (ys > 8 && (int64_t)sh.n_strips * n_chunks * ceil_div(Ly, ys) < CBDG_TGT2) ys /= 2;
+    sh.ys = ys;
+    sh.n_segs = (int)ceil_div(Ly, sh.ys);
+    return sh;
+}
+
+template <typename T>
+static int64_t max_regions2(int Lx, int Ly, int tile)
+{
+    int64_t r = 0;
+    for (int64_t c = 1; c <= ceil_div(tile, kBlock); ++c) {
+        const Shape sh = choose_shape2<T>(Lx, Ly, c);
+        r = std::max<int64_t>(r, (int64_t)sh.n_strips * sh.n_segs);
+    }
+    return r;
+}
+
+template <typename T, int W>
+static int launch_step2_w(StepArgs A, hipStream_t st)
+{
+    const int n_chunks = (int)ceil_div(A.Bt, kBlock);
+    const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
+    if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
+    A.nblocks = (int)nb;
+    const auto *a1 = reinterpret_cast<const typename Storage<T, false>::type *>(A.prev1);
+    const auto *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
+    if (A.part) hipLaunchKernelGGL((k_cheb_step2<T, W, true>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons);
+    else hipLaunchKernelGGL((k_cheb_step2<T, W, false>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons);
+    CBDG_CHECK_LAUNCH("k_cheb_step2");
+    return CBDG_OK;
+}
+
+template <typename T>
+static int launch_step2(StepArgs A, hipStream_t st)
+{
+    const Shape sh = choose_shape2<T>(A.Lx, A.Ly, ceil_div(A.Bt, kBlock));
+    A.n_strips = sh.n_strips;
+    A.ys = sh.ys;
+    A.n_segs = sh.n_segs;
+#if CBDG_W2_F32 == 16 || CBDG_W2_F64 == 16
+    if (sh.W == 16) return launch_step2_w<T, 16>(A, st);
+#endif
+    if (sh.W == 8) return launch_step2_w<T, 8>(A, st);
+    if (sh.W == 4) return launch_step2_w<T, 4>(A, st);
+    if (sh.W == 2) return launch_step2_w<T, 2>(A, st);
+    return launch_step2_w<T, 1>(A, st);
+}
+
+static bool uses_two_step(const cbdg_op *op)
+{
+    return CBDG_TWO_STEP && op->scalar == CBDG_REAL && !op->general;
+}
+
 // Moments 2n-1 and 2n of every vector from the partial sums of step n:
 //   mu_ee[2n]   = 2 <a_n|a_n> - mu_ee[0]
 //   mu_ee[2n-1] = 2 Re<a_n|a_{n-1}> - mu_ee[1]
@@ -558,8 +856,11 @@ int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, doubl
 
 // Direct: steps n = 1 .. N-1, each capturing moment n of every vector.
 // Doubling: steps n = 1 .. ceil((N-1)/2); step 1 captures moment 1 and every
-// step's partial sums give moments 2n-1 and 2n.  The partials sit after the
-// two vector buffers in the workspace.
+// step's partial sums give moments 2n-1 and 2n.  Real uniform operators take
+// the steps after the first two at a time (four tile buffers), the others
+// one at a time in place (two buffers).  Workspace: the tile buffers, the
+// tile's bounding box, then for doubling the partials of a pass's two steps
+// [regions][K][Bp] x 2 and the run sums [runs][K][Bp].
 template <typename T, bool C>
 static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start, int N, int tile,
                        bool doubling, void *ws, double *mu_ee, double *mu_he, hipStream_t st)
@@ -567,13 +868,16 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
     using S = typename Storage<T, C>::type;
     const int64_t L2 = op->L2;
     const int64_t Bp_max = lane_stride(tile);
-    S *bufA = reinterpret_cast<S *>(ws);
-    S *bufB = bufA + L2 * Bp_max;
-    // tile bounding box, then the doubling partials: [regions][K][Bp], then
-    // [runs][K][Bp]
-    int32_t *cone = reinterpret_cast<int32_t *>(bufB + L2 * Bp_max);
-    double *part = reinterpret_cast<double *>(bufB + L2 * Bp_max) + kConeDoubles;
-    double *part2 = part + (doubling ? max_regions<T, C>(op->Lx, op->Ly, tile) * (C ? 4 : 3) * Bp_max : 0);
+    const bool two = !C && uses_two_step(op);
+    const int nbuf = two ? 4 : 2;
+    S *buf[4];
+    for (int i = 0; i < 4; ++i) buf[i] = reinterpret_cast<S *>(ws) + (i < nbuf ? i : 0) * L2 * Bp_max;
+    int32_t *cone = reinterpret_cast<int32_t *>(reinterpret_cast<S *>(ws) + nbuf * L2 * Bp_max);
+    constexpr int K = C ? 4 : 3;
+    const int64_t Rmax = std::max(max_regions<T, C>(op->Lx, op->Ly, tile), two ? max_regions2<T>(op->Lx, op->Ly, tile) : 0);
+    double *part = reinterpret_cast<double *>(cone) + kConeDoubles;
+    double *part_b = part + (doubling ? Rmax * K * Bp_max : 0);
+    double *part2 = part_b + (doubling ? Rmax * K * Bp_max : 0);
     const void *onsite = std::is_same<T, double>::value ? (const void *)op->onsite64 : (const void *)op->onsite32;
     const void *bonds = std::is_same<T, double>::value ? op->bonds64 : op->bonds32;
     const int he_mult = C ? 2 : 1;
@@ -584,11 +888,14 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         double *mhe = mu_he + t0 * N * he_mult;
         const int32_t *ts = sites + t0;
         const int64_t nz = L2 * Bp;
-        hipLaunchKernelGGL((k_zero<T, C>), dim3((unsigned)std::min<int64_t>(ceil_div(nz, kBlock), 8192)),
-                           dim3(kBlock), 0, st, bufA, nz);
-        CBDG_CHECK_LAUNCH("k_zero");
+        const unsigned zgrid = (unsigned)std::min<int64_t>(ceil_div(nz, kBlock), 8192);
+        for (int i = 0; i < nbuf; ++i) {
+            if (i == 1) continue;  // a_1 is written whole by the first step
+            hipLaunchKernelGGL((k_zero<T, C>), dim3(zgrid), dim3(kBlock), 0, st, buf[i], nz);
+            CBDG_CHECK_LAUNCH("k_zero");
+        }
         hipLaunchKernelGGL((k_seed<T, C>), dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st,
-                           bufA, Bp, Bt, L2, ts, mee, mhe, N);
+                           buf[0], Bp, Bt, L2, ts, mee, mhe, N);
         CBDG_CHECK_LAUNCH("k_seed");
         hipLaunchKernelGGL(k_tile_cone, dim3(1), dim3(kBlock), 0, st, ts, Bt, op->Lx, L2, cone);
         CBDG_CHECK_LAUNCH("k_tile_cone");
@@ -599,31 +906,74 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         A.th = op->t / op->bounds.a;
         A.Lx = op->Lx; A.Ly = op->Ly; A.bcx = op->bc_x; A.bcy = op->bc_y;
         A.Bp = (int)Bp; A.Bt = Bt; A.N = N;
-        A.sites = ts; A.mu_ee = mee; A.mu_he = mhe;
-        S *buf[2] = {bufA, bufB};
+        A.sites = ts; A.mu_he = mhe;
         const int n_steps = doubling ? N / 2 : N - 1;
-        const Shape sh = choose_shape<T, C>(op->Lx, op->Ly, ceil_div(Bt, kBlock));
-        const int64_t regions = (int64_t)sh.n_strips * sh.n_segs;
-        int64_t per = 0, groups = 0;
-        doubling_groups(regions, &per, &groups);
-        for (int n = 1; n <= n_steps; ++n) {
-            A.first = n == 1;
-            A.n = n;
-            A.prev1 = buf[(n - 1) & 1];
-            A.prev2 = buf[n & 1];
-            A.out = buf[n & 1];
+        const int64_t chunks = ceil_div(Bt, kBlock);
+        const Shape sh1 = choose_shape<T, C>(op->Lx, op->Ly, chunks);
+        const int64_t regions1 = (int64_t)sh1.n_strips * sh1.n_segs;
+        int64_t regions2 = 0;
+        if constexpr (!C) {
+            if (two) {
+                const Shape sh2 = choose_shape2<T>(op->Lx, op->Ly, chunks);
+                regions2 = (int64_t)sh2.n_strips * sh2.n_segs;
+            }
+        }
+        auto reduce = [&](const double *pp, int64_t regions, int n) -> int {
+            int64_t per = 0, groups = 0;
+            doubling_groups(regions, &per, &groups);
+            hipLaunchKernelGGL((k_doubling_groups<C>), dim3((unsigned)ceil_div(Bt, kBlock), (unsigned)groups),
+                               dim3(kBlock), 0, st, pp, regions, per, Bp, Bt, part2);
+            CBDG_CHECK_LAUNCH("k_doubling_groups");
+            hipLaunchKernelGGL((k_doubling_reduce<C>), dim3((unsigned)ceil_div(Bt, kWave)),
+                               dim3(kRedWaves * kWave), 0, st, part2, groups, Bp, Bt, n, N, mee, mhe);
+            CBDG_CHECK_LAUNCH("k_doubling_reduce");
+            return CBDG_OK;
+        };
+        // P2 holds a_{n-2}, P1 a_{n-1}; Q0, Q1 are free (two-step passes)
+        S *P2 = buf[0], *P1 = buf[1], *Q0 = buf[2], *Q1 = buf[3];
+        int n = 1;
+        if (n_steps >= 1) {
+            A.first = 1;
+            A.n = 1;
+            A.prev1 = P2;
+            A.prev2 = P2;
+            A.out = P1;
             A.part = doubling ? part : nullptr;
-            A.mu_ee = (!doubling || n == 1) ? mee : nullptr;
+            A.mu_ee = mee;
             int rc = op->general ? launch_step<T, C, true>(A, st) : launch_step<T, C, false>(A, st);
             if (rc) return rc;
-            if (doubling) {
-                hipLaunchKernelGGL((k_doubling_groups<C>), dim3((unsigned)ceil_div(Bt, kBlock), (unsigned)groups),
-                                   dim3(kBlock), 0, st, part, regions, per, Bp, Bt, part2);
-                CBDG_CHECK_LAUNCH("k_doubling_groups");
-                hipLaunchKernelGGL((k_doubling_reduce<C>), dim3((unsigned)ceil_div(Bt, kWave)),
-                                   dim3(kRedWaves * kWave), 0, st, part2, groups, Bp, Bt, n, N, mee, mhe);
-                CBDG_CHECK_LAUNCH("k_doubling_reduce");
+            if (doubling && (rc = reduce(part, regions1, 1))) return rc;
+            n = 2;
+        }
+        A.first = 0;
+        A.mu_ee = doubling ? nullptr : mee;
+        if constexpr (!C) {
+            while (two && n + 1 <= n_steps) {
+                A.n = n;
+                A.prev2 = P2;
+                A.prev1 = P1;
+                A.out = Q0;
+                A.out2 = Q1;
+                A.part = doubling ? part : nullptr;
+                A.part_b = doubling ? part_b : nullptr;
+                int rc = launch_step2<T>(A, st);
+                if (rc) return rc;
+                if (doubling && ((rc = reduce(part, regions2, n)) || (rc = reduce(part_b, regions2, n + 1)))) return rc;
+                std::swap(P2, Q0);
+                std::swap(P1, Q1);
+                n += 2;
             }
+        }
+        for (; n <= n_steps; ++n) {
+            A.n = n;
+            A.prev1 = P1;
+            A.prev2 = P2;
+            A.out = P2;
+            A.part = doubling ? part : nullptr;
+            int rc = op->general ? launch_step<T, C, true>(A, st) : launch_step<T, C, false>(A, st);
+            if (rc) return rc;
+            if (doubling && (rc = reduce(part, regions1, n))) return rc;
+            std::swap(P1, P2);
         }
     }
     return CBDG_OK;
@@ -675,12 +1025,24 @@ static int resolve_algorithm(const cbdg_op *op, int32_t algorithm, int32_t N, co
 static int64_t doubling_partial_bytes(const cbdg_op *op, int tile, int precision)
 {
     const bool cplx = op->scalar == CBDG_COMPLEX;
+    const bool two = uses_two_step(op);
     const int K = cplx ? 4 : 3;
     int64_t R;
-    if (precision == CBDG_FP64) R = cplx ? max_regions<double, true>(op->Lx, op->Ly, tile) : max_regions<double, false>(op->Lx, op->Ly, tile);
-    else R = cplx ? max_regions<float, true>(op->Lx, op->Ly, tile) : max_regions<float, false>(op->Lx, op->Ly, tile);
+    if (precision == CBDG_FP64)
+        R = cplx ? max_regions<double, true>(op->Lx, op->Ly, tile)
+                 : std::max(max_regions<double, false>(op->Lx, op->Ly, tile), two ? max_regions2<double>(op->Lx, op->Ly, tile) : 0);
+    else
+        R = cplx ? max_regions<float, true>(op->Lx, op->Ly, tile)
+                 : std::max(max_regions<float, false>(op->Lx, op->Ly, tile), two ? max_regions2<float>(op->Lx, op->Ly, tile) : 0);
+    // every run count is at most min(kMaxGroups, ceil(R/4)) for R <= Rmax
     const int64_t G = std::min<int64_t>(kMaxGroups, ceil_div(R, 4));
-    return (R + G) * K * lane_stride(tile) * (int64_t)sizeof(double);
+    return (2 * R + G) * K * lane_stride(tile) * (int64_t)sizeof(double);
+}
+
+static size_t tile_buffer_bytes(const cbdg_op *op, int64_t tile, int precision)
+{
+    const size_t nbuf = uses_two_step(op) ? 4 : 2;
+    return nbuf * (size_t)op->L2 * (size_t)lane_stride(tile) * pair_bytes(op->scalar, precision);
 }
 
 extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision, int32_t algorithm,
@@ -695,8 +1057,7 @@ extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int3
     // sized for any N: the partials are included whenever doubling may run
     int rc = resolve_algorithm(op, algorithm, 3, "moments_workspace_size", &doubling);
     if (rc) return rc;
-    *bytes = 2 * (size_t)op->L2 * (size_t)lane_stride(tile) * pair_bytes(op->scalar, precision) +
-             kConeDoubles * sizeof(double);
+    *bytes = tile_buffer_bytes(op, tile, precision) + kConeDoubles * sizeof(double);
     if (doubling) *bytes += (size_t)doubling_partial_bytes(op, tile, precision);
     return CBDG_OK;
 }
@@ -720,8 +1081,7 @@ extern "C" int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_si
     if (!start_sites || !mu_ee || !mu_he || !workspace)
         return fail(CBDG_EINVAL, "chebyshev_moments: start_sites, mu_ee, mu_he and workspace must not be NULL");
     const int64_t eff_tile = std::min<int64_t>(tile, n_start);
-    size_t need = 2 * (size_t)op->L2 * (size_t)lane_stride(eff_tile) * pair_bytes(op->scalar, precision) +
-                  kConeDoubles * sizeof(double);
+    size_t need = tile_buffer_bytes(op, eff_tile, precision) + kConeDoubles * sizeof(double);
     if (doubling) need += (size_t)doubling_partial_bytes(op, (int)eff_tile, precision);
     if (workspace_bytes < need)
         return fail(CBDG_EINVAL, "chebyshev_moments: workspace of %zu bytes is smaller than the %zu needed",

@@ -31,6 +31,8 @@ struct StepArgs {
     const int32_t *cone; // {x_min, x_max, y_min, y_max} of the tile's valid start
                          // sites, or null: steps n >= 2 skip strips and rows
                          // farther than n from that box (a_n is zero there)
+    void *out2;          // two-step pass: a_{n+1}
+    double *part_b;      // two-step pass: doubling partials of step n+1
 };
 
 // Lane stride of a tile of B vectors: B rounded up to the wavefront, plus
