@@ -9,8 +9,9 @@ package: the two share no code.  Inputs come from the seeded generators in
 Parts (each function cites the passage of the paper it follows):
   core.py   explicit sparse Hamiltonian of eq. (hamil2), the vector recursion
             of eq. (ref2) and its adjoint, in plain C (cbdg_oracle.c)
-  kpm.py    kernel factors, energy weights, the gap equation eq. (op1) and the
-            LDOS eq. (ldos), in NumPy FP64
+  kpm.py    kernel factors, energy weights (T = 0 closed forms, finite-T
+            quadrature), the gap equation eq. (op1), the LDOS eq. (ldos) and
+            the electron density, in NumPy FP64
   scf.py    the self-consistency loop (plain mixing)
 
 Readings of passages the paper leaves open are listed with the code that
@@ -19,12 +20,12 @@ uses them.
 from .core import (build_csr, bounds, moments, moments_backward, workload_csr, workload_bounds,
                    workload_moments, max_threads, ensure_built)
 from .kpm import (jackson, lorentz, sign_coefficients, sign_weight_coefficients, gap_weights, gap_map,
-                  ldos, ldos_weights, chebyshev_T)
+                  ldos, ldos_weights, chebyshev_T, thermal_coefficients, density, gap_map_thermal)
 from .scf import scf_plain
 
 __all__ = [
     "build_csr", "bounds", "moments", "moments_backward", "workload_csr", "workload_bounds",
     "workload_moments", "max_threads", "ensure_built", "jackson", "lorentz",
     "sign_coefficients", "sign_weight_coefficients", "gap_weights", "gap_map", "ldos", "ldos_weights",
-    "chebyshev_T", "scf_plain",
+    "chebyshev_T", "scf_plain", "thermal_coefficients", "density", "gap_map_thermal",
 ]

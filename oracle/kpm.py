@@ -120,3 +120,77 @@ def ldos(mu_ee, energies, a, b, kernel="jackson", lam=0.0):
     mu_ee = np.asarray(mu_ee, dtype=np.float64)
     W = ldos_weights(mu_ee.shape[-1], energies, a, b, kernel, lam)
     return mu_ee @ W.T
+
+
+def _theta(x):
+    return float(np.arccos(min(max(x, -1.0), 1.0)))
+
+
+def thermal_coefficients(N: int, a: float, b: float, T: float, E_c: float = 0.0,
+                         quantity: str = "gap") -> np.ndarray:
+    """Chebyshev coefficients c_n of the energy weights at temperature T, so
+    that w(a x + b) = sum_n c_n T_n(x) on [-1, 1]:
+      quantity "gap":     w(E) = 1 - 2 f(E) = tanh(E / 2T) on |E| < E_c (E_c <= 0:
+                          no cutoff), 0 outside -- the weight of eq. (op1);
+      quantity "density": w(E) = f(E) = 1 / (exp(E/T) + 1) -- the weight of the
+                          electron-density equation.
+    c_n = ((2 - delta_n0)/pi) int_0^pi w(a cos t + b) cos(n t) dt, each
+    integral by adaptive quadrature for the cosine weight (scipy QAWO),
+    split where w changes fastest (E = 0) and at the cutoff.  T = 0 gives
+    the step functions sign(E) and theta(-E).
+    """
+    from scipy import integrate
+    lo, hi = 0.0, np.pi
+    if quantity == "gap":
+        if E_c > 0:
+            lo, hi = _theta((E_c - b) / a), _theta((-E_c - b) / a)
+        if T > 0:
+            def w(t):
+                return np.tanh((a * np.cos(t) + b) / (2.0 * T))
+        else:
+            def w(t):
+                return np.sign(a * np.cos(t) + b)
+    elif quantity == "density":
+        if T > 0:
+            def w(t):
+                return 0.5 * (1.0 - np.tanh((a * np.cos(t) + b) / (2.0 * T)))
+        else:
+            def w(t):
+                return 1.0 if a * np.cos(t) + b < 0 else 0.0
+    else:
+        raise ValueError(quantity)
+    t0 = _theta(-b / a)
+    cuts = sorted({lo, hi, min(max(t0, lo), hi)})
+    c = np.zeros(N)
+    for n in range(N):
+        s = 0.0
+        for p, q in zip(cuts[:-1], cuts[1:]):
+            if q > p:
+                if n == 0:
+                    s += integrate.quad(w, p, q, limit=400, epsabs=1e-14, epsrel=1e-13)[0]
+                else:
+                    s += integrate.quad(w, p, q, weight="cos", wvar=n, limit=400, epsabs=1e-14)[0]
+        c[n] = (1.0 if n == 0 else 2.0) / np.pi * s
+    return c
+
+
+def density(mu_ee, a, b, T=0.0, kernel="jackson", lam=0.0):
+    """Electron density per site from the electron-density equation,
+    n_i = int [N_up(E,i) + N_down(E,i)] f(E) dE with N_down = N_up (singlet
+    pairing; the reading of the spin-down LDOS), i.e.
+    n_i = 2 sum_n g_n c_n mu^ee_n(i) with c_n the coefficients of f(a x + b)."""
+    mu_ee = np.asarray(mu_ee, dtype=np.float64)
+    N = mu_ee.shape[-1]
+    g = jackson(N) if kernel == "jackson" else lorentz(N, lam)
+    return 2.0 * mu_ee @ (g * thermal_coefficients(N, a, b, T, quantity="density"))
+
+
+def gap_map_thermal(mu_he, U, a, b, T, E_c=0.0, kernel="jackson", lam=0.0):
+    """Eq. (op1) at temperature T: Delta_i = (U/2) conj(sum_n g_n c_n mu^he_n(i))
+    with c_n the coefficients of tanh(E/2T) on |E| < E_c (reading of the
+    prefactor as in gap_map)."""
+    mu_he = np.asarray(mu_he)
+    N = mu_he.shape[-1]
+    g = jackson(N) if kernel == "jackson" else lorentz(N, lam)
+    s = mu_he @ (g * thermal_coefficients(N, a, b, T, E_c, "gap"))
+    return 0.5 * np.asarray(U) * np.conj(s)

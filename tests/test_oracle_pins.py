@@ -475,3 +475,89 @@ def test_moment_doubling_identities(case):
             B = np.sum(u_n * v_m - v_n * u_m)
             assert abs(2 * (-1) ** n * B - mu_he[0, 1] - mu_he[0, 2 * n - 1]) < 1e-13
             assert abs(mu_he[0, 2 * n]) < 1e-13
+
+
+# ------------------------------------------- finite temperature and density
+def test_thermal_coefficients_reduce_to_closed_forms_at_zero_temperature():
+    """T = 0: the quadrature gives the closed-form sign coefficients (pinned
+    above) and, for the density, those of theta(-E) written out here."""
+    N, a, b = 64, 5.3, 0.4
+    for E_c in (0.0, 2.1):
+        q = oracle.thermal_coefficients(N, a, b, 0.0, E_c, "gap")
+        assert np.max(np.abs(q - oracle.sign_weight_coefficients(N, a, b, E_c))) < 1e-10
+    q = oracle.thermal_coefficients(N, a, b, 0.0, quantity="density")
+    t0 = np.arccos(-b / a)
+    n = np.arange(1, N)
+    closed = np.concatenate([[(np.pi - t0) / np.pi], -2.0 * np.sin(n * t0) / (np.pi * n)])
+    assert np.max(np.abs(q - closed)) < 1e-10
+    # and a small temperature stays within O(T/a) of the step
+    qs = oracle.thermal_coefficients(N, a, b, 1e-4, quantity="density")
+    assert np.max(np.abs(qs - closed)) < 1e-4
+
+
+@pytest.mark.parametrize("quantity,T", [("gap", 0.3), ("density", 0.3)])
+def test_thermal_series_reconstructs_the_weight(quantity, T):
+    """Smooth weights: sum_n c_n T_n(x) converges to the weight itself, so the
+    c_n are its Chebyshev coefficients."""
+    a, b, N = 4.7, -0.3, 600
+    c = oracle.thermal_coefficients(N, a, b, T, 0.0, quantity)
+    x = np.linspace(-0.95, 0.95, 41)
+    E = a * x + b
+    w = np.tanh(E / (2 * T)) if quantity == "gap" else 1.0 / (np.exp(E / T) + 1.0)
+    series = np.polynomial.chebyshev.chebval(x, c)
+    assert np.max(np.abs(series - w)) < 1e-6
+
+
+def test_thermal_gap_coefficients_with_cutoff_equal_discrete_transform():
+    """With a cutoff the weight jumps at |E| = E_c; compare with the discrete
+    Chebyshev transform on M Chebyshev-Gauss nodes, whose error from the jumps
+    is O(1/M)."""
+    a, b, T, E_c, N, M = 4.7, -0.3, 0.5, 2.5, 200, 400000
+    c = oracle.thermal_coefficients(N, a, b, T, E_c, "gap")
+    t = np.pi * (np.arange(M) + 0.5) / M
+    E = a * np.cos(t) + b
+    w = np.tanh(E / (2 * T)) * (np.abs(E) < E_c)
+    n = np.arange(N)
+    d = np.where(n == 0, 1.0, 2.0) / M * (np.cos(np.outer(n, t)) @ w)
+    assert np.max(np.abs(c - d)) < 2e-5
+
+
+def test_finite_temperature_gap_and_density_approach_exact_ed():
+    """Physics checks against exact diagonalisation at T = 0.25: the error is
+    the Jackson broadening (width ~ pi a/N, much smaller than T), so it falls
+    as 1/N^2 -- 16x from N = 256 to 1024 (measured 2.1e-3 -> 1.4e-4):
+    Delta_i = (U/2) sum_k u_k(i) conj(v_k(i)) tanh(E_k/2T) and
+    n_i = 2 sum_k |u_k(i)|^2 f(E_k)."""
+    w = _small(Lx=4, Ly=4, seed=31)
+    _, _, a, b = oracle.workload_bounds(w)
+    T = 0.25
+    Et, V = ed.eig(w, a, b)
+    E = a * Et + b
+    L2 = w.L2
+    exact_gap = 0.5 * w.U * np.sum(V[:L2] * np.conj(V[L2:]) * np.tanh(E / (2 * T))[None, :], axis=1).real
+    exact_n = 2.0 * np.sum(np.abs(V[:L2]) ** 2 / (np.exp(E / T) + 1.0)[None, :], axis=1)
+    errs = []
+    for N in (256, 1024):
+        mu_ee, mu_he = oracle.workload_moments(w, a, b, N=N)
+        g = oracle.gap_map_thermal(mu_he, w.U, a, b, T).real
+        n = oracle.density(mu_ee, a, b, T)
+        errs.append((np.max(np.abs(g - exact_gap)), np.max(np.abs(n - exact_n))))
+    assert errs[0][0] > 12 * errs[1][0] and errs[0][1] > 12 * errs[1][1]
+    assert errs[1][0] < 3e-4 and errs[1][1] < 3e-4
+
+
+def test_density_of_a_free_lattice_counts_filled_states():
+    """Delta = 0, eps = 0: at T -> 0 the total electron number is twice the
+    number of tight-binding levels below mu (open square lattice, levels
+    -2t(cos(k_x) + cos(k_y)) with k = pi m/(L+1)); moments by the oracle,
+    N large."""
+    L, mu = 6, -0.3
+    w = W.Workload("free", L, L, W.OPEN, W.OPEN, 1.0, mu, 0.0, np.zeros(L * L), np.zeros(L * L),
+                   None, None, 2048, np.arange(L * L, dtype=np.int32), L * L)
+    a, b = 4.4, 0.0
+    mu_ee, _ = oracle.workload_moments(w, a, b)
+    n = oracle.density(mu_ee, a, b, T=0.02)
+    k = np.pi * np.arange(1, L + 1) / (L + 1)
+    levels = (-2 * (np.cos(k)[:, None] + np.cos(k)[None, :])).ravel() - mu
+    assert np.min(np.abs(levels)) > 0.1                     # no level near E = 0
+    assert abs(np.sum(n) - 2 * np.sum(levels < 0)) < 1e-3
