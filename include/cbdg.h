@@ -79,6 +79,11 @@ enum cbdg_kernel { CBDG_KERNEL_JACKSON = 0, CBDG_KERNEL_LORENTZ = 1 };
  *             Needs b == 0 (a spectrum centred by the rescaling).
  *   AUTO      DOUBLING when b == 0 and N >= 3, else DIRECT. */
 enum cbdg_algorithm { CBDG_ALG_AUTO = 0, CBDG_ALG_DIRECT = 1, CBDG_ALG_DOUBLING = 2 };
+/* Energy weight of a moment sum (cbdg_sum_coefficients):
+ *   GAP      1 - 2f(E) = tanh(E/2T) on |E| < E_c (E_c <= 0: no cutoff), the
+ *            weight of eq. (op1)
+ *   DENSITY  f(E) = 1/(exp(E/T) + 1), the weight of the electron density */
+enum cbdg_quantity { CBDG_QTY_GAP = 0, CBDG_QTY_DENSITY = 1 };
 
 /* Lattice geometry and number type (host struct).
  * Periodic directions need at least 3 sites. */
@@ -97,7 +102,8 @@ typedef struct cbdg_bounds {
 /* Kernel damping and energy weighting of the truncated expansion (host).
  *   kernel  CBDG_KERNEL_JACKSON (default) or CBDG_KERNEL_LORENTZ with
  *           parameter lambda (broadening lambda/N in rescaled units)
- *   T       temperature; only T = 0 is implemented (else EUNSUPPORTED)
+ *   T       temperature >= 0; sums with T > 0 take coefficients from
+ *           cbdg_sum_coefficients
  *   E_c     cutoff energy of the gap equation (<= 0: no cutoff)
  *   a, b    the operator's rescaling (from cbdg_bounds) */
 typedef struct cbdg_weights {
@@ -200,21 +206,54 @@ int cbdg_check_moments(const double *mu_ee, const void *mu_he, int64_t n_rows, i
                        int32_t scalar, double tol, int32_t *flag, void *stream);
 
 /*
- * One step of the T = 0 gap equation, eq. (op1), from the anomalous moments:
+ * Chebyshev coefficients of a weight of the moment sums, damped by the
+ * kernel: coeff[n] = g_n c_n with w(a x + b) = sum_n c_n T_n(x) and
+ *   CBDG_QTY_GAP      w(E) = 1 - 2f(E) = tanh(E/2T) on |E| < E_c (eq. (op1))
+ *   CBDG_QTY_DENSITY  w(E) = f(E) (the electron-density equation)
+ * at the weights' temperature T >= 0 (T = 0: sign(E) and theta(-E)).
+ * c_n = ((2 - delta_n0)/pi) int_0^pi w(a cos t + b) cos(n t) dt: closed form
+ * where |E| > 40 T, Gauss-Legendre panels (width <= min(1/(2N), T/(4a))) in
+ * between.  coeff: out [N] FP64 on the device.  EINVAL when E = 0 is outside
+ * [b - a, b + a] or T is too small for the panels (use T = 0).
+ */
+int cbdg_sum_coefficients(const cbdg_weights *w, int32_t N, int32_t quantity, double *coeff,
+                          void *stream);
+
+/*
+ * One step of the gap equation, eq. (op1), from the anomalous moments:
  *   Delta_new[r] = (U_r/2) conj( sum_n g_n c_n mu_he[r][n] )
  * where g_n is the kernel and c_n are the Chebyshev coefficients of the
- * weight (1 - 2f(E)) = sign(E) on |E| < E_c; then plain mixing
+ * weight (1 - 2f(E)) on |E| < E_c; then plain mixing
  *   delta_out[r] = (1 - alpha) delta_in[r] + alpha Delta_new[r]
  * and the residual *resid = max_r |Delta_new[r] - delta_in[r]|.
+ *   coeff      [N] g_n c_n from cbdg_sum_coefficients(CBDG_QTY_GAP), or NULL
+ *              for the built-in T = 0 weight sign(E) (EINVAL when T > 0)
  *   mu_he      [n_rows*N] FP64 (REAL) or complex128 (COMPLEX)
  *   U, U_rows  coupling: U_rows ([n_rows] FP64) if not NULL, else U
  *   delta_in   [n_rows], delta_out [n_rows] (may alias delta_in)
  *   resid      out, one FP64 on the device (NaN if any Delta_new is NaN)
  */
 int cbdg_gap_update(const void *mu_he, int64_t n_rows, int32_t N, int32_t scalar,
-                    const cbdg_weights *w, double U, const double *U_rows,
+                    const cbdg_weights *w, const double *coeff, double U, const double *U_rows,
                     const void *delta_in, double alpha, void *delta_out,
                     double *resid, void *stream);
+
+/*
+ * Electron density of the electron-density equation with the spin-down LDOS
+ * equal to the spin-up one (singlet pairing):
+ *   density[r] = 2 sum_n g_n c_n mu_ee[r][n],  c_n the coefficients of f(E)
+ *   coeff    [N] from cbdg_sum_coefficients(CBDG_QTY_DENSITY), or NULL for
+ *            the built-in T = 0 weight theta(-E) (EINVAL when T > 0)
+ *   density  out [n_rows] FP64
+ */
+int cbdg_density(const double *mu_ee, int64_t n_rows, int32_t N, const cbdg_weights *w,
+                 const double *coeff, double *density, void *stream);
+
+/* Transpose of cbdg_density: d_mu_ee[r][n] = 2 g_n c_n d_density[r]
+ * (overwritten). */
+int cbdg_density_backward(const double *d_density, int64_t n_rows, int32_t N,
+                          const cbdg_weights *w, const double *coeff, double *d_mu_ee,
+                          void *stream);
 
 /*
  * Local density of states per spin, eq. (ldos) with eq. (imag2):
@@ -230,11 +269,11 @@ int cbdg_ldos(const double *mu_ee, int64_t n_rows, int32_t N, const cbdg_weights
 /* Transpose of cbdg_gap_update for a REAL operator:
  *   d_mu_he[r][n] = alpha (U_r/2) g_n c_n d_delta_out[r]
  *   d_delta_in[r] = (1 - alpha) d_delta_out[r]        (if d_delta_in != NULL)
- * Outputs are overwritten.  COMPLEX returns EUNSUPPORTED. */
+ * coeff as for cbdg_gap_update.  Outputs are overwritten. */
 int cbdg_gap_update_backward(const double *d_delta_out, int64_t n_rows, int32_t N,
-                             const cbdg_weights *w, double U, const double *U_rows,
-                             double alpha, double *d_mu_he, double *d_delta_in,
-                             void *stream);
+                             const cbdg_weights *w, const double *coeff, double U,
+                             const double *U_rows, double alpha, double *d_mu_he,
+                             double *d_delta_in, void *stream);
 
 /* Transpose of cbdg_ldos:  d_mu_ee[r][n] = sum_m d_ldos[r][m] W[m][n]
  * (overwritten). */

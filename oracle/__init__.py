@@ -20,12 +20,12 @@ uses them.
 from .core import (build_csr, bounds, moments, moments_backward, workload_csr, workload_bounds,
                    workload_moments, max_threads, ensure_built)
 from .kpm import (jackson, lorentz, sign_coefficients, sign_weight_coefficients, gap_weights, gap_map,
-                  ldos, ldos_weights, chebyshev_T, thermal_coefficients, density, gap_map_thermal)
+                  ldos, ldos_weights, chebyshev_T, thermal_coefficients, thermal_gap_weights, density, gap_map_thermal)
 from .scf import scf_plain
 
 __all__ = [
     "build_csr", "bounds", "moments", "moments_backward", "workload_csr", "workload_bounds",
     "workload_moments", "max_threads", "ensure_built", "jackson", "lorentz",
     "sign_coefficients", "sign_weight_coefficients", "gap_weights", "gap_map", "ldos", "ldos_weights",
-    "chebyshev_T", "scf_plain", "thermal_coefficients", "density", "gap_map_thermal",
+    "chebyshev_T", "scf_plain", "thermal_coefficients", "thermal_gap_weights", "density", "gap_map_thermal",
 ]

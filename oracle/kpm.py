@@ -185,12 +185,17 @@ def density(mu_ee, a, b, T=0.0, kernel="jackson", lam=0.0):
     return 2.0 * mu_ee @ (g * thermal_coefficients(N, a, b, T, quantity="density"))
 
 
-def gap_map_thermal(mu_he, U, a, b, T, E_c=0.0, kernel="jackson", lam=0.0):
+def thermal_gap_weights(N, a, b, T, E_c=0.0, kernel="jackson", lam=0.0):
+    """g_n c_n of eq. (op1) at temperature T (c_n of tanh(E/2T) on |E| < E_c)."""
+    g = jackson(N) if kernel == "jackson" else lorentz(N, lam)
+    return g * thermal_coefficients(N, a, b, T, E_c, "gap")
+
+
+def gap_map_thermal(mu_he, U, a, b, T, E_c=0.0, kernel="jackson", lam=0.0, weights=None):
     """Eq. (op1) at temperature T: Delta_i = (U/2) conj(sum_n g_n c_n mu^he_n(i))
     with c_n the coefficients of tanh(E/2T) on |E| < E_c (reading of the
-    prefactor as in gap_map)."""
+    prefactor as in gap_map).  weights: precomputed thermal_gap_weights."""
     mu_he = np.asarray(mu_he)
     N = mu_he.shape[-1]
-    g = jackson(N) if kernel == "jackson" else lorentz(N, lam)
-    s = mu_he @ (g * thermal_coefficients(N, a, b, T, E_c, "gap"))
-    return 0.5 * np.asarray(U) * np.conj(s)
+    wts = thermal_gap_weights(N, a, b, T, E_c, kernel, lam) if weights is None else weights
+    return 0.5 * np.asarray(U) * np.conj(mu_he @ wts)

@@ -23,6 +23,7 @@ CBDG_REAL, CBDG_COMPLEX = 0, 1
 CBDG_FP64, CBDG_FP32_ACC64 = 0, 1
 CBDG_KERNEL_JACKSON, CBDG_KERNEL_LORENTZ = 0, 1
 CBDG_ALG_AUTO, CBDG_ALG_DIRECT, CBDG_ALG_DOUBLING = 0, 1, 2
+CBDG_QTY_GAP, CBDG_QTY_DENSITY = 0, 1
 
 _NAMES = {CBDG_EINVAL: "EINVAL", CBDG_ENOMEM: "ENOMEM", CBDG_EHIP: "EHIP",
           CBDG_EBOUNDS: "EBOUNDS", CBDG_EUNSUPPORTED: "EUNSUPPORTED"}
@@ -62,10 +63,13 @@ SIGNATURES = {
     "cbdg_moments_workspace_size": [_vp, _i32, _i32, _i32, C.POINTER(_sz)],
     "cbdg_chebyshev_moments": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp],
     "cbdg_check_moments": [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _vp],
-    "cbdg_gap_update": [_vp, _i64, _i32, _i32, C.POINTER(cbdg_weights), _f64, _vp, _vp,
+    "cbdg_sum_coefficients": [C.POINTER(cbdg_weights), _i32, _i32, _vp, _vp],
+    "cbdg_gap_update": [_vp, _i64, _i32, _i32, C.POINTER(cbdg_weights), _vp, _f64, _vp, _vp,
                         _f64, _vp, _vp, _vp],
+    "cbdg_density": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _vp, _vp, _vp],
+    "cbdg_density_backward": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _vp, _vp, _vp],
     "cbdg_ldos": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _vp, _i32, _vp, _vp],
-    "cbdg_gap_update_backward": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _f64, _vp, _f64,
+    "cbdg_gap_update_backward": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _vp, _f64, _vp, _f64,
                                  _vp, _vp, _vp],
     "cbdg_ldos_backward": [_vp, _i64, _i32, C.POINTER(cbdg_weights), _vp, _i32, _vp, _vp],
     "cbdg_backward_workspace_size": [_vp, _i32, _i32, _i32, _i32, C.POINTER(_sz)],
@@ -120,6 +124,9 @@ cbdg_op_bounds = _call("cbdg_op_bounds")
 cbdg_moments_workspace_size = _call("cbdg_moments_workspace_size")
 cbdg_chebyshev_moments = _call("cbdg_chebyshev_moments")
 cbdg_check_moments = _call("cbdg_check_moments")
+cbdg_sum_coefficients = _call("cbdg_sum_coefficients")
+cbdg_density = _call("cbdg_density")
+cbdg_density_backward = _call("cbdg_density_backward")
 cbdg_gap_update = _call("cbdg_gap_update")
 cbdg_ldos = _call("cbdg_ldos")
 cbdg_gap_update_backward = _call("cbdg_gap_update_backward")

@@ -100,8 +100,8 @@ class Operator:
         L.cbdg_op_update_delta(self.handle, _ptr(delta, ddt, "delta"),
                                _ptr(delta_bond, ddt, "delta_bond"), _stream())
 
-    def weights(self, kernel="jackson", lam=0.0, E_c=0.0):
-        return weights(self.bounds.a, self.bounds.b, kernel, lam, 0.0, E_c)
+    def weights(self, kernel="jackson", lam=0.0, E_c=0.0, T=0.0):
+        return weights(self.bounds.a, self.bounds.b, kernel, lam, T, E_c)
 
     def close(self):
         if getattr(self, "_alive", False):
@@ -159,18 +159,37 @@ def check_moments(mu_ee: torch.Tensor, mu_he: torch.Tensor, tol: float = 1e-9) -
     return int(flag.item()) == 0
 
 
+def sum_coefficients(w: L.cbdg_weights, N: int, quantity: int = L.CBDG_QTY_GAP,
+                     device="cuda") -> torch.Tensor:
+    """Damped Chebyshev coefficients g_n c_n of the gap (tanh(E/2T) on
+    |E| < E_c) or density (f(E)) weight at the weights' temperature."""
+    out = torch.empty(int(N), dtype=torch.float64, device=device)
+    L.cbdg_sum_coefficients(C.byref(w), int(N), int(quantity), _ptr(out, torch.float64, "coeff"), _stream())
+    return out
+
+
+def _coeff_for(w, N, quantity, coeff, device):
+    if coeff is None and w.T > 0.0:
+        coeff = sum_coefficients(w, N, quantity, device)
+    return coeff
+
+
 def gap_update(mu_he: torch.Tensor, w: L.cbdg_weights, U: float, delta_in: torch.Tensor,
                alpha: float = 1.0, U_rows: Optional[torch.Tensor] = None,
-               delta_out: Optional[torch.Tensor] = None, resid: Optional[torch.Tensor] = None):
+               delta_out: Optional[torch.Tensor] = None, resid: Optional[torch.Tensor] = None,
+               coeff: Optional[torch.Tensor] = None):
+    """coeff: g_n c_n of the gap weight (computed here when T > 0 and not given)."""
     n, N = mu_he.shape
     cplx = mu_he.is_complex()
+    coeff = _coeff_for(w, N, L.CBDG_QTY_GAP, coeff, mu_he.device)
     if delta_out is None:
         delta_out = torch.empty_like(delta_in)
     if resid is None:
         resid = torch.empty(1, dtype=torch.float64, device=mu_he.device)
     ddt = torch.complex128 if cplx else torch.float64
     L.cbdg_gap_update(_ptr(mu_he, ddt, "mu_he"), n, N, L.CBDG_COMPLEX if cplx else L.CBDG_REAL,
-                      C.byref(w), float(U), _ptr(U_rows, torch.float64, "U_rows"),
+                      C.byref(w), _ptr(coeff, torch.float64, "coeff"), float(U),
+                      _ptr(U_rows, torch.float64, "U_rows"),
                       _ptr(delta_in, ddt, "delta_in"), float(alpha), _ptr(delta_out, ddt, "delta_out"),
                       _ptr(resid, torch.float64, "resid"), _stream())
     return delta_out, resid
@@ -190,15 +209,38 @@ def ldos(mu_ee: torch.Tensor, w: L.cbdg_weights, energies: torch.Tensor,
 
 def gap_update_backward(d_delta_out: torch.Tensor, N: int, w: L.cbdg_weights, U: float,
                         alpha: float = 1.0, U_rows: Optional[torch.Tensor] = None,
-                        want_delta_in: bool = True):
+                        want_delta_in: bool = True, coeff: Optional[torch.Tensor] = None):
     n = int(d_delta_out.numel())
     d_mu = torch.empty((n, N), dtype=torch.float64, device=d_delta_out.device)
     d_in = torch.empty_like(d_delta_out) if want_delta_in else None
+    coeff = _coeff_for(w, N, L.CBDG_QTY_GAP, coeff, d_delta_out.device)
     L.cbdg_gap_update_backward(_ptr(d_delta_out, torch.float64, "d_delta_out"), n, int(N), C.byref(w),
-                               float(U), _ptr(U_rows, torch.float64, "U_rows"), float(alpha),
+                               _ptr(coeff, torch.float64, "coeff"), float(U), _ptr(U_rows, torch.float64, "U_rows"), float(alpha),
                                _ptr(d_mu, torch.float64, "d_mu_he"), _ptr(d_in, torch.float64, "d_delta_in"),
                                _stream())
     return d_mu, d_in
+
+
+def density(mu_ee: torch.Tensor, w: L.cbdg_weights, coeff: Optional[torch.Tensor] = None,
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Electron density per site, 2 sum_n g_n c_n mu_ee_n (f(E) weight)."""
+    n, N = mu_ee.shape
+    coeff = _coeff_for(w, N, L.CBDG_QTY_DENSITY, coeff, mu_ee.device)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=mu_ee.device)
+    L.cbdg_density(_ptr(mu_ee, torch.float64, "mu_ee"), n, N, C.byref(w), _ptr(coeff, torch.float64, "coeff"),
+                   _ptr(out, torch.float64, "density"), _stream())
+    return out
+
+
+def density_backward(d_density: torch.Tensor, N: int, w: L.cbdg_weights,
+                     coeff: Optional[torch.Tensor] = None) -> torch.Tensor:
+    n = int(d_density.numel())
+    coeff = _coeff_for(w, N, L.CBDG_QTY_DENSITY, coeff, d_density.device)
+    d_mu = torch.empty((n, N), dtype=torch.float64, device=d_density.device)
+    L.cbdg_density_backward(_ptr(d_density, torch.float64, "d_density"), n, int(N), C.byref(w),
+                            _ptr(coeff, torch.float64, "coeff"), _ptr(d_mu, torch.float64, "d_mu_ee"), _stream())
+    return d_mu
 
 
 def ldos_backward(d_ldos: torch.Tensor, N: int, w: L.cbdg_weights, energies: torch.Tensor):

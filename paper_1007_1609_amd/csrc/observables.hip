@@ -11,6 +11,9 @@
 // th_lo = acos((-E_c - b)/a) (0 and pi without a cutoff), so
 //   c_0 = (2 th_0 - th_hi - th_lo)/pi,
 //   c_n = 2 (2 sin(n th_0) - sin(n th_hi) - sin(n th_lo)) / (pi n).
+// At T > 0 the weights tanh(E/2T) (gap) and f(E) (electron density) have no
+// closed form; cbdg_sum_coefficients integrates them (k_sum_coeff) and the
+// sums take those coefficients instead.
 #include "common.hpp"
 
 #include <algorithm>
@@ -23,6 +26,7 @@ struct WeightParams {
     int kernel;
     double lambda;
     double th0, thh, thl;  // angles of the sign weight
+    const double *coeff;   // damped coefficients g_n c_n replacing the T = 0 ones, or null
 };
 
 __device__ inline double kernel_factor(int n, const WeightParams &P)
@@ -39,7 +43,17 @@ __device__ inline double sign_coefficient(int n, const WeightParams &P)
     return 2.0 * (2.0 * sin(n * P.th0) - sin(n * P.thh) - sin(n * P.thl)) / (M_PI * n);
 }
 
-static int make_weights(const cbdg_weights *w, int N, bool need_sign, WeightParams &P, const char *who)
+// theta(-E) = 1 for theta > th_0: c_0 = (pi - th_0)/pi, c_n = -2 sin(n th_0)/(pi n)
+__device__ inline double step_coefficient(int n, double th0)
+{
+    if (n == 0) return (M_PI - th0) / M_PI;
+    return -2.0 * sin(n * th0) / (M_PI * n);
+}
+
+// w->T must be 0 unless the caller passes coefficients (need_sign: the sum
+// uses the T-dependent weight).
+static int make_weights(const cbdg_weights *w, int N, bool need_sign, WeightParams &P, const char *who,
+                        const double *coeff = nullptr)
 {
     if (!w) return fail(CBDG_EINVAL, "%s: weights must not be NULL", who);
     if (w->kernel != CBDG_KERNEL_JACKSON && w->kernel != CBDG_KERNEL_LORENTZ)
@@ -48,12 +62,14 @@ static int make_weights(const cbdg_weights *w, int N, bool need_sign, WeightPara
         return fail(CBDG_EINVAL, "%s: the Lorentz kernel needs lambda > 0", who);
     if (!(w->a > 0.0) || !std::isfinite(w->a) || !std::isfinite(w->b))
         return fail(CBDG_EINVAL, "%s: weights need a finite a > 0 and finite b", who);
-    if (w->T != 0.0)
-        return fail(CBDG_EUNSUPPORTED, "%s: only T = 0 weights are implemented", who);
+    if (!(w->T >= 0.0) || !std::isfinite(w->T)) return fail(CBDG_EINVAL, "%s: T must be finite and >= 0", who);
+    if (need_sign && w->T > 0.0 && !coeff)
+        return fail(CBDG_EINVAL, "%s: T > 0 needs the coefficients of cbdg_sum_coefficients", who);
     P.N = N;
     P.kernel = w->kernel;
     P.lambda = w->lambda;
     P.th0 = P.thh = P.thl = 0.0;
+    P.coeff = need_sign ? coeff : nullptr;
     if (need_sign) {
         const double x0 = -w->b / w->a;
         if (!(std::fabs(x0) < 1.0)) return fail(CBDG_EINVAL, "%s: E = 0 lies outside the rescaled interval", who);
@@ -95,7 +111,8 @@ __global__ __launch_bounds__(kBlock) void k_gap(GapArgs A)
 {
     extern __shared__ double wt[];
     const int N = A.P.N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) wt[n] = kernel_factor(n, A.P) * sign_coefficient(n, A.P);
+    for (int n = threadIdx.x; n < N; n += blockDim.x)
+        wt[n] = A.P.coeff ? A.P.coeff[n] : kernel_factor(n, A.P) * sign_coefficient(n, A.P);
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int wpb = blockDim.x / kWave;
@@ -246,13 +263,141 @@ __global__ __launch_bounds__(kBlock) void k_gap_bwd(GapBwdArgs A)
 {
     extern __shared__ double wt[];
     const int N = A.P.N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) wt[n] = kernel_factor(n, A.P) * sign_coefficient(n, A.P);
+    for (int n = threadIdx.x; n < N; n += blockDim.x)
+        wt[n] = A.P.coeff ? A.P.coeff[n] : kernel_factor(n, A.P) * sign_coefficient(n, A.P);
     __syncthreads();
     for (int64_t r = blockIdx.x; r < A.rows; r += gridDim.x) {
         const double g = A.dout[r];
         const double f = A.alpha * 0.5 * (A.Urows ? A.Urows[r] : A.U) * g;
         for (int n = threadIdx.x; n < N; n += blockDim.x) A.dmu[r * N + n] = f * wt[n];
         if (threadIdx.x == 0 && A.din) A.din[r] = (1.0 - A.alpha) * g;
+    }
+}
+
+// Chebyshev coefficients of the finite-T weights, one workgroup per n:
+//   c_n = ((2 - delta_n0)/pi) int w(a cos t + b) cos(n t) dt  over [t_lo, t_hi]
+// (the cutoff range for the gap, [0, pi] for the density).  Outside the
+// transition zone |E| < 40 T the weight is constant to 1e-17 (+1 / -1 for
+// tanh(E/2T), 0 / 1 for f(E)) and its pieces integrate in closed form; the
+// zone is split into P panels of 8-point Gauss-Legendre nodes, panel width at
+// most 1/(2N) (cos(n t)) and T/(4a) (the weight).  Panels are shared out over
+// the threads in a fixed order and reduced in a fixed tree: reproducible bits.
+struct CoeffArgs {
+    int N;
+    int quantity;
+    WeightParams P;     // kernel factors
+    double a, b, T;
+    double lo, hi;      // integration range in t
+    double z0, z1;      // transition zone (z0 < z1), clipped to [lo, hi]
+    int64_t panels;
+    double gx[8], gw[8];  // Gauss-Legendre nodes and weights on [-1, 1]
+    double *out;
+};
+
+__device__ inline double piece(int n, double p, double q)
+{
+    if (!(q > p)) return 0.0;
+    return n == 0 ? q - p : (sin(n * q) - sin(n * p)) / n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_coeff(CoeffArgs A)
+{
+    const int n = blockIdx.x;
+    const bool gap = A.quantity == CBDG_QTY_GAP;
+    double acc = 0.0;
+    if (A.z1 > A.z0) {
+        const double h = (A.z1 - A.z0) / (double)A.panels;
+        for (int64_t p = threadIdx.x; p < A.panels; p += blockDim.x) {
+            const double c = A.z0 + (p + 0.5) * h;
+            double sp = 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const double t = c + 0.5 * h * A.gx[k];
+                const double th = tanh((A.a * cos(t) + A.b) / (2.0 * A.T));
+                const double wv = gap ? th : 0.5 * (1.0 - th);
+                sp += A.gw[k] * wv * cos(n * t);
+            }
+            acc += 0.5 * h * sp;
+        }
+    }
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // constant pieces: t < z0 is E above the zone, t > z1 below it
+        double cst;
+        if (gap) cst = piece(n, A.lo, fmin(A.z0, A.hi)) - piece(n, fmax(A.z1, A.lo), A.hi);
+        else cst = piece(n, fmax(A.z1, A.lo), A.hi);
+        const double c = (n == 0 ? 1.0 : 2.0) / M_PI * (cst + red[0]);
+        A.out[n] = kernel_factor(n, A.P) * c;
+    }
+}
+
+struct DensArgs {
+    const double *mu;
+    int64_t rows;
+    WeightParams P;
+    double th0;
+    double *out;
+};
+
+// n_i = 2 sum_n g_n c_n mu_ee_n(i): one wavefront per row, weights in LDS.
+__global__ __launch_bounds__(kBlock) void k_density(DensArgs A)
+{
+    extern __shared__ double wt[];
+    const int N = A.P.N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x)
+        wt[n] = A.P.coeff ? A.P.coeff[n] : kernel_factor(n, A.P) * step_coefficient(n, A.th0);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + wv; r < A.rows; r += (int64_t)gridDim.x * wpb) {
+        const double *row = A.mu + r * N;
+        double s = 0.0;
+        for (int n = lane; n < N; n += kWave) s += wt[n] * row[n];
+        s = wave_sum(s);
+        if (lane == 0) A.out[r] = 2.0 * s;
+    }
+}
+
+// d mu_ee[r][n] = 2 g_n c_n d n[r]
+__global__ __launch_bounds__(kBlock) void k_density_bwd(const double *dn, int64_t rows, WeightParams P, double th0,
+                                                       double *dmu)
+{
+    extern __shared__ double wt[];
+    const int N = P.N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x)
+        wt[n] = P.coeff ? P.coeff[n] : kernel_factor(n, P) * step_coefficient(n, th0);
+    __syncthreads();
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
+        for (int n = threadIdx.x; n < N; n += blockDim.x) dmu[r * N + n] = 2.0 * dn[r] * wt[n];
+}
+
+// Nodes and weights of n-point Gauss-Legendre quadrature on [-1, 1]: roots of
+// P_n by Newton's method from cos(pi (i + 3/4) / (n + 1/2)), weights
+// 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss_legendre(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
 }
 
@@ -269,7 +414,7 @@ static int lds_ok(size_t bytes, const char *who)
 using namespace cbdg;
 
 extern "C" int cbdg_gap_update(const void *mu_he, int64_t n_rows, int32_t N, int32_t scalar,
-                               const cbdg_weights *w, double U, const double *U_rows,
+                               const cbdg_weights *w, const double *coeff, double U, const double *U_rows,
                                const void *delta_in, double alpha, void *delta_out, double *resid,
                                void *stream)
 {
@@ -279,7 +424,7 @@ extern "C" int cbdg_gap_update(const void *mu_he, int64_t n_rows, int32_t N, int
     if (!resid) return fail(CBDG_EINVAL, "gap_update: resid must not be NULL");
     if (!std::isfinite(U) || !std::isfinite(alpha)) return fail(CBDG_EINVAL, "gap_update: U and alpha must be finite");
     WeightParams P;
-    int rc = make_weights(w, N, true, P, "gap_update");
+    int rc = make_weights(w, N, true, P, "gap_update", coeff);
     if (rc) return rc;
     rc = lds_ok((size_t)N * 8, "gap_update");
     if (rc) return rc;
@@ -315,13 +460,14 @@ extern "C" int cbdg_ldos(const double *mu_ee, int64_t n_rows, int32_t N, const c
 }
 
 extern "C" int cbdg_gap_update_backward(const double *d_delta_out, int64_t n_rows, int32_t N,
-                                        const cbdg_weights *w, double U, const double *U_rows,
-                                        double alpha, double *d_mu_he, double *d_delta_in, void *stream)
+                                        const cbdg_weights *w, const double *coeff, double U,
+                                        const double *U_rows, double alpha, double *d_mu_he,
+                                        double *d_delta_in, void *stream)
 {
     clear_error();
     if (n_rows < 0 || N < 1) return fail(CBDG_EINVAL, "gap_update_backward: need n_rows >= 0 and N >= 1");
     WeightParams P;
-    int rc = make_weights(w, N, true, P, "gap_update_backward");
+    int rc = make_weights(w, N, true, P, "gap_update_backward", coeff);
     if (rc) return rc;
     rc = lds_ok((size_t)N * 8, "gap_update_backward");
     if (rc) return rc;
@@ -347,5 +493,89 @@ extern "C" int cbdg_ldos_backward(const double *d_ldos, int64_t n_rows, int32_t 
     LdosBwdArgs A{d_ldos, n_rows, P, w->a, w->b, energies, n_E, d_mu_ee};
     hipLaunchKernelGGL(k_ldos_bwd, dim3(grid_rows(n_rows, 1)), dim3(kBlock), 0, as_stream(stream), A);
     CBDG_CHECK_LAUNCH("k_ldos_bwd");
+    return CBDG_OK;
+}
+
+extern "C" int cbdg_sum_coefficients(const cbdg_weights *w, int32_t N, int32_t quantity, double *coeff,
+                                     void *stream)
+{
+    clear_error();
+    if (N < 1) return fail(CBDG_EINVAL, "sum_coefficients: N must be >= 1");
+    if (quantity != CBDG_QTY_GAP && quantity != CBDG_QTY_DENSITY)
+        return fail(CBDG_EINVAL, "sum_coefficients: unknown quantity %d", quantity);
+    if (!coeff) return fail(CBDG_EINVAL, "sum_coefficients: coeff must not be NULL");
+    WeightParams P;
+    int rc = make_weights(w, N, false, P, "sum_coefficients");
+    if (rc) return rc;
+    const double a = w->a, b = w->b, T = w->T;
+    if (!(std::fabs(b / a) < 1.0)) return fail(CBDG_EINVAL, "sum_coefficients: E = 0 lies outside the rescaled interval");
+    auto th = [&](double x) { return std::acos(std::min(1.0, std::max(-1.0, x))); };
+    CoeffArgs A{};
+    A.N = N;
+    A.quantity = quantity;
+    A.P = P;
+    A.a = a; A.b = b; A.T = T;
+    A.lo = 0.0; A.hi = M_PI;
+    if (quantity == CBDG_QTY_GAP && w->E_c > 0.0) { A.lo = th((w->E_c - b) / a); A.hi = th((-w->E_c - b) / a); }
+    const double Z = 40.0 * T;  // |E| beyond which tanh(E/2T) = +-1 and f(E) = 0 or 1 to 1e-17
+    A.z0 = std::max(th((Z - b) / a), A.lo);
+    A.z1 = std::min(th((-Z - b) / a), A.hi);
+    if (T == 0.0) A.z0 = A.z1 = th(-b / a);
+    A.panels = 0;
+    if (A.z1 > A.z0) {
+        const double hmax = std::min(0.5 / N, 0.25 * T / a);
+        const double np = std::ceil((A.z1 - A.z0) / hmax);
+        if (!(np < 4.0e7)) return fail(CBDG_EINVAL, "sum_coefficients: T = %g too small for the quadrature; use T = 0", T);
+        A.panels = (int64_t)np;
+    }
+    gauss_legendre(8, A.gx, A.gw);
+    A.out = coeff;
+    hipLaunchKernelGGL(k_sum_coeff, dim3((unsigned)N), dim3(kBlock), 0, as_stream(stream), A);
+    CBDG_CHECK_LAUNCH("k_sum_coeff");
+    return CBDG_OK;
+}
+
+extern "C" int cbdg_density(const double *mu_ee, int64_t n_rows, int32_t N, const cbdg_weights *w,
+                            const double *coeff, double *density, void *stream)
+{
+    clear_error();
+    if (n_rows < 0 || N < 1) return fail(CBDG_EINVAL, "density: need n_rows >= 0 and N >= 1");
+    WeightParams P;
+    int rc = make_weights(w, N, false, P, "density");
+    if (rc) return rc;
+    if (w->T > 0.0 && !coeff) return fail(CBDG_EINVAL, "density: T > 0 needs the coefficients of cbdg_sum_coefficients");
+    if (!(std::fabs(w->b / w->a) < 1.0)) return fail(CBDG_EINVAL, "density: E = 0 lies outside the rescaled interval");
+    P.coeff = coeff;
+    rc = lds_ok((size_t)N * 8, "density");
+    if (rc) return rc;
+    if (n_rows == 0) return CBDG_OK;
+    if (!mu_ee || !density) return fail(CBDG_EINVAL, "density: mu_ee and density must not be NULL");
+    DensArgs A{mu_ee, n_rows, P, std::acos(-w->b / w->a), density};
+    hipLaunchKernelGGL(k_density, dim3(grid_rows(n_rows, kBlock / kWave)), dim3(kBlock), (size_t)N * 8,
+                       as_stream(stream), A);
+    CBDG_CHECK_LAUNCH("k_density");
+    return CBDG_OK;
+}
+
+extern "C" int cbdg_density_backward(const double *d_density, int64_t n_rows, int32_t N, const cbdg_weights *w,
+                                     const double *coeff, double *d_mu_ee, void *stream)
+{
+    clear_error();
+    if (n_rows < 0 || N < 1) return fail(CBDG_EINVAL, "density_backward: need n_rows >= 0 and N >= 1");
+    WeightParams P;
+    int rc = make_weights(w, N, false, P, "density_backward");
+    if (rc) return rc;
+    if (w->T > 0.0 && !coeff)
+        return fail(CBDG_EINVAL, "density_backward: T > 0 needs the coefficients of cbdg_sum_coefficients");
+    if (!(std::fabs(w->b / w->a) < 1.0))
+        return fail(CBDG_EINVAL, "density_backward: E = 0 lies outside the rescaled interval");
+    P.coeff = coeff;
+    rc = lds_ok((size_t)N * 8, "density_backward");
+    if (rc) return rc;
+    if (n_rows == 0) return CBDG_OK;
+    if (!d_density || !d_mu_ee) return fail(CBDG_EINVAL, "density_backward: d_density and d_mu_ee must not be NULL");
+    hipLaunchKernelGGL(k_density_bwd, dim3(grid_rows(n_rows, 1)), dim3(kBlock), (size_t)N * 8, as_stream(stream),
+                       d_density, n_rows, P, std::acos(-w->b / w->a), d_mu_ee);
+    CBDG_CHECK_LAUNCH("k_density_bwd");
     return CBDG_OK;
 }

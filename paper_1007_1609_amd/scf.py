@@ -18,7 +18,7 @@ from typing import List, Optional
 import torch
 
 from . import _lib as L
-from .api import Operator, chebyshev_moments, gap_update, moments_workspace_bytes, workspace
+from .api import Operator, chebyshev_moments, gap_update, moments_workspace_bytes, sum_coefficients, workspace
 
 
 @dataclass
@@ -34,12 +34,14 @@ class ScfResult:
 def plain_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
                  precision: int = L.CBDG_FP64, alpha: float = 1.0, tol: float = 1e-6,
                  max_iter: int = 200, kernel: str = "jackson", E_c: float = 0.0,
-                 sites: Optional[torch.Tensor] = None, callback=None) -> ScfResult:
-    """Delta <- (1 - alpha) Delta + alpha F(Delta) until max|F(Delta) - Delta| < tol."""
+                 sites: Optional[torch.Tensor] = None, callback=None, T: float = 0.0) -> ScfResult:
+    """Delta <- (1 - alpha) Delta + alpha F(Delta) until max|F(Delta) - Delta| < tol
+    (temperature T: the gap weight tanh(E/2T), coefficients computed once)."""
     dev = delta0.device
     if sites is None:
         sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
-    w = op.weights(kernel, E_c=E_c)
+    w = op.weights(kernel, E_c=E_c, T=T)
+    coeff = sum_coefficients(w, N, L.CBDG_QTY_GAP, dev) if T > 0 else None
     ws = workspace(moments_workspace_bytes(op, min(tile, sites.numel()), precision), dev)
     n = sites.numel()
     mu_ee = torch.empty((n, N), dtype=torch.float64, device=dev)
@@ -54,7 +56,7 @@ def plain_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int
     it = 0
     for it in range(1, max_iter + 1):
         chebyshev_moments(op, sites, N, tile, precision, ws=ws, out=(mu_ee, mu_he))
-        gap_update(mu_he, w, U, delta, alpha, delta_out=nxt, resid=resid)
+        gap_update(mu_he, w, U, delta, alpha, delta_out=nxt, resid=resid, coeff=coeff)
         r = float(resid.item())
         hist.append(r)
         delta, nxt = nxt, delta
@@ -126,7 +128,7 @@ def _gmres(matvec, rhs, tol, restart=30, maxiter=60):
 def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
                   tol: float = 1e-6, max_newton: int = 30, jv: str = "vjp", fd_step: float = 1e-7,
                   gmres_tol: float = 1e-2, warmup_tol: float = 1e-2, max_warmup: int = 100,
-                  kernel: str = "jackson", callback=None) -> ScfResult:
+                  kernel: str = "jackson", callback=None, T: float = 0.0) -> ScfResult:
     """Solve F(Delta) = Delta with inexact Newton steps (J_F - I) d = -(F - Delta).
 
     The gap map has more than one fixed point (Delta -> -Delta, and the
@@ -147,7 +149,8 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
         raise L.CbdgError(L.CBDG_EUNSUPPORTED, "newton_krylov", "real operators only")
     dev = delta0.device
     sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
-    w = op.weights(kernel)
+    w = op.weights(kernel, T=T)
+    coeff = sum_coefficients(w, N, L.CBDG_QTY_GAP, dev) if T > 0 else None
     ws = workspace(moments_workspace_bytes(op, min(tile, op.L2), L.CBDG_FP64), dev)
     mu_ee = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
     mu_he = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
@@ -158,7 +161,7 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
     def F(delta_t):
         op.update_delta(delta_t)
         chebyshev_moments(op, sites, N, tile, L.CBDG_FP64, ws=ws, out=(mu_ee, mu_he))
-        new, _ = gap_update(mu_he, w, U, delta_t, 1.0, resid=resid)
+        new, _ = gap_update(mu_he, w, U, delta_t, 1.0, resid=resid, coeff=coeff)
         counts["F"] += 1
         return new
 
@@ -199,7 +202,7 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
                 counts["F"] -= 1
                 jvv = (Fp - Fd_now) / h
             else:
-                d_mu, _ = gap_update_backward(v, N, w, U, 1.0, want_delta_in=False)
+                d_mu, _ = gap_update_backward(v, N, w, U, 1.0, want_delta_in=False, coeff=coeff)
                 _, jvv = chebyshev_moments_backward(op, sites, N, tile, None, d_mu, ws=bw_ws["ws"])
             return (jvv - v).cpu().numpy()
 

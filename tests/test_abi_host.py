@@ -80,15 +80,25 @@ def test_host_validation_without_gpu():
     n = C.c_size_t()
     assert lib.cbdg_moments_workspace_size(None, 64, 0, 0, C.byref(n)) == L.CBDG_EINVAL
     assert lib.cbdg_chebyshev_moments(None, None, 0, 8, 8, 0, 0, None, 0, None, None, None) == L.CBDG_EINVAL
-    # gap update: bad N, bad kernel, finite temperature, E = 0 outside the interval
+    # gap update: bad N, bad kernel, finite temperature without coefficients,
+    # E = 0 outside the interval
     w = L.cbdg_weights(0, 0.0, 0.0, 0.0, 2.0, 0.0)
-    assert lib.cbdg_gap_update(None, 4, 0, 0, C.byref(w), 1.0, None, None, 1.0, None, 8, None) == L.CBDG_EINVAL
+    assert lib.cbdg_gap_update(None, 4, 0, 0, C.byref(w), None, 1.0, None, None, 1.0, None, 8, None) == L.CBDG_EINVAL
     bad = L.cbdg_weights(7, 0.0, 0.0, 0.0, 2.0, 0.0)
-    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(bad), 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
+    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(bad), None, 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
     hot = L.cbdg_weights(0, 0.0, 0.1, 0.0, 2.0, 0.0)
-    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(hot), 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EUNSUPPORTED
+    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(hot), None, 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
+    assert "cbdg_sum_coefficients" in L.cbdg_last_error()
+    neg = L.cbdg_weights(0, 0.0, -0.1, 0.0, 2.0, 0.0)
+    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(neg), 8, 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
     off = L.cbdg_weights(0, 0.0, 0.0, 0.0, 2.0, 5.0)
-    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(off), 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
+    assert lib.cbdg_gap_update(8, 4, 8, 0, C.byref(off), None, 1.0, None, 8, 1.0, 8, 8, None) == L.CBDG_EINVAL
+    # coefficients: bad quantity, NULL output, E = 0 outside; density without coefficients at T > 0
+    assert lib.cbdg_sum_coefficients(C.byref(hot), 16, 5, 8, None) == L.CBDG_EINVAL
+    assert lib.cbdg_sum_coefficients(C.byref(hot), 16, 0, None, None) == L.CBDG_EINVAL
+    assert lib.cbdg_sum_coefficients(C.byref(off), 16, 1, 8, None) == L.CBDG_EINVAL
+    assert lib.cbdg_density(8, 4, 8, C.byref(hot), None, 8, None) == L.CBDG_EINVAL
+    assert lib.cbdg_density_backward(8, 4, 8, C.byref(hot), None, 8, None) == L.CBDG_EINVAL
     lor = L.cbdg_weights(1, 0.0, 0.0, 0.0, 2.0, 0.0)
     assert lib.cbdg_ldos(8, 4, 8, C.byref(lor), 8, 4, 8, None) == L.CBDG_EINVAL
     assert lib.cbdg_check_moments(None, None, 4, 8, 0, 1e-9, None, None) == L.CBDG_EINVAL
