@@ -10,6 +10,8 @@ adjoint_form   128x128 workload with 64 impurities, N = 512: forward pass,
                reverse pass for dSum(Delta)/dV, dLDOS(0)/dV at the centre, and
                the self-consistent solve by plain mixing and by Newton-Krylov
 scf_form       256x256 workload solved self-consistently to max|dDelta| < 1e-6
+paper_form     the paper's two example geometries (surface LDOS convergence with
+               N at constant Lorentz broadening; impurity LDOS maps)
 """
 from __future__ import annotations
 
@@ -293,3 +295,70 @@ def scf_form(args, dev):
             "moments_per_s": w.L2 * w.N * passes / r.seconds}
     line.update(extra)
     return line
+
+
+def paper_form(args, dev):
+    """The paper's two examples as synthetic workloads.
+
+    First example (planar normal metal 380a / superconductor 20a x 500a,
+    Delta = 0.1t): LDOS at 64 surface sites of the normal metal with the
+    Lorentz kernel at constant broadening eps = 0.001t (lambda = N eps / a),
+    for N = 2000 .. 16000, and how far each N is from the largest.
+    Second example (SC/N/SC 50a/50a/50a x 100a, Gaussian impurity V = 2t at
+    (60a, 50a)): LDOS maps at E = 0, 0.03t, 0.06t on the 21x21 square around
+    the impurity, minus those of the clean system, for the sandwich and for a
+    homogeneous normal metal."""
+    res = {"sn_surface": {}, "sns_impurity": {}}
+    eps = 0.001
+    Ns = (2000, 4000, 8000, 16000)
+    w0 = W.sn_surface(N=Ns[-1])
+    op = P.Operator.from_workload(w0, dev)
+    a = op.bounds.a
+    sites = torch.as_tensor(w0.start_sites, device=dev)
+    E = torch.as_tensor(w0.energies, device=dev)
+    ld = {}
+    for N in Ns:
+        lam = N * eps / a
+        wt = op.weights("lorentz", lam=lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu_ee, _ = P.chebyshev_moments(op, sites, N, len(w0.start_sites))
+        l = P.ldos(mu_ee, wt, E)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ld[N] = l
+        res["sn_surface"][str(N)] = {"seconds": dt, "lambda": lam, "moments_per_s": sites.numel() * N / dt}
+        log("S/N surface N=%d: %.2f s" % (N, dt))
+    ref = ld[Ns[-1]]
+    scale = float(ref.abs().max())
+    for N in Ns[:-1]:
+        res["sn_surface"][str(N)]["max_ldos_change_to_N16000_rel"] = float((ld[N] - ref).abs().max()) / scale
+    res["sn_surface"]["workload"] = w0.name
+    res["sn_surface"]["bounds_a"] = a
+    op.close()
+
+    for sc in (True, False):
+        maps = {}
+        for imp in (True, False):
+            w = W.sns_impurity(superconducting=sc, impurity=imp)
+            op = P.Operator.from_workload(w, dev)
+            s = torch.as_tensor(w.start_sites, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mu_ee, _ = P.chebyshev_moments(op, s, w.N, w.tile)
+            maps[imp] = P.ldos(mu_ee, op.weights(), torch.as_tensor(w.energies, device=dev))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            op.close()
+            res["sns_impurity"]["%s_%s_seconds" % ("sns" if sc else "normal", "imp" if imp else "clean")] = dt
+        diff = (maps[True] - maps[False]).cpu().numpy()       # [441, 3]
+        key = "sns" if sc else "normal"
+        res["sns_impurity"][key + "_max_abs_dldos_per_energy"] = [float(v) for v in np.abs(diff).max(axis=0)]
+        res["sns_impurity"][key + "_dldos_at_impurity_per_energy"] = [float(v) for v in diff[220]]
+        log("%s impurity maps done" % key)
+    return {"metric": METRIC, "value": res["sn_surface"]["16000"]["moments_per_s"], "unit": "moments/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "the paper's two examples as synthetic lattices: planar N 380a / S 20a x "
+                                   "500a surface LDOS (Lorentz kernel, eps = 0.001t, N = 2000..16000) and "
+                                   "SC/N/SC 150a x 100a impurity LDOS maps (N = 2048)"},
+            "examples": res}

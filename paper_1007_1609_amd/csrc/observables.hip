@@ -173,38 +173,39 @@ struct LdosArgs {
 };
 
 // Rows in a grid-stride loop; per row the damped moments pref_n g_n mu_n go to
-// LDS and each thread sums one energy with the three-term recurrence of T_n.
+// LDS in chunks of kLdosChunk and each thread advances the three-term
+// recurrence of T_n for its energies through every chunk (any N).
+constexpr int kLdosChunk = 2048;
+
 __global__ __launch_bounds__(kBlock) void k_ldos(LdosArgs A)
 {
-    extern __shared__ double sm[];
+    __shared__ double m[kLdosChunk];
     const int N = A.P.N;
-    double *g = sm, *m = sm + N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) g[n] = (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P);
-    __syncthreads();
     const double norm = 1.0 / (M_PI * A.a);
     for (int64_t r = blockIdx.x; r < A.rows; r += gridDim.x) {
-        for (int n = threadIdx.x; n < N; n += blockDim.x) m[n] = g[n] * A.mu[r * N + n];
-        __syncthreads();
-        for (int e = threadIdx.x; e < A.nE; e += blockDim.x) {
-            const double x = (A.E[e] - A.b) / A.a;
-            double val;
-            if (!(fabs(x) < 1.0)) {
-                val = __builtin_nan("");
-            } else {
-                double t0 = 1.0, t1 = x;
-                double acc = m[0];
-                if (N > 1) acc += m[1] * x;
-                for (int n = 2; n < N; ++n) {
-                    const double t2 = 2.0 * x * t1 - t0;
-                    acc += m[n] * t2;
-                    t0 = t1;
-                    t1 = t2;
+        for (int e0 = 0; e0 < A.nE; e0 += kBlock) {
+            const int e = e0 + threadIdx.x;
+            const double x = e < A.nE ? (A.E[e] - A.b) / A.a : 0.0;
+            double t0 = 1.0, t1 = x, acc = 0.0;  // T_{n-2}, T_{n-1} entering each chunk
+            for (int c0 = 0; c0 < N; c0 += kLdosChunk) {
+                const int cn = min(kLdosChunk, N - c0);
+                __syncthreads();
+                for (int k = threadIdx.x; k < cn; k += blockDim.x) {
+                    const int n = c0 + k;
+                    m[k] = (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P) * A.mu[r * N + n];
                 }
-                val = acc * norm / sqrt(1.0 - x * x);
+                __syncthreads();
+                for (int k = 0; k < cn; ++k) {
+                    const int n = c0 + k;
+                    double tn;
+                    if (n == 0) tn = 1.0;
+                    else if (n == 1) tn = x;
+                    else { tn = 2.0 * x * t1 - t0; t0 = t1; t1 = tn; }
+                    acc += m[k] * tn;
+                }
             }
-            A.out[r * A.nE + e] = val;
+            if (e < A.nE) A.out[r * A.nE + e] = fabs(x) < 1.0 ? acc * norm / sqrt(1.0 - x * x) : __builtin_nan("");
         }
-        __syncthreads();
     }
 }
 
@@ -449,12 +450,10 @@ extern "C" int cbdg_ldos(const double *mu_ee, int64_t n_rows, int32_t N, const c
     WeightParams P;
     int rc = make_weights(w, N, false, P, "ldos");
     if (rc) return rc;
-    rc = lds_ok((size_t)2 * N * 8, "ldos");
-    if (rc) return rc;
     if (n_rows == 0 || n_E == 0) return CBDG_OK;
     if (!mu_ee || !energies || !ldos) return fail(CBDG_EINVAL, "ldos: mu_ee, energies and ldos must not be NULL");
     LdosArgs A{mu_ee, n_rows, P, w->a, w->b, energies, n_E, ldos};
-    hipLaunchKernelGGL(k_ldos, dim3(grid_rows(n_rows, 1)), dim3(kBlock), (size_t)2 * N * 8, as_stream(stream), A);
+    hipLaunchKernelGGL(k_ldos, dim3(grid_rows(n_rows, 1)), dim3(kBlock), 0, as_stream(stream), A);
     CBDG_CHECK_LAUNCH("k_ldos");
     return CBDG_OK;
 }

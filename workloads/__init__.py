@@ -232,4 +232,49 @@ def small_random(Lx: int, Ly: int, N: int, seed: int, *, bc_x: int = OPEN,
         pairing="bond" if bond else "onsite")
 
 
+def sn_surface(Lx_n: int = 380, Lx_s: int = 20, Ly: int = 500, N: int = 2000, delta: float = 0.1,
+               mu_c: float = -0.4, n_sites: int = 64) -> Workload:
+    """The planar normal-metal / s-wave superconductor system of the first
+    example (its text: L_x^N = 380a, L_x^S = 20a, L_y = 500a, Delta = 0.1t;
+    the caption's 300/20 swaps the regions): normal metal on x < Lx_n with a
+    free surface at x = 0, superconductor on x >= Lx_n, periodic in y (the
+    planar geometry).  Delta is fixed (not self-consistent); the start sites
+    are n_sites consecutive surface sites x = 0 around y = Ly/2.  The example
+    gives no chemical potential: mu_c = -0.4 as in the other workloads."""
+    Lx = Lx_n + Lx_s
+    L2 = Lx * Ly
+    xs = np.tile(np.arange(Lx), Ly)
+    d = np.where(xs >= Lx_n, delta, 0.0)
+    y0 = Ly // 2 - n_sites // 2
+    sites = np.array([site(Lx, 0, y0 + k) for k in range(n_sites)], dtype=np.int32)
+    return Workload(name=f"sn_surface_{Lx_n}+{Lx_s}x{Ly}_N{N}", Lx=Lx, Ly=Ly, bc_x=OPEN, bc_y=PERIODIC,
+                    t=1.0, mu_c=mu_c, U=0.0, eps=np.zeros(L2), delta=d, delta_bond=None, peierls=None,
+                    N=N, start_sites=sites, tile=n_sites, energies=np.linspace(-0.2, 0.2, 401),
+                    kernel="lorentz", notes={"broadening": 0.001, "surface_x": 0})
+
+
+def sns_impurity(N: int = 2048, V: float = 2.0, delta: float = 0.1, mu_c: float = -0.4,
+                 superconducting: bool = True, impurity: bool = True, window: int = 10) -> Workload:
+    """The SC / normal metal / SC sandwich of the second example, 50a/50a/50a x
+    100a (superconductor on x < 50 and x >= 100), with the Gaussian impurity
+    V_i = V exp(-|r_i - r_0|^2 / a^2), V = 2t, r_0 = (60a, 50a) in the normal
+    layer; superconducting=False gives the homogeneous normal metal of the
+    comparison panels, impurity=False the clean system whose LDOS is
+    subtracted.  The example gives neither Delta nor mu: Delta = 0.1t as in
+    the first example, mu_c = -0.4.  Open boundaries; fixed Delta.  Start
+    sites: the (2 window + 1)^2 square around r_0."""
+    Lx, Ly = 150, 100
+    L2 = Lx * Ly
+    xs, ys = np.tile(np.arange(Lx), Ly), np.repeat(np.arange(Ly), Lx)
+    d = np.where((xs < 50) | (xs >= 100), delta, 0.0) if superconducting else np.zeros(L2)
+    eps = V * np.exp(-((xs - 60.0) ** 2 + (ys - 50.0) ** 2)) if impurity else np.zeros(L2)
+    sites = np.array([site(Lx, 60 + dx, 50 + dy) for dy in range(-window, window + 1)
+                      for dx in range(-window, window + 1)], dtype=np.int32)
+    tag = ("sns" if superconducting else "normal") + ("_imp" if impurity else "_clean")
+    return Workload(name=f"{tag}_150x100_N{N}", Lx=Lx, Ly=Ly, bc_x=OPEN, bc_y=OPEN, t=1.0, mu_c=mu_c, U=0.0,
+                    eps=eps, delta=d, delta_bond=None, peierls=None, N=N, start_sites=sites,
+                    tile=len(sites), energies=np.array([0.0, 0.03, 0.06]),
+                    notes={"impurity_centre": (60, 50), "window": window})
+
+
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
