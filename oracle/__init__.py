@@ -13,6 +13,8 @@ Parts (each function cites the passage of the paper it follows):
             quadrature), the gap equation eq. (op1), the LDOS eq. (ldos) and
             the electron density, in NumPy FP64
   scf.py    the self-consistency loop (plain mixing)
+  offdiag.py  moments between a start site and its neighbours, the bond order
+            parameter and the bond current
 
 Readings of passages the paper leaves open are listed with the code that
 uses them.
@@ -22,10 +24,12 @@ from .core import (build_csr, bounds, moments, moments_backward, workload_csr, w
 from .kpm import (jackson, lorentz, sign_coefficients, sign_weight_coefficients, gap_weights, gap_map,
                   ldos, ldos_weights, chebyshev_T, thermal_coefficients, thermal_gap_weights, density, gap_map_thermal)
 from .scf import scf_plain
+from .offdiag import neighbour_site, neighbour_moments, bond_gap_map, bond_current
 
 __all__ = [
     "build_csr", "bounds", "moments", "moments_backward", "workload_csr", "workload_bounds",
     "workload_moments", "max_threads", "ensure_built", "jackson", "lorentz",
     "sign_coefficients", "sign_weight_coefficients", "gap_weights", "gap_map", "ldos", "ldos_weights",
     "chebyshev_T", "scf_plain", "thermal_coefficients", "thermal_gap_weights", "density", "gap_map_thermal",
+    "neighbour_site", "neighbour_moments", "bond_gap_map", "bond_current",
 ]
