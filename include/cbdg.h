@@ -198,6 +198,25 @@ int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_
                            void *workspace, size_t workspace_bytes,
                            double *mu_ee, void *mu_he, void *stream);
 
+/*
+ * The moments of cbdg_chebyshev_moments (direct algorithm) and, from the same
+ * vectors, the off-diagonal moments between each start site and its four
+ * lattice neighbours j (the moments of the paragraph after eq. (ref2) with a
+ * bra on another grid point):
+ *   nb_ee[k][d][n] = <j,e|a_n>,  nb_he[k][d][n] = <j,h|a_n>,
+ *   d = 0..3 for j = s + x, s - x, s + y, s - y (wrapping on periodic
+ *   directions; a neighbour outside an open lattice gives a zero row).
+ * They feed cbdg_bond_gap_update and cbdg_bond_current.
+ *   nb_ee, nb_he  out [n_start*4*N] FP64 (REAL) or complex128 (COMPLEX)
+ *   workspace     >= cbdg_moments_workspace_size(op, tile, precision,
+ *                 CBDG_ALG_DIRECT) bytes
+ * Other arguments and NaN rows for invalid sites as cbdg_chebyshev_moments.
+ */
+int cbdg_chebyshev_moments_nb(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                              int32_t N, int32_t tile, int32_t precision, void *workspace,
+                              size_t workspace_bytes, double *mu_ee, void *mu_he, void *nb_ee,
+                              void *nb_he, void *stream);
+
 /* Bounds check of moments: |mu| <= 1 holds for every moment when the
  * spectrum of Ht lies in [-1, 1].  Writes 1 to *flag if any |mu_ee| or
  * |mu_he| exceeds 1 + tol or is not finite, else 0.
@@ -265,6 +284,36 @@ int cbdg_density_backward(const double *d_density, int64_t n_rows, int32_t N,
  */
 int cbdg_ldos(const double *mu_ee, int64_t n_rows, int32_t N, const cbdg_weights *w,
               const double *energies, int32_t n_E, double *ldos, void *stream);
+
+/*
+ * Bond order parameter of eq. (op1) for i != j (singlet, symmetrised), from
+ * the neighbour moments of every site (rows = sites 0..Lx*Ly-1 in order):
+ *   Delta_new(s, s+e) = (U/4) [conj(sum_n g_n c_n nb_he[s][+e][n])
+ *                            + conj(sum_n g_n c_n nb_he[s+e][-e][n])],
+ * e = x (axis 0) or y (axis 1), then plain mixing and the residual as in
+ * cbdg_gap_update.  Bonds leaving an open lattice get Delta_new = 0.
+ *   nb_he           [Lx*Ly*4*N] from cbdg_chebyshev_moments_nb
+ *   coeff           as for cbdg_gap_update (NULL: T = 0)
+ *   delta_bond_in   [2*Lx*Ly] (axis-major, the layout of cbdg_build_bdg),
+ *   delta_bond_out  [2*Lx*Ly] (may alias delta_bond_in); FP64 or complex128
+ */
+int cbdg_bond_gap_update(const void *nb_he, int32_t Lx, int32_t Ly, int32_t bc_x, int32_t bc_y,
+                         int32_t N, int32_t scalar, const cbdg_weights *w, const double *coeff,
+                         double U, const void *delta_bond_in, double alpha, void *delta_bond_out,
+                         double *resid, void *stream);
+
+/*
+ * Particle current along every bond, both spins (the current-density
+ * equation, read as the continuity current of the hopping -t_ij c_i^+ c_j of
+ * eq. (hamil2)):  J(s -> s+e) = 4 Im( t_{s,s+e} <c_s^+ c_{s+e}> ),
+ *   <c_s^+ c_{s+e}> = sum_n g_n c_n nb_ee[s][+e][n],  c_n of f(E),
+ * t the operator's unscaled hopping (with its Peierls phase).
+ *   nb_ee    [L2*4*N] from cbdg_chebyshev_moments_nb (rows = all sites)
+ *   coeff    [N] from cbdg_sum_coefficients(CBDG_QTY_DENSITY) (required)
+ *   current  out [2*L2] FP64, axis-major; 0 for bonds leaving an open lattice
+ */
+int cbdg_bond_current(const cbdg_op *op, const void *nb_ee, int32_t N, const cbdg_weights *w,
+                      const double *coeff, double *current, void *stream);
 
 /* Transpose of cbdg_gap_update for a REAL operator:
  *   d_mu_he[r][n] = alpha (U_r/2) g_n c_n d_delta_out[r]

@@ -17,12 +17,14 @@ _lib.load()
 from .api import (Operator, Bounds, weights, chebyshev_moments, check_moments,  # noqa: E402
                   gap_update, ldos, gap_update_backward, ldos_backward,
                   chebyshev_moments_backward, moments_workspace_bytes,
-                  backward_workspace_bytes, workspace, sum_coefficients, density, density_backward)
+                  backward_workspace_bytes, workspace, sum_coefficients, density, density_backward,
+                  chebyshev_moments_nb, bond_gap_update, bond_current)
 
 __all__ = [
     "CbdgError", "CBDG_FP64", "CBDG_FP32_ACC64", "CBDG_REAL", "CBDG_COMPLEX", "CBDG_BC_OPEN",
     "CBDG_BC_PERIODIC", "CBDG_ALG_AUTO", "CBDG_ALG_DIRECT", "CBDG_ALG_DOUBLING", "Operator", "Bounds", "weights", "chebyshev_moments", "check_moments",
     "gap_update", "ldos", "gap_update_backward", "ldos_backward", "chebyshev_moments_backward",
     "moments_workspace_bytes", "backward_workspace_bytes", "workspace", "CBDG_QTY_GAP",
-    "CBDG_QTY_DENSITY", "sum_coefficients", "density", "density_backward",
+    "CBDG_QTY_DENSITY", "sum_coefficients", "density", "density_backward", "chebyshev_moments_nb",
+    "bond_gap_update", "bond_current",
 ]

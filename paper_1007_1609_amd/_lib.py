@@ -62,7 +62,11 @@ SIGNATURES = {
     "cbdg_op_bounds": [_vp, C.POINTER(cbdg_bounds)],
     "cbdg_moments_workspace_size": [_vp, _i32, _i32, _i32, C.POINTER(_sz)],
     "cbdg_chebyshev_moments": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp],
+    "cbdg_chebyshev_moments_nb": [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp],
     "cbdg_check_moments": [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _vp],
+    "cbdg_bond_gap_update": [_vp, _i32, _i32, _i32, _i32, _i32, _i32, C.POINTER(cbdg_weights), _vp, _f64,
+                             _vp, _f64, _vp, _vp, _vp],
+    "cbdg_bond_current": [_vp, _vp, _i32, C.POINTER(cbdg_weights), _vp, _vp, _vp],
     "cbdg_sum_coefficients": [C.POINTER(cbdg_weights), _i32, _i32, _vp, _vp],
     "cbdg_gap_update": [_vp, _i64, _i32, _i32, C.POINTER(cbdg_weights), _vp, _f64, _vp, _vp,
                         _f64, _vp, _vp, _vp],
@@ -127,6 +131,9 @@ cbdg_check_moments = _call("cbdg_check_moments")
 cbdg_sum_coefficients = _call("cbdg_sum_coefficients")
 cbdg_density = _call("cbdg_density")
 cbdg_density_backward = _call("cbdg_density_backward")
+cbdg_chebyshev_moments_nb = _call("cbdg_chebyshev_moments_nb")
+cbdg_bond_gap_update = _call("cbdg_bond_gap_update")
+cbdg_bond_current = _call("cbdg_bond_current")
 cbdg_gap_update = _call("cbdg_gap_update")
 cbdg_ldos = _call("cbdg_ldos")
 cbdg_gap_update_backward = _call("cbdg_gap_update_backward")

@@ -54,6 +54,7 @@ class Operator:
                  delta_cap=0.0, eta=0.01):
         L.load()
         self.Lx, self.Ly = int(Lx), int(Ly)
+        self.bc_x, self.bc_y = int(bc_x), int(bc_y)
         self.scalar = L.CBDG_COMPLEX if complex_ else L.CBDG_REAL
         ddt = torch.complex128 if complex_ else torch.float64
         lat = L.cbdg_lattice(self.Lx, self.Ly, int(bc_x), int(bc_y), self.scalar)
@@ -147,6 +148,60 @@ def chebyshev_moments(op: Operator, sites: torch.Tensor, N: int, tile: int,
                              _ptr(mu_ee, torch.float64, "mu_ee"), _ptr(mu_he, None, "mu_he"),
                              _stream())
     return mu_ee, mu_he
+
+
+def chebyshev_moments_nb(op: Operator, sites: torch.Tensor, N: int, tile: int,
+                         precision: int = L.CBDG_FP64, ws: Optional[torch.Tensor] = None):
+    """Direct moments plus the neighbour moments nb_ee, nb_he [n, 4, N]
+    (neighbours +x, -x, +y, -y; complex128 for complex operators)."""
+    n = int(sites.numel())
+    eff = max(1, min(int(tile), n))
+    need = moments_workspace_bytes(op, eff, precision, L.CBDG_ALG_DIRECT)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, sites.device)
+    cdt = torch.complex128 if op.is_complex else torch.float64
+    mu_ee = torch.empty((n, N), dtype=torch.float64, device=sites.device)
+    mu_he = torch.empty((n, N), dtype=cdt, device=sites.device)
+    nb_ee = torch.empty((n, 4, N), dtype=cdt, device=sites.device)
+    nb_he = torch.empty((n, 4, N), dtype=cdt, device=sites.device)
+    L.cbdg_chebyshev_moments_nb(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N), int(tile), int(precision),
+                                _ptr(ws, None, "workspace"), ws.numel(), _ptr(mu_ee, torch.float64, "mu_ee"),
+                                _ptr(mu_he, None, "mu_he"), _ptr(nb_ee, None, "nb_ee"), _ptr(nb_he, None, "nb_he"),
+                                _stream())
+    return mu_ee, mu_he, nb_ee, nb_he
+
+
+def bond_gap_update(nb_he: torch.Tensor, op: Operator, w: L.cbdg_weights, U: float,
+                    delta_bond_in: torch.Tensor, alpha: float = 1.0,
+                    delta_bond_out: Optional[torch.Tensor] = None, resid: Optional[torch.Tensor] = None,
+                    coeff: Optional[torch.Tensor] = None):
+    """Symmetrised bond order parameter [2 * L2] from the neighbour moments of
+    every site of op's lattice (rows in site order)."""
+    N = nb_he.shape[-1]
+    coeff = _coeff_for(w, N, L.CBDG_QTY_GAP, coeff, nb_he.device)
+    if delta_bond_out is None:
+        delta_bond_out = torch.empty_like(delta_bond_in)
+    if resid is None:
+        resid = torch.empty(1, dtype=torch.float64, device=nb_he.device)
+    ddt = torch.complex128 if op.is_complex else torch.float64
+    L.cbdg_bond_gap_update(_ptr(nb_he, ddt, "nb_he"), op.Lx, op.Ly, op.bc_x, op.bc_y, int(N), op.scalar, C.byref(w),
+                           _ptr(coeff, torch.float64, "coeff"), float(U), _ptr(delta_bond_in, ddt, "delta_bond_in"),
+                           float(alpha), _ptr(delta_bond_out, ddt, "delta_bond_out"),
+                           _ptr(resid, torch.float64, "resid"), _stream())
+    return delta_bond_out, resid
+
+
+def bond_current(op: Operator, nb_ee: torch.Tensor, w: L.cbdg_weights,
+                 coeff: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Particle current [2, L2] along the +x and +y bond of every site."""
+    N = nb_ee.shape[-1]
+    if coeff is None:
+        coeff = sum_coefficients(w, N, L.CBDG_QTY_DENSITY, nb_ee.device)
+    out = torch.empty((2, op.L2), dtype=torch.float64, device=nb_ee.device)
+    ddt = torch.complex128 if op.is_complex else torch.float64
+    L.cbdg_bond_current(op.handle, _ptr(nb_ee, ddt, "nb_ee"), int(N), C.byref(w), _ptr(coeff, torch.float64, "coeff"),
+                        _ptr(out, torch.float64, "current"), _stream())
+    return out
 
 
 def check_moments(mu_ee: torch.Tensor, mu_he: torch.Tensor, tol: float = 1e-9) -> bool:

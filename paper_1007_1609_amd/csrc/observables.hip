@@ -378,6 +378,140 @@ __global__ __launch_bounds__(kBlock) void k_density_bwd(const double *dn, int64_
         for (int n = threadIdx.x; n < N; n += blockDim.x) dmu[r * N + n] = 2.0 * dn[r] * wt[n];
 }
 
+// Neighbour d (+x, -x, +y, -y) of site s, or -1 outside an open lattice.
+__device__ inline int64_t neighbour_of(int64_t s, int d, int Lx, int Ly, int bcx, int bcy)
+{
+    const int x = (int)(s % Lx), y = (int)(s / Lx);
+    int x2 = x + (d == 0 ? 1 : d == 1 ? -1 : 0), y2 = y + (d == 2 ? 1 : d == 3 ? -1 : 0);
+    if (x2 < 0 || x2 >= Lx) { if (!bcx) return -1; x2 = (x2 + Lx) % Lx; }
+    if (y2 < 0 || y2 >= Ly) { if (!bcy) return -1; y2 = (y2 + Ly) % Ly; }
+    return x2 + (int64_t)Lx * y2;
+}
+
+struct BondArgs {
+    const double *nb;      // [L2][4][N] (complex interleaved when cplx)
+    int Lx, Ly, bcx, bcy;
+    int cplx;
+    WeightParams P;
+    double U;
+    const double *din;     // [2][L2]
+    double alpha;
+    double *dout;
+    unsigned long long *resid;
+    // current
+    const void *bonds;     // operator's forward bonds (general), or null
+    double t_uniform, a;
+    double *cur;           // [2][L2]
+};
+
+// sum_n wt_n nb[row][d][n] by one wavefront (complex: both parts)
+__device__ inline void wave_dot(const double *nb, int64_t row, int d, int N, int cplx, const double *wt, int lane,
+                                double &re, double &im)
+{
+    re = 0.0; im = 0.0;
+    const int64_t base = (row * 4 + d) * (int64_t)N;
+    if (cplx) {
+        for (int n = lane; n < N; n += kWave) { re += wt[n] * nb[2 * (base + n)]; im += wt[n] * nb[2 * (base + n) + 1]; }
+    } else {
+        for (int n = lane; n < N; n += kWave) re += wt[n] * nb[base + n];
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+}
+
+// Bond order parameter (symmetrised singlet) with mixing and residual: one
+// wavefront per bond q = axis * L2 + s (bond s -> s + x for axis 0, s + y for
+// axis 1): Delta_new = (U/4) [conj(S(s; fwd)) + conj(S(j; back))].
+__global__ __launch_bounds__(kBlock) void k_bond_gap(BondArgs A)
+{
+    extern __shared__ double wt[];
+    const int N = A.P.N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x)
+        wt[n] = A.P.coeff ? A.P.coeff[n] : kernel_factor(n, A.P) * sign_coefficient(n, A.P);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const int64_t L2 = (int64_t)A.Lx * A.Ly;
+    double rmax = 0.0;
+    bool saw_nan = false;
+    for (int64_t q = (int64_t)blockIdx.x * wpb + wv; q < 2 * L2; q += (int64_t)gridDim.x * wpb) {
+        const int axis = (int)(q / L2);
+        const int64_t s = q % L2;
+        const int fwd = axis == 0 ? 0 : 2, back = fwd + 1;
+        const int64_t j = neighbour_of(s, fwd, A.Lx, A.Ly, A.bcx, A.bcy);
+        double nr = 0.0, ni = 0.0;
+        if (j >= 0) {
+            double fr, fi, br, bi;
+            wave_dot(A.nb, s, fwd, N, A.cplx, wt, lane, fr, fi);
+            wave_dot(A.nb, j, back, N, A.cplx, wt, lane, br, bi);
+            nr = 0.25 * A.U * (fr + br);
+            ni = -0.25 * A.U * (fi + bi);  // conj
+        }
+        if (lane == 0) {
+            if (A.cplx) {
+                const double orr = A.din[2 * q], oi = A.din[2 * q + 1];
+                A.dout[2 * q] = (1.0 - A.alpha) * orr + A.alpha * nr;
+                A.dout[2 * q + 1] = (1.0 - A.alpha) * oi + A.alpha * ni;
+                const double d = hypot(nr - orr, ni - oi);
+                if (d != d) saw_nan = true; else rmax = fmax(rmax, d);
+            } else {
+                const double orr = A.din[q];
+                A.dout[q] = (1.0 - A.alpha) * orr + A.alpha * nr;
+                const double d = fabs(nr - orr);
+                if (d != d) saw_nan = true; else rmax = fmax(rmax, d);
+            }
+        }
+    }
+    if (saw_nan) rmax = __builtin_nan("");
+    __shared__ double red[kBlock / kWave];
+    if (lane == 0) red[wv] = rmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        bool nan = m != m;
+        for (int i = 1; i < wpb; ++i) { nan |= red[i] != red[i]; m = fmax(m, red[i]); }
+        const unsigned long long bits = nan ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(m);
+        atomicMax(A.resid, bits);
+    }
+}
+
+// Particle current along bond q (both spins): J = 4 Im(t_ij <c_i^+ c_j>) with
+// <c_i^+ c_j> = sum_n wt_n <j,e|T_n|i,e> and t_ij the unscaled hopping.
+__global__ __launch_bounds__(kBlock) void k_bond_current(BondArgs A)
+{
+    extern __shared__ double wt[];
+    const int N = A.P.N;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) wt[n] = A.P.coeff[n];
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const int64_t L2 = (int64_t)A.Lx * A.Ly;
+    for (int64_t q = (int64_t)blockIdx.x * wpb + wv; q < 2 * L2; q += (int64_t)gridDim.x * wpb) {
+        const int axis = (int)(q / L2);
+        const int64_t s = q % L2;
+        const int fwd = axis == 0 ? 0 : 2;
+        const int64_t j = neighbour_of(s, fwd, A.Lx, A.Ly, A.bcx, A.bcy);
+        double J = 0.0;
+        if (j >= 0) {
+            double rr, ri;
+            wave_dot(A.nb, s, fwd, N, A.cplx, wt, lane, rr, ri);
+            double tr = A.t_uniform, ti = 0.0;
+            if (A.bonds) {
+                if (A.cplx) {
+                    const BondsC<double> b = reinterpret_cast<const BondsC<double> *>(A.bonds)[s];
+                    tr = A.a * (axis == 0 ? b.txr : b.tyr);
+                    ti = A.a * (axis == 0 ? b.txi : b.tyi);
+                } else {
+                    const BondsR<double> b = reinterpret_cast<const BondsR<double> *>(A.bonds)[s];
+                    tr = A.a * (axis == 0 ? b.tx : b.ty);
+                }
+            }
+            J = 4.0 * (tr * ri + ti * rr);
+        }
+        if (lane == 0) A.cur[q] = J;
+    }
+}
+
 // Nodes and weights of n-point Gauss-Legendre quadrature on [-1, 1]: roots of
 // P_n by Newton's method from cos(pi (i + 3/4) / (n + 1/2)), weights
 // 2 / ((1 - x^2) P_n'(x)^2).
@@ -576,5 +710,70 @@ extern "C" int cbdg_density_backward(const double *d_density, int64_t n_rows, in
     hipLaunchKernelGGL(k_density_bwd, dim3(grid_rows(n_rows, 1)), dim3(kBlock), (size_t)N * 8, as_stream(stream),
                        d_density, n_rows, P, std::acos(-w->b / w->a), d_mu_ee);
     CBDG_CHECK_LAUNCH("k_density_bwd");
+    return CBDG_OK;
+}
+
+extern "C" int cbdg_bond_gap_update(const void *nb_he, int32_t Lx, int32_t Ly, int32_t bc_x, int32_t bc_y,
+                                    int32_t N, int32_t scalar, const cbdg_weights *w, const double *coeff,
+                                    double U, const void *delta_bond_in, double alpha, void *delta_bond_out,
+                                    double *resid, void *stream)
+{
+    clear_error();
+    if (Lx < 1 || Ly < 1 || N < 1) return fail(CBDG_EINVAL, "bond_gap_update: need Lx, Ly, N >= 1");
+    if ((bc_x && Lx < 3) || (bc_y && Ly < 3)) return fail(CBDG_EINVAL, "bond_gap_update: periodic directions need >= 3 sites");
+    if (scalar != CBDG_REAL && scalar != CBDG_COMPLEX) return fail(CBDG_EINVAL, "bond_gap_update: bad scalar");
+    if (!std::isfinite(U) || !std::isfinite(alpha)) return fail(CBDG_EINVAL, "bond_gap_update: U and alpha must be finite");
+    if (!nb_he || !delta_bond_in || !delta_bond_out || !resid)
+        return fail(CBDG_EINVAL, "bond_gap_update: nb_he, delta_bond_in, delta_bond_out and resid must not be NULL");
+    WeightParams P;
+    int rc = make_weights(w, N, true, P, "bond_gap_update", coeff);
+    if (rc) return rc;
+    rc = lds_ok((size_t)N * 8, "bond_gap_update");
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, st, resid, 0.0);
+    CBDG_CHECK_LAUNCH("k_set_f64");
+    BondArgs A{};
+    A.nb = (const double *)nb_he;
+    A.Lx = Lx; A.Ly = Ly; A.bcx = bc_x; A.bcy = bc_y;
+    A.cplx = scalar == CBDG_COMPLEX;
+    A.P = P;
+    A.U = U;
+    A.din = (const double *)delta_bond_in;
+    A.alpha = alpha;
+    A.dout = (double *)delta_bond_out;
+    A.resid = (unsigned long long *)resid;
+    const int64_t nb = 2 * (int64_t)Lx * Ly;
+    hipLaunchKernelGGL(k_bond_gap, dim3(grid_rows(nb, kBlock / kWave)), dim3(kBlock), (size_t)N * 8, st, A);
+    CBDG_CHECK_LAUNCH("k_bond_gap");
+    return CBDG_OK;
+}
+
+extern "C" int cbdg_bond_current(const cbdg_op *op, const void *nb_ee, int32_t N, const cbdg_weights *w,
+                                 const double *coeff, double *current, void *stream)
+{
+    clear_error();
+    if (!op || N < 1) return fail(CBDG_EINVAL, "bond_current: need op and N >= 1");
+    if (!nb_ee || !current) return fail(CBDG_EINVAL, "bond_current: nb_ee and current must not be NULL");
+    WeightParams P;
+    int rc = make_weights(w, N, false, P, "bond_current");
+    if (rc) return rc;
+    if (!coeff) return fail(CBDG_EINVAL, "bond_current: coeff (cbdg_sum_coefficients, CBDG_QTY_DENSITY) is required");
+    P.coeff = coeff;
+    rc = lds_ok((size_t)N * 8, "bond_current");
+    if (rc) return rc;
+    BondArgs A{};
+    A.nb = (const double *)nb_ee;
+    A.Lx = op->Lx; A.Ly = op->Ly; A.bcx = op->bc_x; A.bcy = op->bc_y;
+    A.cplx = op->scalar == CBDG_COMPLEX;
+    A.P = P;
+    A.bonds = op->general ? op->bonds64 : nullptr;
+    A.t_uniform = op->t;
+    A.a = op->bounds.a;
+    A.cur = current;
+    const int64_t nb = 2 * op->L2;
+    hipLaunchKernelGGL(k_bond_current, dim3(grid_rows(nb, kBlock / kWave)), dim3(kBlock), (size_t)N * 8,
+                       as_stream(stream), A);
+    CBDG_CHECK_LAUNCH("k_bond_current");
     return CBDG_OK;
 }

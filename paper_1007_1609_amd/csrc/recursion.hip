@@ -45,11 +45,14 @@ namespace cbdg {
 #endif
 
 
-template <typename T, bool C, bool GEN, bool FIRST, int W, bool PF, bool DOT>
+// MODE 0: moments at the start site; 1: also the moment-doubling partial sums;
+// 2: also the values at the four neighbours of the start site.
+template <typename T, bool C, bool GEN, bool FIRST, int W, bool PF, int MODE>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
     StepArgs A, const typename Storage<T, C>::type *__restrict__ a1,
     const OnSite<T> *__restrict__ ons, const void *__restrict__ bonds)
 {
+    constexpr bool DOT = MODE == 1, NB = MODE == 2;
     using P = Pair<T, C>;
     using S = typename Storage<T, C>::type;
     const int lb = xcd_remap(blockIdx.x, A.nblocks);
@@ -103,6 +106,21 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     S *ao = reinterpret_cast<S *>(A.out);
     const int my_site = A.sites[b];
     const T th = T(A.th);
+    // neighbours +x, -x, +y, -y of the start site (-1: none)
+    [[maybe_unused]] int nbs[4] = {-1, -1, -1, -1};
+    [[maybe_unused]] bool nbf[4] = {false, false, false, false};
+    [[maybe_unused]] P nbv[NB ? 4 : 1];
+    if constexpr (NB) {
+        if (my_site >= 0 && my_site < Lx * Ly) {
+            const int mx = my_site % Lx, my = my_site / Lx;
+            if (mx + 1 < Lx) nbs[0] = my_site + 1; else if (A.bcx) nbs[0] = my_site + 1 - Lx;
+            if (mx > 0) nbs[1] = my_site - 1; else if (A.bcx) nbs[1] = my_site - 1 + Lx;
+            if (my + 1 < Ly) nbs[2] = my_site + Lx; else if (A.bcy) nbs[2] = my_site + Lx - Lx * Ly;
+            if (my > 0) nbs[3] = my_site - Lx; else if (A.bcy) nbs[3] = my_site - Lx + Lx * Ly;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nbv[q] = zero_pair<T, C>();
+    }
 
     // Column k of the register window holds x = x0 - 1 + k.  Every column gets
     // an in-bounds column index and a mask; a column outside an open lattice is
@@ -191,6 +209,14 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
             const bool hit = s == my_site;
             found = found || hit;
             mval = select_pair<T, C>(hit, ov, mval);
+            if constexpr (NB) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool hq = s == nbs[q];
+                    nbf[q] = nbf[q] || hq;
+                    nbv[q] = select_pair<T, C>(hq, ov, nbv[q]);
+                }
+            }
             if constexpr (DOT) {
                 const P &c = cur[k + 1];
                 if constexpr (C) {
@@ -248,6 +274,36 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
             A.mu_ee[m] = (double)mval.e;
             A.mu_he[m] = (double)mval.h;
         }
+    }
+    if constexpr (NB) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!nbf[q]) continue;
+            const int64_t m = ((int64_t)b * 4 + q) * A.N + A.n;
+            if constexpr (C) {
+                A.nb_ee[2 * m] = (double)nbv[q].er;
+                A.nb_ee[2 * m + 1] = (double)nbv[q].ei;
+                A.nb_he[2 * m] = (double)nbv[q].hr;
+                A.nb_he[2 * m + 1] = (double)nbv[q].hi;
+            } else {
+                A.nb_ee[m] = (double)nbv[q].e;
+                A.nb_he[m] = (double)nbv[q].h;
+            }
+        }
+    }
+}
+
+// Neighbour-moment rows [Bt][4][N]: zero (n = 0, and missing neighbours), NaN
+// for invalid start sites.
+__global__ void k_seed_nb(double *nb_ee, double *nb_he, const int32_t *sites, int Bt, int64_t L2, int N, int cplx)
+{
+    const int64_t per = (int64_t)4 * N * (cplx ? 2 : 1);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)Bt * per;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = sites[i / per];
+        const double v = (s < 0 || s >= L2) ? __builtin_nan("") : 0.0;
+        nb_ee[i] = v;
+        nb_he[i] = v;
     }
 }
 
@@ -616,11 +672,14 @@ static int launch_step_w(StepArgs A, hipStream_t st)
     const auto *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
     const dim3 g(A.nblocks), bl(kBlock);
     if (A.part) {
-        if (A.first) hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF, true>), g, bl, 0, st, A, a1, ons, A.bonds);
-        else hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF, true>), g, bl, 0, st, A, a1, ons, A.bonds);
+        if (A.first) hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF, 1>), g, bl, 0, st, A, a1, ons, A.bonds);
+        else hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF, 1>), g, bl, 0, st, A, a1, ons, A.bonds);
+    } else if (A.nb_ee) {
+        if (A.first) hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF, 2>), g, bl, 0, st, A, a1, ons, A.bonds);
+        else hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF, 2>), g, bl, 0, st, A, a1, ons, A.bonds);
     } else {
-        if (A.first) hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF, false>), g, bl, 0, st, A, a1, ons, A.bonds);
-        else hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF, false>), g, bl, 0, st, A, a1, ons, A.bonds);
+        if (A.first) hipLaunchKernelGGL((k_cheb_step<T, C, GEN, true, W, PF, 0>), g, bl, 0, st, A, a1, ons, A.bonds);
+        else hipLaunchKernelGGL((k_cheb_step<T, C, GEN, false, W, PF, 0>), g, bl, 0, st, A, a1, ons, A.bonds);
     }
     CBDG_CHECK_LAUNCH("k_cheb_step");
     return CBDG_OK;
@@ -863,12 +922,13 @@ int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, doubl
 // [regions][K][Bp] x 2 and the run sums [runs][K][Bp].
 template <typename T, bool C>
 static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start, int N, int tile,
-                       bool doubling, void *ws, double *mu_ee, double *mu_he, hipStream_t st)
+                       bool doubling, void *ws, double *mu_ee, double *mu_he, hipStream_t st,
+                       double *nb_ee = nullptr, double *nb_he = nullptr)
 {
     using S = typename Storage<T, C>::type;
     const int64_t L2 = op->L2;
     const int64_t Bp_max = lane_stride(tile);
-    const bool two = !C && uses_two_step(op);
+    const bool two = !C && uses_two_step(op) && !nb_ee;
     const int nbuf = two ? 4 : 2;
     S *buf[4];
     for (int i = 0; i < 4; ++i) buf[i] = reinterpret_cast<S *>(ws) + (i < nbuf ? i : 0) * L2 * Bp_max;
@@ -900,6 +960,13 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         hipLaunchKernelGGL(k_tile_cone, dim3(1), dim3(kBlock), 0, st, ts, Bt, op->Lx, L2, cone);
         CBDG_CHECK_LAUNCH("k_tile_cone");
         StepArgs A{};
+        if (nb_ee) {
+            A.nb_ee = nb_ee + t0 * 4 * N * he_mult;
+            A.nb_he = nb_he + t0 * 4 * N * he_mult;
+            hipLaunchKernelGGL(k_seed_nb, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)Bt * 4 * N * he_mult, kBlock), 4096)),
+                               dim3(kBlock), 0, st, A.nb_ee, A.nb_he, ts, Bt, L2, N, C ? 1 : 0);
+            CBDG_CHECK_LAUNCH("k_seed_nb");
+        }
         A.cone = cone;
         A.onsite = onsite;
         A.bonds = bonds;
@@ -1095,6 +1162,37 @@ extern "C" int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_si
                     : run_moments<double, false>(op, start_sites, n_start, N, et, doubling, workspace, mu_ee, mhe, st);
     return cplx ? run_moments<float, true>(op, start_sites, n_start, N, et, doubling, workspace, mu_ee, mhe, st)
                 : run_moments<float, false>(op, start_sites, n_start, N, et, doubling, workspace, mu_ee, mhe, st);
+}
+
+extern "C" int cbdg_chebyshev_moments_nb(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                                         int32_t N, int32_t tile, int32_t precision, void *workspace,
+                                         size_t workspace_bytes, double *mu_ee, void *mu_he, void *nb_ee,
+                                         void *nb_he, void *stream)
+{
+    clear_error();
+    if (!op) return fail(CBDG_EINVAL, "chebyshev_moments_nb: op must not be NULL");
+    if (n_start < 0 || N < 1 || tile < 1) return fail(CBDG_EINVAL, "chebyshev_moments_nb: need n_start >= 0, N >= 1, tile >= 1");
+    if (precision != CBDG_FP64 && precision != CBDG_FP32_ACC64)
+        return fail(CBDG_EINVAL, "chebyshev_moments_nb: unknown precision %d", precision);
+    if (n_start == 0) return CBDG_OK;
+    if (!start_sites || !mu_ee || !mu_he || !nb_ee || !nb_he || !workspace)
+        return fail(CBDG_EINVAL, "chebyshev_moments_nb: start_sites, moment outputs and workspace must not be NULL");
+    const int64_t eff_tile = std::min<int64_t>(tile, n_start);
+    size_t need = 2 * (size_t)op->L2 * (size_t)lane_stride(eff_tile) * pair_bytes(op->scalar, precision) +
+                  kConeDoubles * sizeof(double);
+    if (workspace_bytes < need)
+        return fail(CBDG_EINVAL, "chebyshev_moments_nb: workspace of %zu bytes is smaller than the %zu needed",
+                    workspace_bytes, need);
+    hipStream_t st = as_stream(stream);
+    double *mhe = reinterpret_cast<double *>(mu_he);
+    double *ne = reinterpret_cast<double *>(nb_ee), *nh = reinterpret_cast<double *>(nb_he);
+    const bool cplx = op->scalar == CBDG_COMPLEX;
+    const int et = (int)eff_tile;
+    if (precision == CBDG_FP64)
+        return cplx ? run_moments<double, true>(op, start_sites, n_start, N, et, false, workspace, mu_ee, mhe, st, ne, nh)
+                    : run_moments<double, false>(op, start_sites, n_start, N, et, false, workspace, mu_ee, mhe, st, ne, nh);
+    return cplx ? run_moments<float, true>(op, start_sites, n_start, N, et, false, workspace, mu_ee, mhe, st, ne, nh)
+                : run_moments<float, false>(op, start_sites, n_start, N, et, false, workspace, mu_ee, mhe, st, ne, nh);
 }
 
 extern "C" int cbdg_check_moments(const double *mu_ee, const void *mu_he, int64_t n_rows, int32_t N,

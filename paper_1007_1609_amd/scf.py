@@ -18,7 +18,8 @@ from typing import List, Optional
 import torch
 
 from . import _lib as L
-from .api import Operator, chebyshev_moments, gap_update, moments_workspace_bytes, sum_coefficients, workspace
+from .api import (Operator, bond_gap_update, chebyshev_moments, chebyshev_moments_nb, gap_update,
+                  moments_workspace_bytes, sum_coefficients, workspace)
 
 
 @dataclass
@@ -69,6 +70,43 @@ def plain_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int
             break
     torch.cuda.synchronize()
     return ScfResult(delta, it, r, hist, time.perf_counter() - t0, it)
+
+
+def bond_plain_mixing(op: Operator, U: float, delta: torch.Tensor, delta_bond0: torch.Tensor, N: int,
+                      tile: int, alpha: float = 1.0, tol: float = 1e-6, max_iter: int = 200,
+                      kernel: str = "jackson", T: float = 0.0, callback=None) -> ScfResult:
+    """Self-consistency of the bond order parameter (on-site Delta held at
+    `delta`): neighbour moments of every site, the symmetrised bond gap map
+    with mixing, cbdg_op_update_delta with the new bonds, until
+    max|Delta_new - Delta| < tol.  The result's delta is the [2 * L2] bond array."""
+    dev = delta_bond0.device
+    sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
+    w = op.weights(kernel, T=T)
+    coeff = sum_coefficients(w, N, L.CBDG_QTY_GAP, dev) if T > 0 else None
+    ws = workspace(moments_workspace_bytes(op, min(tile, op.L2), L.CBDG_FP64, L.CBDG_ALG_DIRECT), dev)
+    db = delta_bond0.clone()
+    nxt = torch.empty_like(db)
+    resid = torch.empty(1, dtype=torch.float64, device=dev)
+    hist: List[float] = []
+    t0 = time.perf_counter()
+    op.update_delta(delta, db)
+    r = float("inf")
+    it = 0
+    for it in range(1, max_iter + 1):
+        _, _, _, nb_he = chebyshev_moments_nb(op, sites, N, tile, ws=ws)
+        bond_gap_update(nb_he, op, w, U, db, alpha, delta_bond_out=nxt, resid=resid, coeff=coeff)
+        r = float(resid.item())
+        hist.append(r)
+        db, nxt = nxt, db
+        op.update_delta(delta, db)
+        if callback is not None:
+            callback(it, r)
+        if not (r == r):
+            raise L.CbdgError(L.CBDG_EBOUNDS, "scf", "non-finite residual at iteration %d" % it)
+        if r < tol:
+            break
+    torch.cuda.synchronize()
+    return ScfResult(db, it, r, hist, time.perf_counter() - t0, it)
 
 
 def _gmres(matvec, rhs, tol, restart=30, maxiter=60):
