@@ -240,7 +240,7 @@ def main():
         bp = (bt + 63) // 64 * 64
         lo = (k % n_tiles) * tile
         nl, moved, full = recursion_traffic(sites_np[lo:lo + bt], w.Lx, w.Ly, w.bc_x, w.bc_y, steps_per_tile,
-                                            two_step)
+                                            two_step, three_step=args.precision == "fp32")
         launches += nl
         alg_bytes += moved * 2 * bp * s_bytes
         full_bytes += full * 2 * bp * s_bytes
@@ -274,7 +274,8 @@ def main():
             "algorithm": "doubling" if doubling else "direct", "recursion_steps_per_tile": steps_per_tile,
         },
         "roofline": {
-            "kernel": "k_cheb_step2<%s> (two recursion steps per launch)" % ("double" if s_bytes == 8 else "float"),
+            "kernel": ("k_cheb_step2<double> (two recursion steps per launch)" if s_bytes == 8
+                       else "k_cheb_step3<float> (three recursion steps per launch)"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

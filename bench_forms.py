@@ -44,16 +44,19 @@ def _cone_sites(x, y, Lx, Ly, bc_x, bc_y, n):
     return max(rows, 0) * max(cols, 0)
 
 
-def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step):
+def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step, three_step=False):
     """Recursion launches of one tile as the library issues them, and the
     vector elements (site x vector, in units of one Nambu pair per vector)
     each must move through HBM at minimum:
       first step   read a_0, write a_1 over the lattice: 2 x L2
+      three-step   read a_{n-2}, a_{n-1}, write a_{n+1}, a_{n+2} inside the light
+                   cone of step n+2: 4 x cone(n+2)
       two-step     read a_{n-2}, a_{n-1}, write a_n, a_{n+1} inside the light
                    cone of step n+1: 4 x cone(n+1)
       single step  read a_{n-2}, a_{n-1}, write a_n inside cone(n): 3 x cone(n)
-    Two-step passes cover steps 2.. in pairs on real operators with uniform
-    hopping.  Returns (launches, pair-elements moved, pair-elements of the
+    On real operators with uniform hopping steps 2.. go in threes (FP32) or
+    pairs, the remainder in a pair and/or a single step, as the library
+    issues them.  Returns (launches, pair-elements moved, pair-elements of the
     plain one-step streaming recursion over the whole lattice, 3 x L2 per
     step)."""
     sites = np.asarray(sites)
@@ -64,6 +67,11 @@ def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step):
         return 0, 0, 0
     launches, moved = 1, 2 * L2
     n = 2
+    if two_step and three_step:
+        while n + 2 <= n_steps:
+            launches += 1
+            moved += 4 * _cone_sites(x, y, Lx, Ly, bc_x, bc_y, n + 2)
+            n += 3
     if two_step:
         while n + 1 <= n_steps:
             launches += 1

@@ -175,12 +175,16 @@ struct LdosArgs {
 // Rows in a grid-stride loop; per row the damped moments pref_n g_n mu_n go to
 // LDS in chunks of kLdosChunk and each thread advances the three-term
 // recurrence of T_n for its energies through every chunk (any N).
-constexpr int kLdosChunk = 2048;
+constexpr int kLdosChunk = 2048, kLdosTable = 4096;
 
 __global__ __launch_bounds__(kBlock) void k_ldos(LdosArgs A)
 {
     __shared__ double m[kLdosChunk];
+    __shared__ double gt[kLdosTable];  // pref_n g_n, once per workgroup when N fits
     const int N = A.P.N;
+    const bool table = N <= kLdosTable;
+    if (table)
+        for (int n = threadIdx.x; n < N; n += blockDim.x) gt[n] = (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P);
     const double norm = 1.0 / (M_PI * A.a);
     for (int64_t r = blockIdx.x; r < A.rows; r += gridDim.x) {
         for (int e0 = 0; e0 < A.nE; e0 += kBlock) {
@@ -192,7 +196,8 @@ __global__ __launch_bounds__(kBlock) void k_ldos(LdosArgs A)
                 __syncthreads();
                 for (int k = threadIdx.x; k < cn; k += blockDim.x) {
                     const int n = c0 + k;
-                    m[k] = (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P) * A.mu[r * N + n];
+                    const double g = table ? gt[n] : (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P);
+                    m[k] = g * A.mu[r * N + n];
                 }
                 __syncthreads();
                 for (int k = 0; k < cn; ++k) {

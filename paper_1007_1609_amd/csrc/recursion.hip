@@ -515,6 +515,211 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step2(StepArgs A, const typenam
     }
 }
 
+// Three recursion steps in one pass (real operators, uniform hopping):
+// a_n, a_{n+1}, a_{n+2} from a_{n-2} (A.prev2) and a_{n-1} (a1); only the two
+// vectors the next pass reads are written, a_{n+1} (A.out) and a_{n+2}
+// (A.out2), so the vectors cross HBM four times per three steps.  A lane
+// computes a_n on its strip widened by two columns and rows per side, a_{n+1}
+// widened by one, a_{n+2} on the strip itself.  Columns: a_{n-1} at
+// x0-3 .. x0+W+2 (k <-> x0-3+k), a_n at x0-2 .. x0+W+1, a_{n+1} at
+// x0-1 .. x0+W.  Iteration r computes row r of a_n, row r-1 of a_{n+1} and
+// row r-2 of a_{n+2}.
+template <typename T, int W, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_cheb_step3(StepArgs A, const typename Storage<T, false>::type *__restrict__ a1,
+                                                      const OnSite<T> *__restrict__ ons)
+{
+    using P = Pair<T, false>;
+    using S = typename Storage<T, false>::type;
+    constexpr int X2 = W + 2, X1 = W + 4, Y = W + 6;
+    const int lb = xcd_remap(blockIdx.x, A.nblocks);
+    const int strip = lb % A.n_strips;
+    const int rest = lb / A.n_strips;
+    const int seg = rest % A.n_segs;
+    const int chunk = rest / A.n_segs;
+    const uint32_t b = chunk * kBlock + threadIdx.x;
+    if (b >= (uint32_t)A.Bt) return;
+
+    const int Lx = A.Lx, Ly = A.Ly;
+    const int x0 = strip * W;
+    int y0 = seg * A.ys;
+    int y1 = min(y0 + A.ys, Ly);
+    const int64_t Bp = A.Bp;
+    const int64_t region = strip + (int64_t)A.n_strips * seg;
+    if (A.cone) {
+        const int m = A.n + 2;
+        bool skip = false;
+        if (!A.bcx) skip = x0 + W - 1 < A.cone[0] - m || x0 > A.cone[1] + m;
+        if (!A.bcy) {
+            const int ylo = max(0, A.cone[2] - m), yhi = min(Ly - 1, A.cone[3] + m);
+            const int rows = yhi - ylo + 1;
+            const int per = max(4, (rows + A.n_segs - 1) / A.n_segs);
+            y0 = ylo + seg * per;
+            y1 = min(y0 + per, yhi + 1);
+            skip = skip || rows <= 0 || y0 >= y1;
+        }
+        if (skip) {
+            if constexpr (DOT) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    A.part[(region * 3 + k) * Bp + b] = 0.0;
+                    A.part_b[(region * 3 + k) * Bp + b] = 0.0;
+                    A.part_c[(region * 3 + k) * Bp + b] = 0.0;
+                }
+            }
+            return;
+        }
+    }
+    const S *a2 = reinterpret_cast<const S *>(A.prev2);
+    S *ao = reinterpret_cast<S *>(A.out);
+    S *ao2 = reinterpret_cast<S *>(A.out2);
+    const int my_site = A.sites[b];
+    const T th = T(A.th);
+
+    int cx[Y];
+    uint32_t cm[Y];
+#pragma unroll
+    for (int k = 0; k < Y; ++k) {
+        const int x = x0 - 3 + k;
+        if (A.bcx) {
+            cx[k] = ((x % Lx) + Lx) % Lx;
+            cm[k] = ~0u;
+        } else {
+            const bool ok = x >= 0 && x < Lx;
+            cx[k] = ok ? x : (x < 0 ? 0 : Lx - 1);
+            cm[k] = ok ? ~0u : 0u;
+        }
+    }
+    auto row_of = [&](int y, uint32_t &ok) -> int64_t {
+        if (A.bcy) { ok = ~0u; return (int64_t)(((y % Ly) + Ly) % Ly) * Lx; }
+        const bool in = y >= 0 && y < Ly;
+        ok = in ? ~0u : 0u;
+        return (int64_t)(in ? y : (y < 0 ? 0 : Ly - 1)) * Lx;
+    };
+    auto load_row1 = [&](P *row, int y) -> uint32_t {
+        uint32_t ok;
+        const int64_t rb = row_of(y, ok);
+#pragma unroll
+        for (int k = 0; k < Y; ++k) row[k] = ld<T, false>(a1 + (rb + cx[k]) * Bp + b);
+        return ok;
+    };
+    auto mask_row1 = [&](P *row, uint32_t rm) {
+#pragma unroll
+        for (int k = 0; k < Y; ++k) row[k] = masked<T, false>(row[k], rm & cm[k]);
+    };
+
+    P w0[Y], w1[Y], w2[Y], nx[Y];   // a_{n-1} rows r-1, r, r+1, r+2
+    P m2[X1], m1[X1], m0[X1];       // a_n rows r-2, r-1, r
+    P q2[X2], q1[X2], q0[X2];       // a_{n+1} rows r-3, r-2, r-1
+    P p2[X1];                       // a_{n-2} row r
+    P mv0 = zero_pair<T, false>(), mv1 = zero_pair<T, false>(), mv2 = zero_pair<T, false>();
+    bool f0 = false, f1 = false, f2 = false;
+    double d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // <x|x>, <x|y>, B(x, y) for steps n, n+1, n+2
+    auto dots = [&](double *acc, const P &v, const P &c) {
+        const double e = v.e, h = v.h, ce = c.e, ch = c.h;
+        acc[0] += e * e + h * h;
+        acc[1] += e * ce + h * ch;
+        acc[2] += e * ch - h * ce;
+    };
+    mask_row1(w0, load_row1(w0, y0 - 3));
+    mask_row1(w1, load_row1(w1, y0 - 2));
+    mask_row1(w2, load_row1(w2, y0 - 1));
+#pragma unroll
+    for (int k = 0; k < X1; ++k) { m1[k] = zero_pair<T, false>(); m0[k] = zero_pair<T, false>(); }
+#pragma unroll
+    for (int k = 0; k < X2; ++k) { q1[k] = zero_pair<T, false>(); q0[k] = zero_pair<T, false>(); }
+
+#pragma unroll 1
+    for (int r = y0 - 2; r <= y1 + 1; ++r) {
+        uint32_t nm = 0;
+        if (r + 2 <= y1 + 2) nm = load_row1(nx, r + 2);
+        uint32_t rok;
+        const int64_t rb = row_of(r, rok);
+#pragma unroll
+        for (int k = 0; k < X1; ++k) p2[k] = CBDG_NT_A2 ? ld_nt<T, false>(a2 + (rb + cx[k + 1]) * Bp + b)
+                                                       : ld<T, false>(a2 + (rb + cx[k + 1]) * Bp + b);
+#pragma unroll
+        for (int k = 0; k < X1; ++k) { m2[k] = m1[k]; m1[k] = m0[k]; }
+        // a_n, row r, columns x0-2 .. x0+W+1
+#pragma unroll
+        for (int k = 0; k < X1; ++k) {
+            const OnSite<T> o = ons[rb + cx[k + 1]];
+            const P yv = apply_uniform<T, false>(o, th, w1[k + 1], w1[k], w1[k + 2], w0[k + 1], w2[k + 1]);
+            m0[k] = masked<T, false>(cheb_combine<T, false>(yv, p2[k], false), rok & cm[k + 1]);
+        }
+        if (r >= y0 && r < y1) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const P &v = m0[k + 2];
+                const bool hit = rb + x0 + k == my_site;
+                f0 = f0 || hit;
+                mv0 = select_pair<T, false>(hit, v, mv0);
+                if constexpr (DOT) dots(d, v, w1[k + 3]);
+            }
+        }
+        // a_{n+1}, row r-1, columns x0-1 .. x0+W
+        if (r - 1 >= y0 - 1) {
+            uint32_t qok;
+            const int64_t qb = row_of(r - 1, qok);
+#pragma unroll
+            for (int k = 0; k < X2; ++k) { q2[k] = q1[k]; q1[k] = q0[k]; }
+#pragma unroll
+            for (int k = 0; k < X2; ++k) {
+                const OnSite<T> o = ons[qb + cx[k + 2]];
+                const P yv = apply_uniform<T, false>(o, th, m1[k + 1], m1[k], m1[k + 2], m2[k + 1], m0[k + 1]);
+                q0[k] = masked<T, false>(cheb_combine<T, false>(yv, w0[k + 2], false), qok & cm[k + 2]);
+            }
+            if (r - 1 >= y0 && r - 1 < y1) {
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const int64_t s = qb + x0 + k;
+                    const P &v = q0[k + 1];
+                    if constexpr (CBDG_NT_OUT) st_nt<T, false>(ao + s * Bp + b, v);
+                    else st<T, false>(ao + s * Bp + b, v);
+                    const bool hit = s == my_site;
+                    f1 = f1 || hit;
+                    mv1 = select_pair<T, false>(hit, v, mv1);
+                    if constexpr (DOT) dots(d + 3, v, m1[k + 2]);
+                }
+            }
+        }
+        // a_{n+2}, row r-2, own columns
+        if (r - 2 >= y0) {
+            uint32_t sok;
+            const int64_t sb = row_of(r - 2, sok);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const int64_t s = sb + x0 + k;
+                const OnSite<T> o = ons[s];
+                const P yv = apply_uniform<T, false>(o, th, q1[k + 1], q1[k], q1[k + 2], q2[k + 1], q0[k + 1]);
+                const P v = cheb_combine<T, false>(yv, m2[k + 2], false);
+                if constexpr (CBDG_NT_OUT) st_nt<T, false>(ao2 + s * Bp + b, v);
+                else st<T, false>(ao2 + s * Bp + b, v);
+                const bool hit = s == my_site;
+                f2 = f2 || hit;
+                mv2 = select_pair<T, false>(hit, v, mv2);
+                if constexpr (DOT) dots(d + 6, v, q1[k + 1]);
+            }
+        }
+        if (r + 2 <= y1 + 2) mask_row1(nx, nm);
+#pragma unroll
+        for (int k = 0; k < Y; ++k) { w0[k] = w1[k]; w1[k] = w2[k]; w2[k] = nx[k]; }
+    }
+
+    if constexpr (DOT) {
+        double *pa = A.part + region * 3 * Bp + b;
+        double *pb = A.part_b + region * 3 * Bp + b;
+        double *pc = A.part_c + region * 3 * Bp + b;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { pa[k * Bp] = d[k]; pb[k * Bp] = d[3 + k]; pc[k * Bp] = d[6 + k]; }
+    }
+    if (A.mu_ee) {
+        const int64_t m = (int64_t)b * A.N + A.n;
+        if (f0) { A.mu_ee[m] = (double)mv0.e; A.mu_he[m] = (double)mv0.h; }
+        if (f1) { A.mu_ee[m + 1] = (double)mv1.e; A.mu_he[m + 1] = (double)mv1.h; }
+        if (f2) { A.mu_ee[m + 2] = (double)mv2.e; A.mu_he[m + 2] = (double)mv2.h; }
+    }
+}
+
 // a_0 = |s_b, e> for every lane: zero the buffer ...
 template <typename T, bool C>
 __global__ void k_zero(typename Storage<T, C>::type *p, int64_t n)
@@ -789,6 +994,82 @@ static bool uses_two_step(const cbdg_op *op)
     return CBDG_TWO_STEP && op->scalar == CBDG_REAL && !op->general;
 }
 
+// Three-step passes (k_cheb_step3), used for FP32 only.  One 1024-vector tile
+// of the 256x256 workload, N = 514 by doubling, microseconds per moment index
+// (two-step W = 8: FP64 192.7, FP32 101.7):
+//   FP32: W = 4 94.3 (222 VGPRs, two waves per SIMD), W = 8 111.2, W = 2 135.5
+//   FP64: W = 4 199.1, W = 2 263.0, W = 1 329.6 (the widened register windows
+//         spill into AGPRs: no gain over two steps)
+#ifndef CBDG_THREE_STEP_F64
+#define CBDG_THREE_STEP_F64 0
+#endif
+#ifndef CBDG_THREE_STEP_F32
+#define CBDG_THREE_STEP_F32 1
+#endif
+#ifndef CBDG_W3_F64
+#define CBDG_W3_F64 4
+#endif
+#ifndef CBDG_W3_F32
+#define CBDG_W3_F32 4
+#endif
+template <typename T> struct Step3Shape;
+template <> struct Step3Shape<double> { static constexpr int W = CBDG_W3_F64; static constexpr bool ON = CBDG_THREE_STEP_F64; };
+template <> struct Step3Shape<float> { static constexpr int W = CBDG_W3_F32; static constexpr bool ON = CBDG_THREE_STEP_F32; };
+
+template <typename T>
+static Shape choose_shape3(int Lx, int Ly, int64_t n_chunks)
+{
+    Shape sh;
+    constexpr int WB = Step3Shape<T>::W;
+    sh.W = (Lx % WB == 0) ? WB : (Lx % 4 == 0 ? 4 : (Lx % 2 == 0 ? 2 : 1));
+    sh.PF = false;
+    sh.n_strips = Lx / sh.W;
+    int ys = CBDG_YS2;
+    while (ys > 8 && (int64_t)sh.n_strips * n_chunks * ceil_div(Ly, ys) < CBDG_TGT2) ys /= 2;
+    sh.ys = ys;
+    sh.n_segs = (int)ceil_div(Ly, sh.ys);
+    return sh;
+}
+
+template <typename T>
+static int64_t max_regions3(int Lx, int Ly, int tile)
+{
+    int64_t r = 0;
+    for (int64_t c = 1; c <= ceil_div(tile, kBlock); ++c) {
+        const Shape sh = choose_shape3<T>(Lx, Ly, c);
+        r = std::max<int64_t>(r, (int64_t)sh.n_strips * sh.n_segs);
+    }
+    return r;
+}
+
+template <typename T, int W>
+static int launch_step3_w(StepArgs A, hipStream_t st)
+{
+    const int n_chunks = (int)ceil_div(A.Bt, kBlock);
+    const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
+    if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
+    A.nblocks = (int)nb;
+    const auto *a1 = reinterpret_cast<const typename Storage<T, false>::type *>(A.prev1);
+    const auto *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
+    if (A.part) hipLaunchKernelGGL((k_cheb_step3<T, W, true>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons);
+    else hipLaunchKernelGGL((k_cheb_step3<T, W, false>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons);
+    CBDG_CHECK_LAUNCH("k_cheb_step3");
+    return CBDG_OK;
+}
+
+template <typename T>
+static int launch_step3(StepArgs A, hipStream_t st)
+{
+    const Shape sh = choose_shape3<T>(A.Lx, A.Ly, ceil_div(A.Bt, kBlock));
+    A.n_strips = sh.n_strips;
+    A.ys = sh.ys;
+    A.n_segs = sh.n_segs;
+    if (sh.W == 8) return launch_step3_w<T, 8>(A, st);
+    if (sh.W == 4) return launch_step3_w<T, 4>(A, st);
+    if (sh.W == 2) return launch_step3_w<T, 2>(A, st);
+    return launch_step3_w<T, 1>(A, st);
+}
+
 // Moments 2n-1 and 2n of every vector from the partial sums of step n:
 //   mu_ee[2n]   = 2 <a_n|a_n> - mu_ee[0]
 //   mu_ee[2n-1] = 2 Re<a_n|a_{n-1}> - mu_ee[1]
@@ -916,8 +1197,8 @@ int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, doubl
 // Direct: steps n = 1 .. N-1, each capturing moment n of every vector.
 // Doubling: steps n = 1 .. ceil((N-1)/2); step 1 captures moment 1 and every
 // step's partial sums give moments 2n-1 and 2n.  Real uniform operators take
-// the steps after the first two at a time (four tile buffers), the others
-// one at a time in place (two buffers).  Workspace: the tile buffers, the
+// the steps after the first two at a time (three at a time in FP32; four tile
+// buffers), the others one at a time in place (two buffers).  Workspace: the tile buffers, the
 // tile's bounding box, then for doubling the partials of a pass's two steps
 // [regions][K][Bp] x 2 and the run sums [runs][K][Bp].
 template <typename T, bool C>
@@ -934,10 +1215,13 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
     for (int i = 0; i < 4; ++i) buf[i] = reinterpret_cast<S *>(ws) + (i < nbuf ? i : 0) * L2 * Bp_max;
     int32_t *cone = reinterpret_cast<int32_t *>(reinterpret_cast<S *>(ws) + nbuf * L2 * Bp_max);
     constexpr int K = C ? 4 : 3;
-    const int64_t Rmax = std::max(max_regions<T, C>(op->Lx, op->Ly, tile), two ? max_regions2<T>(op->Lx, op->Ly, tile) : 0);
+    const bool three = two && Step3Shape<T>::ON;
+    const int64_t Rmax = std::max({max_regions<T, C>(op->Lx, op->Ly, tile), two ? max_regions2<T>(op->Lx, op->Ly, tile) : 0,
+                                   three ? max_regions3<T>(op->Lx, op->Ly, tile) : 0});
     double *part = reinterpret_cast<double *>(cone) + kConeDoubles;
     double *part_b = part + (doubling ? Rmax * K * Bp_max : 0);
-    double *part2 = part_b + (doubling ? Rmax * K * Bp_max : 0);
+    double *part_c = part_b + (doubling ? Rmax * K * Bp_max : 0);
+    double *part2 = part_c + (doubling ? Rmax * K * Bp_max : 0);
     const void *onsite = std::is_same<T, double>::value ? (const void *)op->onsite64 : (const void *)op->onsite32;
     const void *bonds = std::is_same<T, double>::value ? op->bonds64 : op->bonds32;
     const int he_mult = C ? 2 : 1;
@@ -978,11 +1262,15 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         const int64_t chunks = ceil_div(Bt, kBlock);
         const Shape sh1 = choose_shape<T, C>(op->Lx, op->Ly, chunks);
         const int64_t regions1 = (int64_t)sh1.n_strips * sh1.n_segs;
-        int64_t regions2 = 0;
+        int64_t regions2 = 0, regions3 = 0;
         if constexpr (!C) {
             if (two) {
                 const Shape sh2 = choose_shape2<T>(op->Lx, op->Ly, chunks);
                 regions2 = (int64_t)sh2.n_strips * sh2.n_segs;
+            }
+            if (three) {
+                const Shape sh3 = choose_shape3<T>(op->Lx, op->Ly, chunks);
+                regions3 = (int64_t)sh3.n_strips * sh3.n_segs;
             }
         }
         auto reduce = [&](const double *pp, int64_t regions, int n) -> int {
@@ -1015,6 +1303,24 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         A.first = 0;
         A.mu_ee = doubling ? nullptr : mee;
         if constexpr (!C) {
+            while (three && n + 2 <= n_steps) {
+                A.n = n;
+                A.prev2 = P2;
+                A.prev1 = P1;
+                A.out = Q0;
+                A.out2 = Q1;
+                A.part = doubling ? part : nullptr;
+                A.part_b = doubling ? part_b : nullptr;
+                A.part_c = doubling ? part_c : nullptr;
+                int rc = launch_step3<T>(A, st);
+                if (rc) return rc;
+                if (doubling && ((rc = reduce(part, regions3, n)) || (rc = reduce(part_b, regions3, n + 1)) ||
+                                 (rc = reduce(part_c, regions3, n + 2))))
+                    return rc;
+                std::swap(P2, Q0);
+                std::swap(P1, Q1);
+                n += 3;
+            }
             while (two && n + 1 <= n_steps) {
                 A.n = n;
                 A.prev2 = P2;
@@ -1095,15 +1401,18 @@ static int64_t doubling_partial_bytes(const cbdg_op *op, int tile, int precision
     const bool two = uses_two_step(op);
     const int K = cplx ? 4 : 3;
     int64_t R;
+    const bool three = two && (precision == CBDG_FP64 ? Step3Shape<double>::ON : Step3Shape<float>::ON);
     if (precision == CBDG_FP64)
         R = cplx ? max_regions<double, true>(op->Lx, op->Ly, tile)
-                 : std::max(max_regions<double, false>(op->Lx, op->Ly, tile), two ? max_regions2<double>(op->Lx, op->Ly, tile) : 0);
+                 : std::max({max_regions<double, false>(op->Lx, op->Ly, tile), two ? max_regions2<double>(op->Lx, op->Ly, tile) : 0,
+                             three ? max_regions3<double>(op->Lx, op->Ly, tile) : 0});
     else
         R = cplx ? max_regions<float, true>(op->Lx, op->Ly, tile)
-                 : std::max(max_regions<float, false>(op->Lx, op->Ly, tile), two ? max_regions2<float>(op->Lx, op->Ly, tile) : 0);
+                 : std::max({max_regions<float, false>(op->Lx, op->Ly, tile), two ? max_regions2<float>(op->Lx, op->Ly, tile) : 0,
+                             three ? max_regions3<float>(op->Lx, op->Ly, tile) : 0});
     // every run count is at most min(kMaxGroups, ceil(R/4)) for R <= Rmax
     const int64_t G = std::min<int64_t>(kMaxGroups, ceil_div(R, 4));
-    return (2 * R + G) * K * lane_stride(tile) * (int64_t)sizeof(double);
+    return (3 * R + G) * K * lane_stride(tile) * (int64_t)sizeof(double);
 }
 
 static size_t tile_buffer_bytes(const cbdg_op *op, int64_t tile, int precision)

@@ -33,6 +33,7 @@ struct StepArgs {
                          // farther than n from that box (a_n is zero there)
     void *out2;          // two-step pass: a_{n+1}
     double *part_b;      // two-step pass: doubling partials of step n+1
+    double *part_c;      // three-step pass: doubling partials of step n+2
     double *nb_ee;       // neighbour moments [Bt][4][N] (+x, -x, +y, -y; complex
     double *nb_he;       //   interleaved for C), tile's first row, or null
 };

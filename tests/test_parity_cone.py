@@ -80,3 +80,24 @@ def test_invalid_sites_do_not_widen_or_empty_the_box(alg):
 def test_complex_bond_operator_corner(alg):
     w = W.small_random(36, 44, N=70, seed=26, complex_=True, bond=True, flux=0.2)
     _check(w, _block(36, 30, 36, 40, 44), 32, alg)
+
+
+@pytest.mark.parametrize("alg", ALGS)
+@pytest.mark.parametrize("Lx,Ly,bc,block,tile,N", [
+    (48, 80, {}, (0, 5, 0, 3), 64, 97),                          # corner tile, light cone
+    (36, 40, dict(bc_x=W.PERIODIC, bc_y=W.PERIODIC), (0, 4, 0, 4), 16, 64),
+    (64, 24, {}, (0, 3, 0, 24), 128, 66),                        # narrow column, three steps plus a pair
+    (13, 37, {}, (0, 13, 0, 37), 100, 65),                       # ragged strips, odd width
+])
+def test_fp32_multi_step_passes(alg, Lx, Ly, bc, block, tile, N):
+    """FP32 real operators take three steps per launch (plus a pair and a
+    single step for the remainder): moments within 2e-5 of the FP64 oracle."""
+    w = W.small_random(Lx, Ly, N=N, seed=Lx + Ly + N, **bc)
+    sites = _block(Lx, *block)
+    op, g_ee, g_he = gpu_moments(w, sites=sites, tile=tile, precision=1, algorithm=alg)
+    a, b = op.bounds.a, op.bounds.b
+    op.close()
+    o_ee, o_he = oracle.workload_moments(w, a, b, sites=sites)
+    e = max(maxdiff(g_ee, o_ee), maxdiff(g_he, o_he))
+    print("fp32 %dx%d N=%d alg=%d: max error %.2e" % (Lx, Ly, N, alg, e))
+    assert e < 2e-5
