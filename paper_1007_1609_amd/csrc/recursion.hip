@@ -1095,14 +1095,18 @@ static inline void doubling_groups(int64_t R, int64_t *per, int64_t *groups)
     *groups = ceil_div(R, *per);
 }
 
+// blockIdx.z selects one of the steps of a multi-step pass: its partials sit
+// pstride doubles after the previous step's, its run sums ostride after.
 template <bool C>
 __global__ __launch_bounds__(kBlock) void k_doubling_groups(
     const double *__restrict__ part, int64_t regions, int64_t per, int64_t Bp, int Bt,
-    double *__restrict__ out)
+    double *__restrict__ out, int64_t pstride, int64_t ostride)
 {
     constexpr int K = C ? 4 : 3;
     const int b = blockIdx.x * kBlock + threadIdx.x;
     if (b >= Bt) return;
+    part += blockIdx.z * pstride;
+    out += blockIdx.z * ostride;
     const int64_t g = blockIdx.y;
     const int64_t r0 = g * per, r1 = std::min<int64_t>(regions, r0 + per);
     double acc[K];
@@ -1117,12 +1121,16 @@ __global__ __launch_bounds__(kBlock) void k_doubling_groups(
     for (int k = 0; k < K; ++k) out[(g * K + k) * Bp + b] = acc[k];
 }
 
+// blockIdx.y selects the step n + blockIdx.y of a multi-step pass (run sums
+// ostride doubles apart); the steps write disjoint moments.
 template <bool C>
 __global__ __launch_bounds__(kRedWaves * kWave) void k_doubling_reduce(
     const double *__restrict__ part, int64_t regions, int64_t Bp, int Bt, int n, int N,
-    double *__restrict__ mu_ee, double *__restrict__ mu_he)
+    double *__restrict__ mu_ee, double *__restrict__ mu_he, int64_t ostride)
 {
     constexpr int K = C ? 4 : 3;
+    part += blockIdx.y * ostride;
+    n += blockIdx.y;
     __shared__ double red[kRedWaves][K][kWave];
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
     const int b = blockIdx.x * kWave + lane;
@@ -1273,14 +1281,18 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
                 regions3 = (int64_t)sh3.n_strips * sh3.n_segs;
             }
         }
-        auto reduce = [&](const double *pp, int64_t regions, int n) -> int {
+        // moments 2m-1, 2m for the steps m = n .. n+ns-1 of one launch, whose
+        // partials sit Rmax*K*Bp_max apart from `part` on
+        const int64_t pstride = Rmax * K * Bp_max, ostride = (int64_t)kMaxGroups * K * Bp_max;
+        auto reduce = [&](int64_t regions, int n, int ns) -> int {
             int64_t per = 0, groups = 0;
             doubling_groups(regions, &per, &groups);
-            hipLaunchKernelGGL((k_doubling_groups<C>), dim3((unsigned)ceil_div(Bt, kBlock), (unsigned)groups),
-                               dim3(kBlock), 0, st, pp, regions, per, Bp, Bt, part2);
+            hipLaunchKernelGGL((k_doubling_groups<C>),
+                               dim3((unsigned)ceil_div(Bt, kBlock), (unsigned)groups, (unsigned)ns),
+                               dim3(kBlock), 0, st, part, regions, per, Bp, Bt, part2, pstride, ostride);
             CBDG_CHECK_LAUNCH("k_doubling_groups");
-            hipLaunchKernelGGL((k_doubling_reduce<C>), dim3((unsigned)ceil_div(Bt, kWave)),
-                               dim3(kRedWaves * kWave), 0, st, part2, groups, Bp, Bt, n, N, mee, mhe);
+            hipLaunchKernelGGL((k_doubling_reduce<C>), dim3((unsigned)ceil_div(Bt, kWave), (unsigned)ns),
+                               dim3(kRedWaves * kWave), 0, st, part2, groups, Bp, Bt, n, N, mee, mhe, ostride);
             CBDG_CHECK_LAUNCH("k_doubling_reduce");
             return CBDG_OK;
         };
@@ -1297,7 +1309,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             A.mu_ee = mee;
             int rc = op->general ? launch_step<T, C, true>(A, st) : launch_step<T, C, false>(A, st);
             if (rc) return rc;
-            if (doubling && (rc = reduce(part, regions1, 1))) return rc;
+            if (doubling && (rc = reduce(regions1, 1, 1))) return rc;
             n = 2;
         }
         A.first = 0;
@@ -1314,9 +1326,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
                 A.part_c = doubling ? part_c : nullptr;
                 int rc = launch_step3<T>(A, st);
                 if (rc) return rc;
-                if (doubling && ((rc = reduce(part, regions3, n)) || (rc = reduce(part_b, regions3, n + 1)) ||
-                                 (rc = reduce(part_c, regions3, n + 2))))
-                    return rc;
+                if (doubling && (rc = reduce(regions3, n, 3))) return rc;
                 std::swap(P2, Q0);
                 std::swap(P1, Q1);
                 n += 3;
@@ -1331,7 +1341,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
                 A.part_b = doubling ? part_b : nullptr;
                 int rc = launch_step2<T>(A, st);
                 if (rc) return rc;
-                if (doubling && ((rc = reduce(part, regions2, n)) || (rc = reduce(part_b, regions2, n + 1)))) return rc;
+                if (doubling && (rc = reduce(regions2, n, 2))) return rc;
                 std::swap(P2, Q0);
                 std::swap(P1, Q1);
                 n += 2;
@@ -1345,7 +1355,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             A.part = doubling ? part : nullptr;
             int rc = op->general ? launch_step<T, C, true>(A, st) : launch_step<T, C, false>(A, st);
             if (rc) return rc;
-            if (doubling && (rc = reduce(part, regions1, n))) return rc;
+            if (doubling && (rc = reduce(regions1, n, 1))) return rc;
             std::swap(P1, P2);
         }
     }
@@ -1410,9 +1420,9 @@ static int64_t doubling_partial_bytes(const cbdg_op *op, int tile, int precision
         R = cplx ? max_regions<float, true>(op->Lx, op->Ly, tile)
                  : std::max({max_regions<float, false>(op->Lx, op->Ly, tile), two ? max_regions2<float>(op->Lx, op->Ly, tile) : 0,
                              three ? max_regions3<float>(op->Lx, op->Ly, tile) : 0});
-    // every run count is at most min(kMaxGroups, ceil(R/4)) for R <= Rmax
-    const int64_t G = std::min<int64_t>(kMaxGroups, ceil_div(R, 4));
-    return (3 * R + G) * K * lane_stride(tile) * (int64_t)sizeof(double);
+    // partials of up to three steps, then run sums of up to three steps at a
+    // stride of kMaxGroups runs
+    return (3 * R + 3 * (int64_t)kMaxGroups) * K * lane_stride(tile) * (int64_t)sizeof(double);
 }
 
 static size_t tile_buffer_bytes(const cbdg_op *op, int64_t tile, int precision)
