@@ -307,7 +307,7 @@ __global__ void k_seed_nb(double *nb_ee, double *nb_he, const int32_t *sites, in
     }
 }
 
-// Two recursion steps in one pass, for real operators with uniform hopping:
+// Two recursion steps in one pass:
 //     a_n     = 2 Ht a_{n-1} - a_{n-2}   (into A.out)
 //     a_{n+1} = 2 Ht a_n     - a_{n-1}   (into A.out2)
 // from a_{n-2} (A.prev2) and a_{n-1} (a1); the four buffers are distinct.  A
@@ -316,21 +316,21 @@ __global__ void k_seed_nb(double *nb_ee, double *nb_he, const int32_t *sites, in
 // rows out, a_{n-2} one out), so a_{n+1} needs nothing from other
 // workgroups.  Per two steps the vectors cross HBM four times (read a_{n-2},
 // a_{n-1}; write a_n, a_{n+1}) instead of six; the widened a_n costs extra
-// arithmetic and L2 reads only.
+// arithmetic and L2 reads only.  GEN: per-bond hopping and pairing (links of
+// the site and of its -x and -y neighbours, scalar loads).
 //
 // Row r of a_n is computed with rows r-1, r, r+1 of a_{n-1} in registers;
 // row r-1 of a_{n+1} follows from rows r-2, r-1, r of a_n.  Columns: a_{n-1}
 // at x0-2 .. x0+W+1 (index k <-> x0-2+k), a_n at x0-1 .. x0+W (k <-> x0-1+k).
-#ifndef CBDG_PF2
-#define CBDG_PF2 0
-#endif
-template <typename T, int W, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_cheb_step2(StepArgs A, const typename Storage<T, false>::type *__restrict__ a1,
-                                                      const OnSite<T> *__restrict__ ons)
+template <typename T, bool C, bool GEN, int W, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_cheb_step2(StepArgs A, const typename Storage<T, C>::type *__restrict__ a1,
+                                                      const OnSite<T> *__restrict__ ons,
+                                                      const void *__restrict__ bonds)
 {
-    using P = Pair<T, false>;
-    using S = typename Storage<T, false>::type;
+    using P = Pair<T, C>;
+    using S = typename Storage<T, C>::type;
     constexpr int X = W + 2, Y = W + 4;
+    constexpr int K = C ? 4 : 3;
     const int lb = xcd_remap(blockIdx.x, A.nblocks);
     const int strip = lb % A.n_strips;
     const int rest = lb / A.n_strips;
@@ -362,9 +362,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step2(StepArgs A, const typenam
         if (skip) {
             if constexpr (DOT) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    A.part[(region * 3 + k) * Bp + b] = 0.0;
-                    A.part_b[(region * 3 + k) * Bp + b] = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    A.part[(region * K + k) * Bp + b] = 0.0;
+                    A.part_b[(region * K + k) * Bp + b] = 0.0;
                 }
             }
             return;
@@ -392,126 +392,139 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step2(StepArgs A, const typenam
         }
     }
     // in-bounds row index of y and its mask
-    auto row_of = [&](int y, uint32_t &ok) -> int64_t {
-        if (A.bcy) { ok = ~0u; return (int64_t)(((y % Ly) + Ly) % Ly) * Lx; }
+    auto row_y = [&](int y, uint32_t &ok) -> int {
+        if (A.bcy) { ok = ~0u; return ((y % Ly) + Ly) % Ly; }
         const bool in = y >= 0 && y < Ly;
         ok = in ? ~0u : 0u;
-        return (int64_t)(in ? y : (y < 0 ? 0 : Ly - 1)) * Lx;
+        return in ? y : (y < 0 ? 0 : Ly - 1);
     };
     auto load_row1 = [&](P *row, int y) -> uint32_t {
         uint32_t ok;
-        const int64_t rb = row_of(y, ok);
+        const int64_t rb = (int64_t)row_y(y, ok) * Lx;
 #pragma unroll
-        for (int k = 0; k < Y; ++k) row[k] = ld<T, false>(a1 + (rb + cx[k]) * Bp + b);
+        for (int k = 0; k < Y; ++k) row[k] = ld<T, C>(a1 + (rb + cx[k]) * Bp + b);
         return ok;
     };
     auto mask_row1 = [&](P *row, uint32_t rm) {
 #pragma unroll
-        for (int k = 0; k < Y; ++k) row[k] = masked<T, false>(row[k], rm & cm[k]);
+        for (int k = 0; k < Y; ++k) row[k] = masked<T, C>(row[k], rm & cm[k]);
+    };
+    // (Ht v)(s) at column xc, row yy from the centre and its four neighbours
+    auto apply = [&](int64_t s, int xc, int yy, const P &c, const P &l, const P &r, const P &up, const P &dn) -> P {
+        const OnSite<T> o = ons[s];
+        if constexpr (GEN) {
+            const int64_t sl = xc > 0 ? s - 1 : (A.bcx ? s + Lx - 1 : -1);
+            const int64_t sd = yy > 0 ? s - Lx : (A.bcy ? s + (int64_t)(Ly - 1) * Lx : -1);
+            Link<T, C> lk[4];
+            links_of<T, C>(bonds, s, sl, sd, lk);
+            const P nb[4] = {r, l, dn, up};  // +x, -x, +y, -y
+            return apply_general<T, C>(o, c, nb, lk);
+        } else {
+            return apply_uniform<T, C>(o, th, c, l, r, up, dn);
+        }
+    };
+    auto dots = [&](double *acc, const P &v, const P &c) {
+        if constexpr (C) {
+            const double er = v.er, ei = v.ei, hr = v.hr, hi = v.hi;
+            const double cer = c.er, cei = c.ei, chr = c.hr, chi = c.hi;
+            acc[0] += (er * er + ei * ei) + (hr * hr + hi * hi);
+            acc[1] += (er * cer + ei * cei) + (hr * chr + hi * chi);
+            acc[2] += (er * chr - ei * chi) - (hr * cer - hi * cei);
+            acc[3] += (er * chi + ei * chr) - (hr * cei + hi * cer);
+        } else {
+            const double e = v.e, h = v.h, ce = c.e, ch = c.h;
+            acc[0] += e * e + h * h;
+            acc[1] += e * ce + h * ch;
+            acc[2] += e * ch - h * ce;
+        }
     };
 
     P w0[Y], w1[Y], w2[Y], nx[Y];      // a_{n-1} rows r-1, r, r+1, r+2
     P m2[X], m1[X], m0[X];             // a_n rows r-2, r-1, r
     P p2[X];                           // a_{n-2} row r
-    [[maybe_unused]] P p2n[CBDG_PF2 ? X : 1];  // a_{n-2} row r + 1 (prefetch)
-    P mval = zero_pair<T, false>(), mval1 = zero_pair<T, false>();
+    P mval = zero_pair<T, C>(), mval1 = zero_pair<T, C>();
     bool found = false, found1 = false;
-    double d_nn = 0.0, d_nm = 0.0, d_b = 0.0, e_nn = 0.0, e_nm = 0.0, e_b = 0.0;
+    double d0[K], d1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { d0[k] = 0.0; d1[k] = 0.0; }
     mask_row1(w0, load_row1(w0, y0 - 2));
     mask_row1(w1, load_row1(w1, y0 - 1));
     mask_row1(w2, load_row1(w2, y0));
 #pragma unroll
-    for (int k = 0; k < X; ++k) { m1[k] = zero_pair<T, false>(); m0[k] = zero_pair<T, false>(); }
-    auto load_row2 = [&](P *row, int y) {
-        uint32_t ok;
-        const int64_t rb = row_of(y, ok);
-#pragma unroll
-        for (int k = 0; k < X; ++k) row[k] = CBDG_NT_A2 ? ld_nt<T, false>(a2 + (rb + cx[k + 1]) * Bp + b)
-                                                        : ld<T, false>(a2 + (rb + cx[k + 1]) * Bp + b);
-    };
-    if constexpr (CBDG_PF2) load_row2(p2, y0 - 1);
+    for (int k = 0; k < X; ++k) { m1[k] = zero_pair<T, C>(); m0[k] = zero_pair<T, C>(); }
 
 #pragma unroll 1
     for (int r = y0 - 1; r <= y1; ++r) {
         uint32_t nm = 0;
         if (r + 2 <= y1 + 1) nm = load_row1(nx, r + 2);
-        if constexpr (CBDG_PF2) {
-            if (r + 1 <= y1) load_row2(p2n, r + 1);
-        } else {
-            load_row2(p2, r);
-        }
         uint32_t rok;
-        const int64_t rb = row_of(r, rok);
+        const int ry = row_y(r, rok);
+        const int64_t rb = (int64_t)ry * Lx;
+#pragma unroll
+        for (int k = 0; k < X; ++k) p2[k] = CBDG_NT_A2 ? ld_nt<T, C>(a2 + (rb + cx[k + 1]) * Bp + b)
+                                                      : ld<T, C>(a2 + (rb + cx[k + 1]) * Bp + b);
 #pragma unroll
         for (int k = 0; k < X; ++k) { m2[k] = m1[k]; m1[k] = m0[k]; }
         // a_n, row r, columns x0-1 .. x0+W
         const bool own_r = r >= y0 && r < y1;
 #pragma unroll
         for (int k = 0; k < X; ++k) {
-            const OnSite<T> o = ons[rb + cx[k + 1]];
-            const P yv = apply_uniform<T, false>(o, th, w1[k + 1], w1[k], w1[k + 2], w0[k + 1], w2[k + 1]);
-            m0[k] = masked<T, false>(cheb_combine<T, false>(yv, p2[k], false), rok & cm[k + 1]);
+            const P yv = apply(rb + cx[k + 1], cx[k + 1], ry, w1[k + 1], w1[k], w1[k + 2], w0[k + 1], w2[k + 1]);
+            m0[k] = masked<T, C>(cheb_combine<T, C>(yv, p2[k], false), rok & cm[k + 1]);
         }
         if (own_r) {
 #pragma unroll
             for (int k = 1; k <= W; ++k) {
                 const int64_t s = rb + x0 + k - 1;
                 const P &v = m0[k];
-                if constexpr (CBDG_NT_OUT) st_nt<T, false>(ao + s * Bp + b, v);
-                else st<T, false>(ao + s * Bp + b, v);
+                if constexpr (CBDG_NT_OUT) st_nt<T, C>(ao + s * Bp + b, v);
+                else st<T, C>(ao + s * Bp + b, v);
                 const bool hit = s == my_site;
                 found = found || hit;
-                mval = select_pair<T, false>(hit, v, mval);
-                if constexpr (DOT) {
-                    const double e = v.e, h = v.h, ce = w1[k + 1].e, ch = w1[k + 1].h;
-                    d_nn += e * e + h * h;
-                    d_nm += e * ce + h * ch;
-                    d_b += e * ch - h * ce;
-                }
+                mval = select_pair<T, C>(hit, v, mval);
+                if constexpr (DOT) dots(d0, v, w1[k + 1]);
             }
         }
         // a_{n+1}, row r-1, own columns
         if (r - 1 >= y0) {
-            uint32_t qok;
-            const int64_t qb = row_of(r - 1, qok);
+            const int64_t qb = (int64_t)(r - 1) * Lx;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const int64_t s = qb + x0 + k;
-                const OnSite<T> o = ons[s];
-                const P yv = apply_uniform<T, false>(o, th, m1[k + 1], m1[k], m1[k + 2], m2[k + 1], m0[k + 1]);
-                const P v = cheb_combine<T, false>(yv, w0[k + 2], false);
-                if constexpr (CBDG_NT_OUT) st_nt<T, false>(ao2 + s * Bp + b, v);
-                else st<T, false>(ao2 + s * Bp + b, v);
+                const P yv = apply(s, x0 + k, r - 1, m1[k + 1], m1[k], m1[k + 2], m2[k + 1], m0[k + 1]);
+                const P v = cheb_combine<T, C>(yv, w0[k + 2], false);
+                if constexpr (CBDG_NT_OUT) st_nt<T, C>(ao2 + s * Bp + b, v);
+                else st<T, C>(ao2 + s * Bp + b, v);
                 const bool hit = s == my_site;
                 found1 = found1 || hit;
-                mval1 = select_pair<T, false>(hit, v, mval1);
-                if constexpr (DOT) {
-                    const double e = v.e, h = v.h, ce = m1[k + 1].e, ch = m1[k + 1].h;
-                    e_nn += e * e + h * h;
-                    e_nm += e * ce + h * ch;
-                    e_b += e * ch - h * ce;
-                }
+                mval1 = select_pair<T, C>(hit, v, mval1);
+                if constexpr (DOT) dots(d1, v, m1[k + 1]);
             }
         }
         if (r + 2 <= y1 + 1) mask_row1(nx, nm);
 #pragma unroll
         for (int k = 0; k < Y; ++k) { w0[k] = w1[k]; w1[k] = w2[k]; w2[k] = nx[k]; }
-        if constexpr (CBDG_PF2) {
-#pragma unroll
-            for (int k = 0; k < X; ++k) p2[k] = p2n[k];
-        }
     }
 
     if constexpr (DOT) {
-        double *pp = A.part + region * 3 * Bp + b;
-        pp[0] = d_nn; pp[Bp] = d_nm; pp[2 * Bp] = d_b;
-        double *qq = A.part_b + region * 3 * Bp + b;
-        qq[0] = e_nn; qq[Bp] = e_nm; qq[2 * Bp] = e_b;
+        double *pp = A.part + region * K * Bp + b;
+        double *qq = A.part_b + region * K * Bp + b;
+#pragma unroll
+        for (int k = 0; k < K; ++k) { pp[k * Bp] = d0[k]; qq[k * Bp] = d1[k]; }
     }
     if (A.mu_ee) {
         const int64_t m = (int64_t)b * A.N + A.n;
-        if (found) { A.mu_ee[m] = (double)mval.e; A.mu_he[m] = (double)mval.h; }
-        if (found1) { A.mu_ee[m + 1] = (double)mval1.e; A.mu_he[m + 1] = (double)mval1.h; }
+        if constexpr (C) {
+            if (found) { A.mu_ee[m] = (double)mval.er; A.mu_he[2 * m] = (double)mval.hr; A.mu_he[2 * m + 1] = (double)mval.hi; }
+            if (found1) {
+                A.mu_ee[m + 1] = (double)mval1.er;
+                A.mu_he[2 * (m + 1)] = (double)mval1.hr;
+                A.mu_he[2 * (m + 1) + 1] = (double)mval1.hi;
+            }
+        } else {
+            if (found) { A.mu_ee[m] = (double)mval.e; A.mu_he[m] = (double)mval.h; }
+            if (found1) { A.mu_ee[m + 1] = (double)mval1.e; A.mu_he[m + 1] = (double)mval1.h; }
+        }
     }
 }
 
@@ -928,70 +941,86 @@ static int launch_step(StepArgs A, hipStream_t st)
 #ifndef CBDG_TGT2
 #define CBDG_TGT2 512
 #endif
-template <typename T> struct Step2Shape;
-template <> struct Step2Shape<double> { static constexpr int W = CBDG_W2_F64, YS = CBDG_YS2; };
-template <> struct Step2Shape<float> { static constexpr int W = CBDG_W2_F32, YS = CBDG_YS2; };
+// Two-step passes for complex operators and per-bond coefficients are
+// available but off: on one 1024-vector tile of the 512x512 Peierls/d-wave
+// lattice (N = 258 by doubling) they were slower than one step per launch,
+// complex128 1371 (W = 2) / 1668 (W = 1) vs 1030 us per moment index,
+// complex64 485 (W = 4 or 2) vs 432 -- the widened windows of 32-byte pairs
+// and the per-site link loads outweigh the saved traffic.
+#ifndef CBDG_TWO_STEP_GEN
+#define CBDG_TWO_STEP_GEN 0
+#endif
+#ifndef CBDG_W2_C128
+#define CBDG_W2_C128 2
+#endif
+#ifndef CBDG_W2_C64
+#define CBDG_W2_C64 4
+#endif
+template <typename T, bool C> struct Step2Shape;
+template <> struct Step2Shape<double, false> { static constexpr int W = CBDG_W2_F64; };
+template <> struct Step2Shape<float, false> { static constexpr int W = CBDG_W2_F32; };
+template <> struct Step2Shape<double, true> { static constexpr int W = CBDG_W2_C128; };
+template <> struct Step2Shape<float, true> { static constexpr int W = CBDG_W2_C64; };
 
-template <typename T>
+template <typename T, bool C>
 static Shape choose_shape2(int Lx, int Ly, int64_t n_chunks)
 {
     Shape sh;
-    constexpr int WB = Step2Shape<T>::W;
-    sh.W = (Lx % WB == 0) ? WB : (Lx % 4 == 0 ? 4 : (Lx % 2 == 0 ? 2 : 1));
+    constexpr int WB = Step2Shape<T, C>::W;
+    sh.W = (Lx % WB == 0) ? WB : (Lx % 4 == 0 && WB > 4 ? 4 : (Lx % 2 == 0 && WB > 2 ? 2 : 1));
     sh.PF = false;
     sh.n_strips = Lx / sh.W;
-    int ys = Step2Shape<T>::YS;
+    int ys = CBDG_YS2;
     while (ys > 8 && (int64_t)sh.n_strips * n_chunks * ceil_div(Ly, ys) < CBDG_TGT2) ys /= 2;
     sh.ys = ys;
     sh.n_segs = (int)ceil_div(Ly, sh.ys);
     return sh;
 }
 
-template <typename T>
+template <typename T, bool C>
 static int64_t max_regions2(int Lx, int Ly, int tile)
 {
     int64_t r = 0;
     for (int64_t c = 1; c <= ceil_div(tile, kBlock); ++c) {
-        const Shape sh = choose_shape2<T>(Lx, Ly, c);
+        const Shape sh = choose_shape2<T, C>(Lx, Ly, c);
         r = std::max<int64_t>(r, (int64_t)sh.n_strips * sh.n_segs);
     }
     return r;
 }
 
-template <typename T, int W>
+template <typename T, bool C, bool GEN, int W>
 static int launch_step2_w(StepArgs A, hipStream_t st)
 {
     const int n_chunks = (int)ceil_div(A.Bt, kBlock);
     const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
     A.nblocks = (int)nb;
-    const auto *a1 = reinterpret_cast<const typename Storage<T, false>::type *>(A.prev1);
+    const auto *a1 = reinterpret_cast<const typename Storage<T, C>::type *>(A.prev1);
     const auto *ons = reinterpret_cast<const OnSite<T> *>(A.onsite);
-    if (A.part) hipLaunchKernelGGL((k_cheb_step2<T, W, true>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons);
-    else hipLaunchKernelGGL((k_cheb_step2<T, W, false>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons);
+    if (A.part) hipLaunchKernelGGL((k_cheb_step2<T, C, GEN, W, true>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons, A.bonds);
+    else hipLaunchKernelGGL((k_cheb_step2<T, C, GEN, W, false>), dim3(A.nblocks), dim3(kBlock), 0, st, A, a1, ons, A.bonds);
     CBDG_CHECK_LAUNCH("k_cheb_step2");
     return CBDG_OK;
 }
 
-template <typename T>
+template <typename T, bool C, bool GEN>
 static int launch_step2(StepArgs A, hipStream_t st)
 {
-    const Shape sh = choose_shape2<T>(A.Lx, A.Ly, ceil_div(A.Bt, kBlock));
+    const Shape sh = choose_shape2<T, C>(A.Lx, A.Ly, ceil_div(A.Bt, kBlock));
     A.n_strips = sh.n_strips;
     A.ys = sh.ys;
     A.n_segs = sh.n_segs;
-#if CBDG_W2_F32 == 16 || CBDG_W2_F64 == 16
-    if (sh.W == 16) return launch_step2_w<T, 16>(A, st);
-#endif
-    if (sh.W == 8) return launch_step2_w<T, 8>(A, st);
-    if (sh.W == 4) return launch_step2_w<T, 4>(A, st);
-    if (sh.W == 2) return launch_step2_w<T, 2>(A, st);
-    return launch_step2_w<T, 1>(A, st);
+    constexpr int WB = Step2Shape<T, C>::W;
+    if (sh.W == WB) return launch_step2_w<T, C, GEN, WB>(A, st);
+    if constexpr (WB > 4) { if (sh.W == 4) return launch_step2_w<T, C, GEN, 4>(A, st); }
+    if constexpr (WB > 2) { if (sh.W == 2) return launch_step2_w<T, C, GEN, 2>(A, st); }
+    return launch_step2_w<T, C, GEN, 1>(A, st);
 }
 
 static bool uses_two_step(const cbdg_op *op)
 {
-    return CBDG_TWO_STEP && op->scalar == CBDG_REAL && !op->general;
+    if (op->scalar == CBDG_REAL && !op->general) return CBDG_TWO_STEP;
+    return CBDG_TWO_STEP && CBDG_TWO_STEP_GEN;
 }
 
 // Three-step passes (k_cheb_step3), used for FP32 only.  One 1024-vector tile
@@ -1217,14 +1246,14 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
     using S = typename Storage<T, C>::type;
     const int64_t L2 = op->L2;
     const int64_t Bp_max = lane_stride(tile);
-    const bool two = !C && uses_two_step(op) && !nb_ee;
+    const bool two = uses_two_step(op) && !nb_ee;
     const int nbuf = two ? 4 : 2;
     S *buf[4];
     for (int i = 0; i < 4; ++i) buf[i] = reinterpret_cast<S *>(ws) + (i < nbuf ? i : 0) * L2 * Bp_max;
     int32_t *cone = reinterpret_cast<int32_t *>(reinterpret_cast<S *>(ws) + nbuf * L2 * Bp_max);
     constexpr int K = C ? 4 : 3;
-    const bool three = two && Step3Shape<T>::ON;
-    const int64_t Rmax = std::max({max_regions<T, C>(op->Lx, op->Ly, tile), two ? max_regions2<T>(op->Lx, op->Ly, tile) : 0,
+    const bool three = two && !C && !op->general && Step3Shape<T>::ON;
+    const int64_t Rmax = std::max({max_regions<T, C>(op->Lx, op->Ly, tile), two ? max_regions2<T, C>(op->Lx, op->Ly, tile) : 0,
                                    three ? max_regions3<T>(op->Lx, op->Ly, tile) : 0});
     double *part = reinterpret_cast<double *>(cone) + kConeDoubles;
     double *part_b = part + (doubling ? Rmax * K * Bp_max : 0);
@@ -1271,15 +1300,13 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         const Shape sh1 = choose_shape<T, C>(op->Lx, op->Ly, chunks);
         const int64_t regions1 = (int64_t)sh1.n_strips * sh1.n_segs;
         int64_t regions2 = 0, regions3 = 0;
-        if constexpr (!C) {
-            if (two) {
-                const Shape sh2 = choose_shape2<T>(op->Lx, op->Ly, chunks);
-                regions2 = (int64_t)sh2.n_strips * sh2.n_segs;
-            }
-            if (three) {
-                const Shape sh3 = choose_shape3<T>(op->Lx, op->Ly, chunks);
-                regions3 = (int64_t)sh3.n_strips * sh3.n_segs;
-            }
+        if (two) {
+            const Shape sh2 = choose_shape2<T, C>(op->Lx, op->Ly, chunks);
+            regions2 = (int64_t)sh2.n_strips * sh2.n_segs;
+        }
+        if (three) {
+            const Shape sh3 = choose_shape3<T>(op->Lx, op->Ly, chunks);
+            regions3 = (int64_t)sh3.n_strips * sh3.n_segs;
         }
         // moments 2m-1, 2m for the steps m = n .. n+ns-1 of one launch, whose
         // partials sit Rmax*K*Bp_max apart from `part` on
@@ -1331,21 +1358,28 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
                 std::swap(P1, Q1);
                 n += 3;
             }
-            while (two && n + 1 <= n_steps) {
-                A.n = n;
-                A.prev2 = P2;
-                A.prev1 = P1;
-                A.out = Q0;
-                A.out2 = Q1;
-                A.part = doubling ? part : nullptr;
-                A.part_b = doubling ? part_b : nullptr;
-                int rc = launch_step2<T>(A, st);
-                if (rc) return rc;
-                if (doubling && (rc = reduce(regions2, n, 2))) return rc;
-                std::swap(P2, Q0);
-                std::swap(P1, Q1);
-                n += 2;
-            }
+        }
+        while (two && n + 1 <= n_steps) {
+            A.n = n;
+            A.prev2 = P2;
+            A.prev1 = P1;
+            A.out = Q0;
+            A.out2 = Q1;
+            A.part = doubling ? part : nullptr;
+            A.part_b = doubling ? part_b : nullptr;
+            int rc;
+#if CBDG_TWO_STEP_GEN
+            rc = op->general ? launch_step2<T, C, true>(A, st) : launch_step2<T, C, false>(A, st);
+#else
+            if constexpr (C) rc = fail(CBDG_EUNSUPPORTED, "chebyshev_moments: two-step passes for complex operators are off");
+            else if (op->general) rc = fail(CBDG_EUNSUPPORTED, "chebyshev_moments: two-step passes for bond coefficients are off");
+            else rc = launch_step2<T, false, false>(A, st);
+#endif
+            if (rc) return rc;
+            if (doubling && (rc = reduce(regions2, n, 2))) return rc;
+            std::swap(P2, Q0);
+            std::swap(P1, Q1);
+            n += 2;
         }
         for (; n <= n_steps; ++n) {
             A.n = n;
@@ -1411,14 +1445,14 @@ static int64_t doubling_partial_bytes(const cbdg_op *op, int tile, int precision
     const bool two = uses_two_step(op);
     const int K = cplx ? 4 : 3;
     int64_t R;
-    const bool three = two && (precision == CBDG_FP64 ? Step3Shape<double>::ON : Step3Shape<float>::ON);
+    const bool three = two && !cplx && !op->general && (precision == CBDG_FP64 ? Step3Shape<double>::ON : Step3Shape<float>::ON);
     if (precision == CBDG_FP64)
-        R = cplx ? max_regions<double, true>(op->Lx, op->Ly, tile)
-                 : std::max({max_regions<double, false>(op->Lx, op->Ly, tile), two ? max_regions2<double>(op->Lx, op->Ly, tile) : 0,
+        R = cplx ? std::max(max_regions<double, true>(op->Lx, op->Ly, tile), two ? max_regions2<double, true>(op->Lx, op->Ly, tile) : 0)
+                 : std::max({max_regions<double, false>(op->Lx, op->Ly, tile), two ? max_regions2<double, false>(op->Lx, op->Ly, tile) : 0,
                              three ? max_regions3<double>(op->Lx, op->Ly, tile) : 0});
     else
-        R = cplx ? max_regions<float, true>(op->Lx, op->Ly, tile)
-                 : std::max({max_regions<float, false>(op->Lx, op->Ly, tile), two ? max_regions2<float>(op->Lx, op->Ly, tile) : 0,
+        R = cplx ? std::max(max_regions<float, true>(op->Lx, op->Ly, tile), two ? max_regions2<float, true>(op->Lx, op->Ly, tile) : 0)
+                 : std::max({max_regions<float, false>(op->Lx, op->Ly, tile), two ? max_regions2<float, false>(op->Lx, op->Ly, tile) : 0,
                              three ? max_regions3<float>(op->Lx, op->Ly, tile) : 0});
     // partials of up to three steps, then run sums of up to three steps at a
     // stride of kMaxGroups runs
