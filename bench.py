@@ -129,8 +129,9 @@ def main():
                          "512x512 Peierls/d-wave LDOS workload; adjoint: 128x128 gradients and "
                          "Newton-Krylov; scf: full self-consistent solve of the 256x256 workload; "
                          "paper: the paper's two example geometries")
-    ap.add_argument("--scf-method", choices=["plain", "nk-fd"], default="plain",
-                    help="--form scf: plain mixing, or Newton-Krylov with finite-difference products")
+    ap.add_argument("--scf-method", choices=["plain", "nk-fd", "anderson"], default="plain",
+                    help="--form scf: plain mixing, Newton-Krylov with finite-difference products, "
+                         "or Anderson mixing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path "

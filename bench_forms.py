@@ -288,6 +288,11 @@ def scf_form(args, dev):
         how = "plain mixing (alpha=1)"
         passes = r.iterations
         extra = {}
+    elif method == "anderson":
+        r = scf.anderson_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60, callback=cb)
+        how = "Anderson mixing (depth 5, beta 1)"
+        passes = r.iterations
+        extra = {}
     else:
         r = scf.newton_krylov(op, w.U, d0, w.N, w.tile, tol=1e-6, jv="fd", callback=cb)
         how = "Newton-Krylov with finite-difference Jacobian products after plain-mixing warm-up to 1e-2"

@@ -163,6 +163,68 @@ def _gmres(matvec, rhs, tol, restart=30, maxiter=60):
     return x, used
 
 
+def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
+                    precision: int = L.CBDG_FP64, depth: int = 5, beta: float = 1.0, tol: float = 1e-6,
+                    max_iter: int = 200, kernel: str = "jackson", E_c: float = 0.0, T: float = 0.0,
+                    warmup_tol: float = 1e-2, callback=None) -> ScfResult:
+    """The fixed point Delta = F(Delta) of the plain-mixing loop, accelerated by
+    Anderson mixing: with g_k = F(Delta_k) - Delta_k and the differences of the
+    last `depth` iterates (dX) and residuals (dG),
+        gamma = argmin ||g_k - dG gamma||,
+        Delta_{k+1} = Delta_k + beta g_k - (dX + beta dG) gamma.
+    The gap map also has the trivial fixed point Delta = 0 (and -Delta), so
+    plain-mixing steps come first until max|F - Delta| < warmup_tol, as for
+    Newton-Krylov; the history restarts when a step raises the residual.
+    One gap-map evaluation per iteration, as plain mixing; the stopping test is
+    the same max|F(Delta) - Delta| < tol.  Real order parameters."""
+    dev = delta0.device
+    sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
+    w = op.weights(kernel, E_c=E_c, T=T)
+    coeff = sum_coefficients(w, N, L.CBDG_QTY_GAP, dev) if T > 0 else None
+    ws = workspace(moments_workspace_bytes(op, min(tile, op.L2), precision), dev)
+    mu_ee = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
+    mu_he = torch.empty((op.L2, N), dtype=delta0.dtype, device=dev)
+    resid = torch.empty(1, dtype=torch.float64, device=dev)
+    hist: List[float] = []
+    t0 = time.perf_counter()
+    x = delta0.clone()
+    xs, gs = [], []
+    r = float("inf")
+    it = 0
+    for it in range(1, max_iter + 1):
+        op.update_delta(x)
+        chebyshev_moments(op, sites, N, tile, precision, ws=ws, out=(mu_ee, mu_he))
+        fx, _ = gap_update(mu_he, w, U, x, 1.0, resid=resid, coeff=coeff)
+        g = fx - x
+        r = float(resid.item())
+        hist.append(r)
+        if callback is not None:
+            callback(it, r)
+        if not (r == r):
+            raise L.CbdgError(L.CBDG_EBOUNDS, "scf", "non-finite residual at iteration %d" % it)
+        if r < tol:
+            x = fx
+            break
+        if r >= max(tol, warmup_tol) or (len(hist) > 1 and r > 2.0 * hist[-2]):
+            xs, gs = [], []
+            x = fx  # plain step
+            continue
+        xs.append(x)
+        gs.append(g)
+        if len(xs) > depth + 1:
+            xs.pop(0)
+            gs.pop(0)
+        if len(xs) == 1:
+            x = x + beta * g
+            continue
+        dX = torch.stack([xs[i + 1] - xs[i] for i in range(len(xs) - 1)], dim=1)
+        dG = torch.stack([gs[i + 1] - gs[i] for i in range(len(gs) - 1)], dim=1)
+        gamma = torch.linalg.lstsq(dG.cpu(), g.cpu().unsqueeze(1)).solution.to(dev).squeeze(1)
+        x = x + beta * g - (dX + beta * dG) @ gamma
+    torch.cuda.synchronize()
+    return ScfResult(x, it, r, hist, time.perf_counter() - t0, it)
+
+
 def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
                   tol: float = 1e-6, max_newton: int = 30, jv: str = "vjp", fd_step: float = 1e-7,
                   gmres_tol: float = 1e-2, warmup_tol: float = 1e-2, max_warmup: int = 100,

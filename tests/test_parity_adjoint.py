@@ -249,3 +249,20 @@ def test_newton_krylov_matches_plain_mixing(jv):
         plain.moment_passes, jv, nk.counts["newton"], nk.counts))
     assert plain.residual < 1e-9 and nk.residual < 1e-9
     assert maxdiff(plain.delta.cpu().numpy(), nk.delta.cpu().numpy()) < 2e-8
+
+
+def test_anderson_mixing_reaches_the_plain_mixing_fixed_point():
+    P = _P()
+    from paper_1007_1609_amd import scf
+    w = _small_cfg4(L=20, N=192)
+    d0 = torch.as_tensor(w.delta, device=DEV)
+    op = P.Operator.from_workload(w, DEV)
+    plain = scf.plain_mixing(op, w.U, d0, w.N, w.tile, tol=1e-9, max_iter=400)
+    op.close()
+    op = P.Operator.from_workload(w, DEV)
+    aa = scf.anderson_mixing(op, w.U, d0, w.N, w.tile, tol=1e-9, max_iter=200)
+    op.close()
+    print("plain mixing %d iterations, Anderson %d" % (plain.iterations, aa.iterations))
+    assert aa.residual < 1e-9
+    assert maxdiff(plain.delta.cpu().numpy(), aa.delta.cpu().numpy()) < 2e-8
+    assert aa.iterations < plain.iterations
