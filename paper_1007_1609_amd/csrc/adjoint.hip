@@ -30,8 +30,14 @@
 // (each term only where its moment index lies in 2..N-1), plus at m = 1 the
 // start-site terms of mu_ee[1] and mu_he[1], whose cotangents collect
 // g[1] - sum_{m>=2} g[2m-1].  The same transposed recursion then runs over
-// m = M .. 1 only: half the forward and adjoint steps, at the price of two
-// more vector reads per adjoint step.
+// m = M .. 1 only: half the forward and adjoint steps, at the price of one
+// more vector read per adjoint step (a_m, with the halo of its strip:
+// a_{m+1} is formed in registers as 2 Ht a_m - a_{m-1}).
+//
+// The forward pass and the segment recomputations take two recursion steps
+// per launch where the operator allows it (the forward moments' two-step
+// pass), so a stored or recomputed a_m moves through HBM as in the forward
+// moments.
 //
 // The sum over the tile's vectors is a wavefront reduction per site; each
 // (64-vector chunk, site) partial is owned by one wavefront, accumulated over
@@ -62,7 +68,6 @@ struct AdjArgs {
     int n_strips, n_segs, nblocks;
     int ys;               // rows per segment
     const void *acur;     // a_m (doubling)
-    const void *anext;    // a_{m+1} (doubling, when a moment 2m+1 <= N-1 exists)
     const double *d1;     // [Bt][2] start-site cotangents of mu_ee[1], mu_he[1] (doubling)
 };
 
@@ -123,7 +128,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
         wh = (active && A.dmu_he) ? A.dmu_he[(int64_t)b * A.N + A.n] : 0.0;
     }
     const S *am = reinterpret_cast<const S *>(A.acur);
-    const S *ap = reinterpret_cast<const S *>(A.anext);
     double *gp = A.gpart + (int64_t)c64 * A.L2 * 2;
 
     int cx[W + 2];
@@ -137,14 +141,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
         else { ok = true; cx[k] = x; }
         cm[k] = ok ? ~0u : 0u;
     }
-    auto load_row = [&](P *row, int y) -> uint32_t {
+    auto load_row = [&](const S *base_ptr, P *row, int y) -> uint32_t {
         bool ok = true;
         int yy = y;
         if (y < 0) { ok = A.bcy != 0; yy = A.bcy ? y + Ly : 0; }
         else if (y >= Ly) { ok = A.bcy != 0; yy = A.bcy ? y - Ly : Ly - 1; }
         const int64_t rbase = (int64_t)yy * Lx;
 #pragma unroll
-        for (int k = 0; k < W + 2; ++k) row[k] = ld<double, false>(lam1 + (rbase + cx[k]) * Bp + b);
+        for (int k = 0; k < W + 2; ++k) row[k] = ld<double, false>(base_ptr + (rbase + cx[k]) * Bp + b);
         return ok ? ~0u : 0u;
     };
     auto apply_mask = [&](P *row, uint32_t rm) {
@@ -160,18 +164,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
         }
     };
 
+    // lam_{n+1} rows y-1 .. y+2; under doubling also a_n rows y-1 .. y+2,
+    // from which a_{n+1} = 2 Ht a_n - a_{n-1} is formed in registers exactly
+    // as the forward step formed it
+    constexpr int WM = DBL ? W + 2 : 1;
     P up[W + 2], cur[W + 2], dn[W + 2], nx[W + 2];
     P pc[W], pn[W], ac[W], an[W];
-    [[maybe_unused]] P mc[DBL ? W : 1], mn[DBL ? W : 1], qc[NXT ? W : 1], qn[NXT ? W : 1];
+    [[maybe_unused]] P mup[WM], mcur[WM], mdn[WM], mnx[WM];
     if constexpr (HAS1) {
-        apply_mask(up, load_row(up, y0 - 1));
-        apply_mask(cur, load_row(cur, y0));
-        apply_mask(dn, load_row(dn, y0 + 1));
+        apply_mask(up, load_row(lam1, up, y0 - 1));
+        apply_mask(cur, load_row(lam1, cur, y0));
+        apply_mask(dn, load_row(lam1, dn, y0 + 1));
+    }
+    if constexpr (DBL) {
+        apply_mask(mup, load_row(am, mup, y0 - 1));
+        apply_mask(mcur, load_row(am, mcur, y0));
+        apply_mask(mdn, load_row(am, mdn, y0 + 1));
     }
     if constexpr (HAS2) load_own(l2, pc, y0, true);
     load_own(aprev, ac, y0, true);
-    if constexpr (DBL) load_own(am, mc, y0, true);
-    if constexpr (NXT) load_own(ap, qc, y0, true);
 
     auto compute_row = [&](int y) {
         const int64_t srow = (int64_t)y * Lx;
@@ -179,8 +190,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
         for (int k = 0; k < W; ++k) {
             const int64_t s = srow + x0 + k;
             P lam = zero_pair<double, false>();
+            [[maybe_unused]] OnSite<double> o;
+            if constexpr (HAS1 || NXT) o = ons[s];
             if constexpr (HAS1) {
-                const OnSite<double> o = ons[s];
                 const P yv = apply_uniform<double, false>(o, th, cur[k + 1], cur[k], cur[k + 2], up[k + 1], dn[k + 1]);
                 lam.e = 2.0 * yv.e;
                 lam.h = 2.0 * yv.h;
@@ -190,12 +202,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
                 lam.h -= pc[k].h;
             }
             if constexpr (DBL) {
-                lam.e += cA * mc[k].e + cR * ac[k].e + cS * ac[k].h;
-                lam.h += cA * mc[k].h + cR * ac[k].h - cS * ac[k].e;
+                const P &mk = mcur[k + 1];
+                lam.e += cA * mk.e + cR * ac[k].e + cS * ac[k].h;
+                lam.h += cA * mk.h + cR * ac[k].h - cS * ac[k].e;
             }
             if constexpr (NXT) {
-                lam.e += cP * qc[k].e - cQ * qc[k].h;
-                lam.h += cP * qc[k].h + cQ * qc[k].e;
+                const P yq = apply_uniform<double, false>(o, th, mcur[k + 1], mcur[k], mcur[k + 2], mup[k + 1], mdn[k + 1]);
+                const P q = cheb_combine<double, false>(yq, ac[k], false);
+                lam.e += cP * q.e - cQ * q.h;
+                lam.h += cP * q.h + cQ * q.e;
             }
             const bool hit = s == my_site;
             lam.e += hit ? we : 0.0;
@@ -215,28 +230,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
     // one row per trip: unrolling would duplicate the register window
 #pragma unroll 1
     for (int y = y0; y < y1 - 1; ++y) {
-        uint32_t nm = 0;
-        if constexpr (HAS1) nm = load_row(nx, y + 2);
+        uint32_t nm = 0, mm = 0;
+        if constexpr (HAS1) nm = load_row(lam1, nx, y + 2);
+        if constexpr (DBL) mm = load_row(am, mnx, y + 2);
         if constexpr (HAS2) load_own(l2, pn, y + 1, true);
         load_own(aprev, an, y + 1, true);
-        if constexpr (DBL) load_own(am, mn, y + 1, true);
-        if constexpr (NXT) load_own(ap, qn, y + 1, true);
         compute_row(y);
         if constexpr (HAS1) {
             apply_mask(nx, nm);
 #pragma unroll
             for (int k = 0; k < W + 2; ++k) { up[k] = cur[k]; cur[k] = dn[k]; dn[k] = nx[k]; }
         }
+        if constexpr (DBL) {
+            apply_mask(mnx, mm);
+#pragma unroll
+            for (int k = 0; k < W + 2; ++k) { mup[k] = mcur[k]; mcur[k] = mdn[k]; mdn[k] = mnx[k]; }
+        }
 #pragma unroll
         for (int k = 0; k < W; ++k) { pc[k] = pn[k]; ac[k] = an[k]; }
-        if constexpr (DBL) {
-#pragma unroll
-            for (int k = 0; k < W; ++k) mc[k] = mn[k];
-        }
-        if constexpr (NXT) {
-#pragma unroll
-            for (int k = 0; k < W; ++k) qc[k] = qn[k];
-        }
     }
     compute_row(y1 - 1);
 }
@@ -312,11 +323,12 @@ static int launch_adj_d(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
     return launch_adj_w<HAS1, HAS2, 1, DBL, NXT>(A, ons, st);
 }
 
+// nxt: the doubling cotangent has a_{n+1} terms (moment 2n+1 <= N-1)
 template <bool HAS1, bool HAS2>
-static int launch_adj(AdjArgs A, const OnSite<double> *ons, bool dbl, hipStream_t st)
+static int launch_adj(AdjArgs A, const OnSite<double> *ons, bool dbl, bool nxt, hipStream_t st)
 {
     if (!dbl) return launch_adj_d<HAS1, HAS2, false, false>(A, ons, st);
-    if (A.anext) return launch_adj_d<HAS1, HAS2, true, true>(A, ons, st);
+    if (nxt) return launch_adj_d<HAS1, HAS2, true, true>(A, ons, st);
     return launch_adj_d<HAS1, HAS2, true, false>(A, ons, st);
 }
 
@@ -436,6 +448,7 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
     double *d1 = gpart + (plan.Bp / kWave) * L2 * 2;
     const int k = plan.k;
     const int top = plan.top, mtop = plan.mtop;
+    const bool two = two_step_f64_real(op);
 
     for (int64_t t0 = 0; t0 < n_start; t0 += eff_tile) {
         const int Bt = (int)std::min<int64_t>(eff_tile, n_start - t0);
@@ -452,13 +465,37 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
         S.th = op->t / op->bounds.a;
         S.Lx = op->Lx; S.Ly = op->Ly; S.bcx = op->bc_x; S.bcy = op->bc_y;
         S.Bp = (int)Bp; S.Bt = Bt; S.N = N; S.sites = ts; S.mu_ee = nullptr; S.mu_he = nullptr;
+        // a_n goes to its checkpoint slot, else to one of four rotating
+        // buffers (two scratch slots and the adjoint vectors, free until the
+        // backward walk) that is neither input of its step nor the other
+        // output of a two-step pass
+        double2 *const pool[4] = {SC(0), SC(1), LA, LB};
+        auto dest_of = [&](int n, const double2 *x, const double2 *y, const double2 *z) -> double2 * {
+            if (n % k == 0) return C0(n / k);
+            if (k > 1 && n % k == 1) return C1(n / k);
+            for (double2 *q : pool)
+                if (q != x && q != y && q != z) return q;
+            return nullptr;
+        };
         const double2 *p2 = nullptr, *p1 = C0(0);
-        for (int n = 1; n <= top; ++n) {
-            double2 *dest;
-            if (n % k == 0) dest = C0(n / k);
-            else if (k > 1 && n % k == 1) dest = C1(n / k);
-            else if (p2 == SC(0) || p2 == SC(1)) dest = const_cast<double2 *>(p2);
-            else dest = (p1 == SC(0)) ? SC(1) : SC(0);
+        for (int n = 1; n <= top;) {
+            if (two && n >= 2 && n + 1 <= top) {
+                double2 *d0 = dest_of(n, p1, p2, nullptr);
+                double2 *d1 = dest_of(n + 1, p1, p2, d0);
+                S.first = 0;
+                S.n = n;
+                S.prev1 = p1;
+                S.prev2 = p2;
+                S.out = d0;
+                S.out2 = d1;
+                rc = run_step2_f64_real(op, S, st);
+                if (rc) return rc;
+                p2 = d0;
+                p1 = d1;
+                n += 2;
+                continue;
+            }
+            double2 *dest = dest_of(n, p1, nullptr, nullptr);
             S.first = n == 1;
             S.n = n;
             S.prev1 = p1;
@@ -468,6 +505,7 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
             if (rc) return rc;
             p2 = p1;
             p1 = dest;
+            ++n;
         }
 
         // backward over the segments in reverse
@@ -488,21 +526,28 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
         for (int j = plan.J - 1; j >= 0; --j) {
             const int s0 = j * k, e0 = std::min(s0 + k - 1, top);
             // forward vector m: recomputed scratch inside this segment, else a
-            // checkpoint (the adjoint of the doubling form also reads a_{e0+1}
-            // and a_{e0+2}, the next segment's pair)
+            // checkpoint (the adjoint of the doubling form also reads a_{e0+1},
+            // the first vector of the next segment's pair)
             auto vec_of = [&](int m) -> const double2 * {
                 if (m % k == 0) return C0(m / k);
                 if (k > 1 && m % k == 1) return C1(m / k);
                 return SC(m - s0 - 2);
             };
-            for (int m = s0 + 2; m <= e0; ++m) {
-                if (m % k == 0 || (k > 1 && m % k == 1)) continue;  // a checkpoint already
+            // a_{s0+2} .. a_{e0} (none a checkpoint), two at a time
+            for (int m = s0 + 2; m <= e0;) {
                 S.first = 0;
                 S.n = m;
                 S.prev1 = vec_of(m - 1);
                 S.prev2 = vec_of(m - 2);
                 S.out = SC(m - s0 - 2);
-                rc = run_step(op, CBDG_FP64, S, st);
+                if (two && m + 1 <= e0) {
+                    S.out2 = SC(m - s0 - 1);
+                    rc = run_step2_f64_real(op, S, st);
+                    m += 2;
+                } else {
+                    rc = run_step(op, CBDG_FP64, S, st);
+                    ++m;
+                }
                 if (rc) return rc;
             }
             for (int n = std::min(e0 + 1, mtop); n >= s0 + 1; --n) {
@@ -513,12 +558,12 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
                 A.out = lam(n);
                 A.aprev = vec_of(n - 1);
                 A.acur = dbl ? vec_of(n) : nullptr;
-                A.anext = (dbl && 2 * n + 1 <= N - 1) ? vec_of(n + 1) : nullptr;
                 A.cscale = (n == 1 ? 1.0 : 2.0) / op->bounds.a;
                 const OnSite<double> *ons = op->onsite64;
-                if (has1 && has2) rc = launch_adj<true, true>(A, ons, dbl, st);
-                else if (has1) rc = launch_adj<true, false>(A, ons, dbl, st);
-                else rc = launch_adj<false, false>(A, ons, dbl, st);
+                const bool nxt = dbl && 2 * n + 1 <= N - 1;
+                if (has1 && has2) rc = launch_adj<true, true>(A, ons, dbl, nxt, st);
+                else if (has1) rc = launch_adj<true, false>(A, ons, dbl, nxt, st);
+                else rc = launch_adj<false, false>(A, ons, dbl, nxt, st);
                 if (rc) return rc;
             }
         }

@@ -1216,6 +1216,21 @@ int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st)
     return op->general ? launch_step<float, false, true>(A, st) : launch_step<float, false, false>(A, st);
 }
 
+bool two_step_f64_real(const cbdg_op *op)
+{
+    return op->scalar == CBDG_REAL && !op->general && CBDG_TWO_STEP;
+}
+
+int run_step2_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st)
+{
+    if (!two_step_f64_real(op))
+        return fail(CBDG_EUNSUPPORTED, "two-step pass: needs a real operator with uniform hopping");
+    A.onsite = op->onsite64;
+    A.bonds = op->bonds64;
+    A.first = 0;
+    return launch_step2<double, false, false>(A, st);
+}
+
 int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, double *mu_ee, double *mu_he, int N,
                        hipStream_t st)
 {

@@ -186,21 +186,31 @@ __device__ __forceinline__ Pair<T, C> apply_general(const OnSite<T> &o, const Pa
     return r;
 }
 
-// Uniform real hopping t (th = t/a) and no bond pairing.
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Uniform real hopping t (th = t/a) and no bond pairing.  The fused
+// multiply-adds are written out and no other contraction is allowed, so
+// every kernel that applies Ht (one, two or three steps per launch, the
+// adjoint) rounds a site's value identically.
 template <typename T, bool C>
 __device__ __forceinline__ Pair<T, C> apply_uniform(const OnSite<T> &o, T th, const Pair<T, C> &c,
                                                     const Pair<T, C> &l, const Pair<T, C> &r,
                                                     const Pair<T, C> &d, const Pair<T, C> &u)
 {
+#pragma clang fp contract(off)
     Pair<T, C> y;
     if constexpr (C) {
-        y.er = o.de * c.er + (o.dr * c.hr - o.di * c.hi) - th * ((l.er + r.er) + (d.er + u.er));
-        y.ei = o.de * c.ei + (o.dr * c.hi + o.di * c.hr) - th * ((l.ei + r.ei) + (d.ei + u.ei));
-        y.hr = (o.dr * c.er + o.di * c.ei) + o.dh * c.hr + th * ((l.hr + r.hr) + (d.hr + u.hr));
-        y.hi = (o.dr * c.ei - o.di * c.er) + o.dh * c.hi + th * ((l.hi + r.hi) + (d.hi + u.hi));
+        const T ser = (l.er + r.er) + (d.er + u.er), sei = (l.ei + r.ei) + (d.ei + u.ei);
+        const T shr = (l.hr + r.hr) + (d.hr + u.hr), shi = (l.hi + r.hi) + (d.hi + u.hi);
+        y.er = fma_t(o.de, c.er, fma_t(o.dr, c.hr, fma_t(-o.di, c.hi, -(th * ser))));
+        y.ei = fma_t(o.de, c.ei, fma_t(o.dr, c.hi, fma_t(o.di, c.hr, -(th * sei))));
+        y.hr = fma_t(o.dh, c.hr, fma_t(o.dr, c.er, fma_t(o.di, c.ei, th * shr)));
+        y.hi = fma_t(o.dh, c.hi, fma_t(o.dr, c.ei, fma_t(-o.di, c.er, th * shi)));
     } else {
-        y.e = o.de * c.e + o.dr * c.h - th * ((l.e + r.e) + (d.e + u.e));
-        y.h = o.dr * c.e + o.dh * c.h + th * ((l.h + r.h) + (d.h + u.h));
+        const T se = (l.e + r.e) + (d.e + u.e), sh = (l.h + r.h) + (d.h + u.h);
+        y.e = fma_t(o.de, c.e, fma_t(o.dr, c.h, -(th * se)));
+        y.h = fma_t(o.dh, c.h, fma_t(o.dr, c.e, th * sh));
     }
     return y;
 }
@@ -209,6 +219,7 @@ __device__ __forceinline__ Pair<T, C> apply_uniform(const OnSite<T> &o, T th, co
 template <typename T, bool C>
 __device__ __forceinline__ Pair<T, C> cheb_combine(const Pair<T, C> &y, const Pair<T, C> &p, bool first)
 {
+#pragma clang fp contract(off)
     Pair<T, C> o;
     if constexpr (C) {
         o.er = first ? y.er : T(2) * y.er - p.er;

@@ -47,6 +47,13 @@ inline int64_t lane_stride(int64_t B) { return round_up(B, kWave) + CBDG_LANE_PA
 // mu_ee == nullptr skips the moment extraction.
 int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st);
 
+// Two recursion steps in one launch (FP64, real operator with uniform
+// hopping): a_n -> A.out and a_{n+1} -> A.out2 from a_{n-2} (A.prev2) and
+// a_{n-1} (A.prev1), n >= 2.  Neither output may alias an input or the other
+// output: a lane reads its neighbours' a_{n-1} and a_{n-2} while they write.
+bool two_step_f64_real(const cbdg_op *op);
+int run_step2_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st);
+
 // a_0 = |s_b,e> for the tile's vectors (FP64 real layout); writes mu_0 when
 // mu_ee is not null.
 int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, double *mu_ee, double *mu_he, int N,
