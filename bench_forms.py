@@ -282,17 +282,22 @@ def scf_form(args, dev):
     op = P.Operator.from_workload(w, dev)
     d0 = torch.as_tensor(w.delta, device=dev)
     method = getattr(args, "scf_method", "plain")
+    fast = P.CBDG_FP32_ACC64 if getattr(args, "scf_fp32", False) else None
     cb = lambda it, res: log("iteration %d residual %.3e" % (it, res))  # noqa: E731
+    sched = (", FP32 recursion until the residual is below 5e-7, FP64 after (only an FP64 "
+             "evaluation ends the loop)") if fast is not None else ""
     if method == "plain":
-        r = scf.plain_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60, callback=cb)
-        how = "plain mixing (alpha=1)"
+        r = scf.plain_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60, callback=cb,
+                             fast_precision=fast)
+        how = "plain mixing (alpha=1)" + sched
         passes = r.iterations
-        extra = {}
+        extra = {"fp32_passes": r.fast_passes, "fp64_passes": passes - r.fast_passes}
     elif method == "anderson":
-        r = scf.anderson_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60, callback=cb)
-        how = "Anderson mixing (depth 5, beta 1)"
+        r = scf.anderson_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60, callback=cb,
+                                fast_precision=fast)
+        how = "Anderson mixing (depth 5, beta 1)" + sched
         passes = r.iterations
-        extra = {}
+        extra = {"fp32_passes": r.fast_passes, "fp64_passes": passes - r.fast_passes}
     else:
         r = scf.newton_krylov(op, w.U, d0, w.N, w.tile, tol=1e-6, jv="fd", callback=cb)
         how = "Newton-Krylov with finite-difference Jacobian products after plain-mixing warm-up to 1e-2"

@@ -30,20 +30,56 @@ class ScfResult:
     history: List[float] = field(default_factory=list)
     seconds: float = 0.0
     moment_passes: int = 0
+    fast_passes: int = 0      # passes evaluated in the reduced recursion precision
+
+
+class _PrecisionSchedule:
+    """Recursion precision of each gap-map evaluation: `fast` (if given) until
+    the residual falls below switch_tol or stops falling (the reduced
+    precision's own error floor), `final` afterwards.  Stopping is allowed
+    only after an evaluation in `final`."""
+
+    def __init__(self, final: int, fast: Optional[int], switch_tol: Optional[float], tol: float):
+        self.final = final
+        self.fast = fast if fast is not None and fast != final else None
+        self.current = self.fast if self.fast is not None else final
+        self.switch_tol = switch_tol if switch_tol is not None else max(0.5 * tol, 1e-7)
+        self.tol = tol
+        self.fast_evaluations = 0
+        self._last = float("inf")
+
+    def workspace_bytes(self, op: Operator, tile: int) -> int:
+        precs = [self.final] + ([self.fast] if self.fast is not None else [])
+        return max(moments_workspace_bytes(op, tile, p) for p in precs)
+
+    def done(self, r: float) -> bool:
+        """Records an evaluation with residual r; True once converged."""
+        if self.current != self.final:
+            self.fast_evaluations += 1
+            if r < self.switch_tol or (r < 1e-4 and r > 0.9 * self._last):
+                self.current = self.final
+            self._last = r
+            return False
+        return r < self.tol
 
 
 def plain_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
                  precision: int = L.CBDG_FP64, alpha: float = 1.0, tol: float = 1e-6,
                  max_iter: int = 200, kernel: str = "jackson", E_c: float = 0.0,
-                 sites: Optional[torch.Tensor] = None, callback=None, T: float = 0.0) -> ScfResult:
+                 sites: Optional[torch.Tensor] = None, callback=None, T: float = 0.0,
+                 fast_precision: Optional[int] = None, switch_tol: Optional[float] = None) -> ScfResult:
     """Delta <- (1 - alpha) Delta + alpha F(Delta) until max|F(Delta) - Delta| < tol
-    (temperature T: the gap weight tanh(E/2T), coefficients computed once)."""
+    (temperature T: the gap weight tanh(E/2T), coefficients computed once).
+    fast_precision: evaluate F with that recursion precision (CBDG_FP32_ACC64)
+    until the residual falls below switch_tol (default max(tol/2, 1e-7)), then
+    with `precision`; only an evaluation in `precision` can end the loop."""
     dev = delta0.device
     if sites is None:
         sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
     w = op.weights(kernel, E_c=E_c, T=T)
     coeff = sum_coefficients(w, N, L.CBDG_QTY_GAP, dev) if T > 0 else None
-    ws = workspace(moments_workspace_bytes(op, min(tile, sites.numel()), precision), dev)
+    sched = _PrecisionSchedule(precision, fast_precision, switch_tol, tol)
+    ws = workspace(sched.workspace_bytes(op, min(tile, sites.numel())), dev)
     n = sites.numel()
     mu_ee = torch.empty((n, N), dtype=torch.float64, device=dev)
     mu_he = torch.empty((n, N), dtype=delta0.dtype, device=dev)
@@ -56,7 +92,7 @@ def plain_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int
     r = float("inf")
     it = 0
     for it in range(1, max_iter + 1):
-        chebyshev_moments(op, sites, N, tile, precision, ws=ws, out=(mu_ee, mu_he))
+        chebyshev_moments(op, sites, N, tile, sched.current, ws=ws, out=(mu_ee, mu_he))
         gap_update(mu_he, w, U, delta, alpha, delta_out=nxt, resid=resid, coeff=coeff)
         r = float(resid.item())
         hist.append(r)
@@ -66,10 +102,10 @@ def plain_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int
             callback(it, r)
         if not (r == r):
             raise L.CbdgError(L.CBDG_EBOUNDS, "scf", "non-finite residual at iteration %d" % it)
-        if r < tol:
+        if sched.done(r):
             break
     torch.cuda.synchronize()
-    return ScfResult(delta, it, r, hist, time.perf_counter() - t0, it)
+    return ScfResult(delta, it, r, hist, time.perf_counter() - t0, it, sched.fast_evaluations)
 
 
 def bond_plain_mixing(op: Operator, U: float, delta: torch.Tensor, delta_bond0: torch.Tensor, N: int,
@@ -166,7 +202,8 @@ def _gmres(matvec, rhs, tol, restart=30, maxiter=60):
 def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
                     precision: int = L.CBDG_FP64, depth: int = 5, beta: float = 1.0, tol: float = 1e-6,
                     max_iter: int = 200, kernel: str = "jackson", E_c: float = 0.0, T: float = 0.0,
-                    warmup_tol: float = 1e-2, callback=None) -> ScfResult:
+                    warmup_tol: float = 1e-2, callback=None, fast_precision: Optional[int] = None,
+                    switch_tol: Optional[float] = None) -> ScfResult:
     """The fixed point Delta = F(Delta) of the plain-mixing loop, accelerated by
     Anderson mixing: with g_k = F(Delta_k) - Delta_k and the differences of the
     last `depth` iterates (dX) and residuals (dG),
@@ -176,12 +213,15 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
     plain-mixing steps come first until max|F - Delta| < warmup_tol, as for
     Newton-Krylov; the history restarts when a step raises the residual.
     One gap-map evaluation per iteration, as plain mixing; the stopping test is
-    the same max|F(Delta) - Delta| < tol.  Real order parameters."""
+    the same max|F(Delta) - Delta| < tol.  Real order parameters.
+    fast_precision / switch_tol: as for plain_mixing; the history is kept
+    across the switch (the two evaluations of F differ by far less than tol)."""
     dev = delta0.device
     sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
     w = op.weights(kernel, E_c=E_c, T=T)
     coeff = sum_coefficients(w, N, L.CBDG_QTY_GAP, dev) if T > 0 else None
-    ws = workspace(moments_workspace_bytes(op, min(tile, op.L2), precision), dev)
+    sched = _PrecisionSchedule(precision, fast_precision, switch_tol, tol)
+    ws = workspace(sched.workspace_bytes(op, min(tile, op.L2)), dev)
     mu_ee = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
     mu_he = torch.empty((op.L2, N), dtype=delta0.dtype, device=dev)
     resid = torch.empty(1, dtype=torch.float64, device=dev)
@@ -193,7 +233,7 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
     it = 0
     for it in range(1, max_iter + 1):
         op.update_delta(x)
-        chebyshev_moments(op, sites, N, tile, precision, ws=ws, out=(mu_ee, mu_he))
+        chebyshev_moments(op, sites, N, tile, sched.current, ws=ws, out=(mu_ee, mu_he))
         fx, _ = gap_update(mu_he, w, U, x, 1.0, resid=resid, coeff=coeff)
         g = fx - x
         r = float(resid.item())
@@ -202,7 +242,7 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
             callback(it, r)
         if not (r == r):
             raise L.CbdgError(L.CBDG_EBOUNDS, "scf", "non-finite residual at iteration %d" % it)
-        if r < tol:
+        if sched.done(r):
             x = fx
             break
         if r >= max(tol, warmup_tol) or (len(hist) > 1 and r > 2.0 * hist[-2]):
@@ -222,7 +262,7 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
         gamma = torch.linalg.lstsq(dG.cpu(), g.cpu().unsqueeze(1)).solution.to(dev).squeeze(1)
         x = x + beta * g - (dX + beta * dG) @ gamma
     torch.cuda.synchronize()
-    return ScfResult(x, it, r, hist, time.perf_counter() - t0, it)
+    return ScfResult(x, it, r, hist, time.perf_counter() - t0, it, sched.fast_evaluations)
 
 
 def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,

@@ -266,3 +266,26 @@ def test_anderson_mixing_reaches_the_plain_mixing_fixed_point():
     assert aa.residual < 1e-9
     assert maxdiff(plain.delta.cpu().numpy(), aa.delta.cpu().numpy()) < 2e-8
     assert aa.iterations < plain.iterations
+
+
+@pytest.mark.parametrize("method", ["plain", "anderson"])
+def test_fp32_first_passes_reach_the_fp64_fixed_point(method):
+    """FP32 recursion for the early gap-map evaluations, FP64 for the last:
+    the loop ends on an FP64 evaluation below tol, at the FP64 fixed point."""
+    P = _P()
+    from paper_1007_1609_amd import scf
+    w = _small_cfg4(L=20, N=192)
+    d0 = torch.as_tensor(w.delta, device=DEV)
+    op = P.Operator.from_workload(w, DEV)
+    plain = scf.plain_mixing(op, w.U, d0, w.N, w.tile, tol=1e-9, max_iter=400)
+    op.close()
+    op = P.Operator.from_workload(w, DEV)
+    fn = scf.plain_mixing if method == "plain" else scf.anderson_mixing
+    kw = dict(max_iter=400) if method == "plain" else dict(max_iter=200)
+    mixed = fn(op, w.U, d0, w.N, w.tile, tol=1e-9, fast_precision=P.CBDG_FP32_ACC64, **kw)
+    op.close()
+    print("%s: %d FP32 + %d FP64 evaluations (FP64 only: %d)" % (
+        method, mixed.fast_passes, mixed.iterations - mixed.fast_passes, plain.iterations))
+    assert mixed.fast_passes > 0 and mixed.iterations > mixed.fast_passes
+    assert mixed.residual < 1e-9
+    assert maxdiff(plain.delta.cpu().numpy(), mixed.delta.cpu().numpy()) < 2e-8
