@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--scf-method", choices=["plain", "nk-fd", "anderson"], default="plain",
                     help="--form scf: plain mixing, Newton-Krylov with finite-difference products, "
                          "or Anderson mixing")
+    ap.add_argument("--no-scf", action="store_true",
+                    help="--form adjoint: time the forward and reverse passes only (no solves)")
     ap.add_argument("--scf-fp32", action="store_true",
                     help="--form scf with plain or Anderson mixing: FP32 recursion until the residual "
                          "is below half the tolerance (5e-7), then FP64")

@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import os
 import sys
+import math
 import time
 
 import numpy as np
@@ -82,6 +83,42 @@ def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step, three_step=F
         moved += 3 * _cone_sites(x, y, Lx, Ly, bc_x, bc_y, n)
         n += 1
     return launches, moved, 3 * L2 * n_steps
+
+
+def adjoint_traffic(N, L2, ckpt=0):
+    """Vector streams of the doubling-form reverse pass of one tile (real
+    operator, uniform hopping), each a whole-lattice read or write of every
+    vector, as the library issues them: the forward a_0 .. a_M keeping the
+    checkpoint pairs (M = N // 2; seed 1 write, first step 2, two-step passes
+    4, single steps 3), the recomputation of each segment's inner vectors
+    (passes 4, a last single step 3), and the adjoint steps m = M .. 1 (read
+    lam_{m+1} and lam_{m+2} where they exist, a_{m-1} and a_m; write lam_m).
+    Returns (streams, launches)."""
+    M = N // 2
+    top = M
+    k = ckpt if ckpt > 0 else int(math.ceil(math.sqrt(M + 1)))
+    J = -(-(top + 1) // k)
+    streams, launches = 1, 0
+    n = 1
+    while n <= top:
+        if n >= 2 and n + 1 <= top:
+            streams += 4; n += 2
+        else:
+            streams += 2 if n == 1 else 3; n += 1
+        launches += 1
+    for j in range(J):
+        s0, e0 = j * k, min(j * k + k - 1, top)
+        m = s0 + 2
+        while m <= e0:
+            if m + 1 <= e0:
+                streams += 4; m += 2
+            else:
+                streams += 3; m += 1
+            launches += 1
+    for m in range(M, 0, -1):
+        streams += (m + 1 <= M) + (m + 2 <= M) + 3
+        launches += 1
+    return streams, launches
 
 
 def _timed(fn):
@@ -248,8 +285,23 @@ def adjoint_form(args, dev):
     torch.cuda.synchronize()
     t_ldos = time.perf_counter() - t0
     log("adjoint: forward %.2f s, reverse %.2f s" % (t_fwd, t_bwd))
-    # self-consistency: plain mixing vs Newton-Krylov (both to 1e-6)
+    n_tiles = -(-w.L2 // tile)
+    streams, launches = adjoint_traffic(N, w.L2)
+    rev_bytes = 0.0  # a vector of a tile: L2 sites x 16 B
+    for t in range(n_tiles):
+        bt = min(tile, w.L2 - t * tile)
+        rev_bytes += streams * w.L2 * 16.0 * bt
+    reverse = {"vector_streams_per_tile": streams, "launches_per_tile": launches,
+               "algorithmic_bytes": rev_bytes, "algorithmic_GBps": rev_bytes / t_bwd / 1e9,
+               "frac": rev_bytes / t_bwd / 8e12}
     out = {}
+    if getattr(args, "no_scf", False):
+        n_moments = w.L2 * N
+        return {"metric": METRIC, "value": n_moments / t_fwd, "unit": "moments/s", "n_gpus": 1,
+                "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                "config": {"workload": "%s: 128x128, N=%d, reverse pass only" % (w.name, N)},
+                "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse}
+    # self-consistency: plain mixing vs Newton-Krylov (both to 1e-6)
     op = P.Operator.from_workload(w, dev)
     r = scf.plain_mixing(op, w.U, d0, N, tile, tol=1e-6, max_iter=300)
     out["plain_mixing"] = {"iterations": r.iterations, "gap_map_evaluations": r.iterations,
@@ -272,7 +324,7 @@ def adjoint_form(args, dev):
             "config": {"workload": "%s: 128x128 open lattice, 64 impurities V~U[0,4] (seed 4), t=1 mu=-0.5 "
                                    "U=2, N=%d, all 16384 start sites in tiles of %d, sqrt(N) checkpoints"
                                    % (w.name, N, tile)},
-            "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd,
+            "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse,
             "reverse_over_forward": t_bwd / t_fwd, "seconds_dldos0_dV_centre": t_ldos,
             "grad_norm_inf": float(g_sum.abs().max()), "scf": out}
 
