@@ -132,6 +132,9 @@ def main():
     ap.add_argument("--scf-method", choices=["plain", "nk-fd", "anderson"], default="plain",
                     help="--form scf: plain mixing, Newton-Krylov with finite-difference products, "
                          "or Anderson mixing")
+    ap.add_argument("--scf-warmup-n", type=int, default=0,
+                    help="--form scf --scf-method anderson: moments of the plain-mixing warm-up "
+                         "evaluations (0: the workload's N)")
     ap.add_argument("--no-scf", action="store_true",
                     help="--form adjoint: time the forward and reverse passes only (no solves)")
     ap.add_argument("--scf-fp32", action="store_true",

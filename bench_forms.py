@@ -345,11 +345,15 @@ def scf_form(args, dev):
         passes = r.iterations
         extra = {"fp32_passes": r.fast_passes, "fp64_passes": passes - r.fast_passes}
     elif method == "anderson":
+        wn = int(getattr(args, "scf_warmup_n", 0) or 0)
         r = scf.anderson_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60, callback=cb,
-                                fast_precision=fast)
+                                fast_precision=fast, warmup_N=wn)
         how = "Anderson mixing (depth 5, beta 1)" + sched
+        if 0 < wn < w.N:
+            how += ", plain-mixing warm-up with N=%d moments down to a residual of 1e-2" % wn
         passes = r.iterations
-        extra = {"fp32_passes": r.fast_passes, "fp64_passes": passes - r.fast_passes}
+        extra = {"fp32_passes": r.fast_passes, "fp64_passes": passes - r.fast_passes,
+                 "warmup_passes": r.warmup_passes, "warmup_N": wn}
     else:
         r = scf.newton_krylov(op, w.U, d0, w.N, w.tile, tol=1e-6, jv="fd", callback=cb)
         how = "Newton-Krylov with finite-difference Jacobian products after plain-mixing warm-up to 1e-2"
@@ -362,7 +366,8 @@ def scf_form(args, dev):
                                    "all 65536 sites, %s to max|dDelta| < 1e-6" % (w.name, how)},
             "iterations": r.iterations, "moment_passes": passes, "residual": r.residual, "history": r.history,
             "seconds_per_pass": r.seconds / passes,
-            "moments_per_s": w.L2 * w.N * passes / r.seconds}
+            "moments_per_s": w.L2 * (w.N * (passes - r.warmup_passes)
+                                     + getattr(args, "scf_warmup_n", 0) * r.warmup_passes) / r.seconds}
     line.update(extra)
     return line
 

@@ -14,9 +14,11 @@
 //     g_delta(j) += c_n/a sum_b [lam(j,e) a(j,h) + lam(j,h) a(j,e)].
 //
 // Memory: a_{n-1} is needed in reverse order.  A forward pass stores the
-// pairs (a_{jk}, a_{jk+1}) every k steps (k = ceil(sqrt(N)) by default);
-// each segment is recomputed from its pair just before the adjoint walks
-// through it.  Per tile: 2*ceil((N-1)/k) + max(k-2, 2) + 2 vectors.
+// pairs (a_{jk}, a_{jk+1}) every k steps (k = ceil(sqrt(N)) by default,
+// ceil(sqrt(M+1)) under doubling); each segment is recomputed from its pair
+// just before the adjoint walks through it.  Per tile, with V = N-1 forward
+// vectors (M+1 under doubling): ceil(V/k) checkpoints, as many again when
+// k > 1, max(k-2, 2) recomputed vectors and 2 adjoint vectors.
 //
 // With moment doubling (b = 0) the moments are functions of a_0 .. a_M only,
 // M = floor(N/2):  mu_ee[2m] = 2<a_m|a_m> - 1,
@@ -338,6 +340,7 @@ struct Plan {
     int mtop;        // first adjoint index: N-1 (direct), M (doubling)
     int k;           // checkpoint stride
     int J;           // segments
+    int J1;          // second checkpoint of each pair: J slots, none when k = 1
     int nscratch;    // segment / scratch vectors
     int64_t Bp;      // lane stride for the widest tile
 };
@@ -354,6 +357,7 @@ static Plan make_plan(int N, int tile, int ckpt_stride, bool dbl)
     const int kdef = (int)std::ceil(std::sqrt((double)(dbl ? nvec : N)));
     p.k = ckpt_stride > 0 ? ckpt_stride : std::max(1, kdef);
     p.J = (int)ceil_div(nvec, p.k);
+    p.J1 = p.k > 1 ? p.J : 0;
     p.nscratch = std::max(p.k - 2, 2);
     p.Bp = lane_stride(tile);
     return p;
@@ -364,7 +368,7 @@ static size_t plan_bytes(const Plan &p, int64_t L2)
     const size_t vec = (size_t)L2 * (size_t)p.Bp * sizeof(double2);
     const size_t gpart = (size_t)(p.Bp / kWave) * (size_t)L2 * 2 * sizeof(double);
     const size_t d1 = p.dbl ? (size_t)p.Bp * 2 * sizeof(double) : 0;
-    return (size_t)(2 * p.J + p.nscratch + 2) * vec + gpart + d1;
+    return (size_t)(p.J + p.J1 + p.nscratch + 2) * vec + gpart + d1;
 }
 
 }  // namespace cbdg
@@ -441,8 +445,8 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
     double2 *base = reinterpret_cast<double2 *>(workspace);
     auto C0 = [&](int j) { return base + (int64_t)j * vec; };
     auto C1 = [&](int j) { return base + (int64_t)(plan.J + j) * vec; };
-    auto SC = [&](int i) { return base + (int64_t)(2 * plan.J + i) * vec; };
-    double2 *LA = base + (int64_t)(2 * plan.J + plan.nscratch) * vec;
+    auto SC = [&](int i) { return base + (int64_t)(plan.J + plan.J1 + i) * vec; };
+    double2 *LA = base + (int64_t)(plan.J + plan.J1 + plan.nscratch) * vec;
     double2 *LB = LA + vec;
     double *gpart = reinterpret_cast<double *>(LB + vec);
     double *d1 = gpart + (plan.Bp / kWave) * L2 * 2;

@@ -31,6 +31,7 @@ class ScfResult:
     seconds: float = 0.0
     moment_passes: int = 0
     fast_passes: int = 0      # passes evaluated in the reduced recursion precision
+    warmup_passes: int = 0    # passes with the reduced warm-up moment count
 
 
 class _PrecisionSchedule:
@@ -203,7 +204,7 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
                     precision: int = L.CBDG_FP64, depth: int = 5, beta: float = 1.0, tol: float = 1e-6,
                     max_iter: int = 200, kernel: str = "jackson", E_c: float = 0.0, T: float = 0.0,
                     warmup_tol: float = 1e-2, callback=None, fast_precision: Optional[int] = None,
-                    switch_tol: Optional[float] = None) -> ScfResult:
+                    switch_tol: Optional[float] = None, warmup_N: int = 0) -> ScfResult:
     """The fixed point Delta = F(Delta) of the plain-mixing loop, accelerated by
     Anderson mixing: with g_k = F(Delta_k) - Delta_k and the differences of the
     last `depth` iterates (dX) and residuals (dG),
@@ -215,15 +216,23 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
     One gap-map evaluation per iteration, as plain mixing; the stopping test is
     the same max|F(Delta) - Delta| < tol.  Real order parameters.
     fast_precision / switch_tol: as for plain_mixing; the history is kept
-    across the switch (the two evaluations of F differ by far less than tol)."""
+    across the switch (the two evaluations of F differ by far less than tol).
+    warmup_N (0 < warmup_N < N): the plain-mixing warm-up steps evaluate the
+    gap map with warmup_N moments; the first evaluation below warmup_tol
+    switches to N for good (and, as any residual jump, restarts the history)."""
     dev = delta0.device
     sites = torch.arange(op.L2, dtype=torch.int32, device=dev)
     w = op.weights(kernel, E_c=E_c, T=T)
-    coeff = sum_coefficients(w, N, L.CBDG_QTY_GAP, dev) if T > 0 else None
     sched = _PrecisionSchedule(precision, fast_precision, switch_tol, tol)
     ws = workspace(sched.workspace_bytes(op, min(tile, op.L2)), dev)
-    mu_ee = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
-    mu_he = torch.empty((op.L2, N), dtype=delta0.dtype, device=dev)
+    Nw = warmup_N if 0 < warmup_N < N else N
+    bufs = {}
+    for n_mom in {N, Nw}:
+        bufs[n_mom] = (torch.empty((op.L2, n_mom), dtype=torch.float64, device=dev),
+                       torch.empty((op.L2, n_mom), dtype=delta0.dtype, device=dev),
+                       sum_coefficients(w, n_mom, L.CBDG_QTY_GAP, dev) if T > 0 else None)
+    n_cur = Nw
+    warm = 0
     resid = torch.empty(1, dtype=torch.float64, device=dev)
     hist: List[float] = []
     t0 = time.perf_counter()
@@ -233,7 +242,8 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
     it = 0
     for it in range(1, max_iter + 1):
         op.update_delta(x)
-        chebyshev_moments(op, sites, N, tile, sched.current, ws=ws, out=(mu_ee, mu_he))
+        mu_ee, mu_he, coeff = bufs[n_cur]
+        chebyshev_moments(op, sites, n_cur, tile, sched.current, ws=ws, out=(mu_ee, mu_he))
         fx, _ = gap_update(mu_he, w, U, x, 1.0, resid=resid, coeff=coeff)
         g = fx - x
         r = float(resid.item())
@@ -242,6 +252,14 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
             callback(it, r)
         if not (r == r):
             raise L.CbdgError(L.CBDG_EBOUNDS, "scf", "non-finite residual at iteration %d" % it)
+        if n_cur != N:
+            # reduced-N warm-up: plain steps only, never the end of the loop
+            warm += 1
+            sched.fast_evaluations += sched.current != sched.final
+            x = fx
+            if r < warmup_tol:
+                n_cur = N
+            continue
         if sched.done(r):
             x = fx
             break
@@ -262,7 +280,7 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
         gamma = torch.linalg.lstsq(dG.cpu(), g.cpu().unsqueeze(1)).solution.to(dev).squeeze(1)
         x = x + beta * g - (dX + beta * dG) @ gamma
     torch.cuda.synchronize()
-    return ScfResult(x, it, r, hist, time.perf_counter() - t0, it, sched.fast_evaluations)
+    return ScfResult(x, it, r, hist, time.perf_counter() - t0, it, sched.fast_evaluations, warm)
 
 
 def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,

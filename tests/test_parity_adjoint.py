@@ -289,3 +289,23 @@ def test_fp32_first_passes_reach_the_fp64_fixed_point(method):
     assert mixed.fast_passes > 0 and mixed.iterations > mixed.fast_passes
     assert mixed.residual < 1e-9
     assert maxdiff(plain.delta.cpu().numpy(), mixed.delta.cpu().numpy()) < 2e-8
+
+
+def test_reduced_moment_warm_up_reaches_the_same_fixed_point():
+    """Anderson mixing whose plain warm-up steps use N/4 moments: the later
+    evaluations use N, so the loop ends at the N-moment fixed point."""
+    P = _P()
+    from paper_1007_1609_amd import scf
+    w = _small_cfg4(L=20, N=192)
+    d0 = torch.as_tensor(w.delta, device=DEV)
+    op = P.Operator.from_workload(w, DEV)
+    plain = scf.plain_mixing(op, w.U, d0, w.N, w.tile, tol=1e-9, max_iter=400)
+    op.close()
+    op = P.Operator.from_workload(w, DEV)
+    aa = scf.anderson_mixing(op, w.U, d0, w.N, w.tile, tol=1e-9, max_iter=200, warmup_N=w.N // 4,
+                             fast_precision=P.CBDG_FP32_ACC64)
+    op.close()
+    print("Anderson: %d evaluations, %d with N/4, %d FP32" % (aa.iterations, aa.warmup_passes, aa.fast_passes))
+    assert aa.warmup_passes > 0 and aa.iterations > aa.warmup_passes
+    assert aa.residual < 1e-9
+    assert maxdiff(plain.delta.cpu().numpy(), aa.delta.cpu().numpy()) < 2e-8
