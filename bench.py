@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--scf-warmup-n", type=int, default=0,
                     help="--form scf --scf-method anderson: moments of the plain-mixing warm-up "
                          "evaluations (0: the workload's N)")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="default form: skip the self-consistent solve reported after the timed steps")
     ap.add_argument("--no-scf", action="store_true",
                     help="--form adjoint: time the forward and reverse passes only (no solves)")
     ap.add_argument("--scf-fp32", action="store_true",
@@ -248,11 +250,11 @@ def main():
         kern_ms += e0.elapsed_time(e1)
         bp = (bt + 63) // 64 * 64
         lo = (k % n_tiles) * tile
-        nl, moved, full = recursion_traffic(sites_np[lo:lo + bt], w.Lx, w.Ly, w.bc_x, w.bc_y, steps_per_tile,
-                                            two_step, three_step=args.precision == "fp32")
+        nl, moved, streamed = recursion_traffic(sites_np[lo:lo + bt], w.Lx, w.Ly, w.bc_x, w.bc_y,
+                                                steps_per_tile, two_step, three_step=args.precision == "fp32")
         launches += nl
         alg_bytes += moved * 2 * bp * s_bytes
-        full_bytes += full * 2 * bp * s_bytes
+        full_bytes += streamed * 2 * bp * s_bytes
     avg_launch_ms = kern_ms / launches
     bytes_per_launch = alg_bytes / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
@@ -309,6 +311,10 @@ def main():
     else:
         line["cpu_baseline"] = None
     op.close()
+    if args.precision == "fp64" and n_sites == w.L2 and not args.no_solve:
+        import bench_forms
+        line["scf_solve"] = bench_forms.scf_solve_summary(w, dev)
+        log("self-consistent solve: %.1f s" % line["scf_solve"]["seconds"])
     print(json.dumps(line), flush=True)
 
 
