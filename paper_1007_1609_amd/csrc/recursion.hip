@@ -51,6 +51,15 @@ namespace cbdg {
 #ifndef CBDG_A2_FIRST
 #define CBDG_A2_FIRST 1
 #endif
+// Three-step passes: a_{n-2} loaded one row ahead, so each trip computes from
+// registers while the next rows of a_{n-1} and a_{n-2} arrive.  FP32, one
+// 1024-vector tile at 256x256: 90.9 -> 85.0 us per moment index (spread
+// start sites), 80.8 -> 75.6 (a block of rows).  The same prefetch in the
+// FP64 two-step pass was slower (W = 8: 192.8 -> 197.3 us, one wave per SIMD
+// with the buffer in AGPRs; W = 4: 226.9 us at two waves per SIMD).
+#ifndef CBDG_PF3
+#define CBDG_PF3 1
+#endif
 
 #ifndef CBDG_LANE_PAD
 #define CBDG_LANE_PAD 0
@@ -669,18 +678,33 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step3(StepArgs A, const typenam
 #pragma unroll
     for (int k = 0; k < X2; ++k) { q1[k] = zero_pair<T, false>(); q0[k] = zero_pair<T, false>(); }
 
+    auto load_p2 = [&](P *pr, int r) {
+        uint32_t ok;
+        const int64_t rb = row_of(r, ok);
+#pragma unroll
+        for (int k = 0; k < X1; ++k) pr[k] = CBDG_NT_A2 ? ld_nt<T, false>(a2 + (rb + cx[k + 1]) * Bp + b)
+                                                       : ld<T, false>(a2 + (rb + cx[k + 1]) * Bp + b);
+    };
+    [[maybe_unused]] P pn[CBDG_PF3 ? X1 : 1];
+    if constexpr (CBDG_PF3) load_p2(p2, y0 - 2);
+
 #pragma unroll 1
     for (int r = y0 - 2; r <= y1 + 1; ++r) {
         uint32_t nm = 0;
-        if constexpr (!CBDG_A2_FIRST) { if (r + 2 <= y1 + 2) nm = load_row1(nx, r + 2); }
         uint32_t rok;
         const int64_t rb = row_of(r, rok);
-#pragma unroll
-        for (int k = 0; k < X1; ++k) p2[k] = CBDG_NT_A2 ? ld_nt<T, false>(a2 + (rb + cx[k + 1]) * Bp + b)
-                                                       : ld<T, false>(a2 + (rb + cx[k + 1]) * Bp + b);
-        if constexpr (CBDG_A2_FIRST) {
-            __builtin_amdgcn_sched_barrier(0);
+        if constexpr (CBDG_PF3) {
+            // a_{n-2} one row ahead: this trip computes with the row loaded on
+            // the previous one (rows past the segment clamped, unused)
             nm = load_row1(nx, min(r + 2, y1 + 2));
+            load_p2(pn, min(r + 1, y1 + 1));
+        } else {
+            if constexpr (!CBDG_A2_FIRST) { if (r + 2 <= y1 + 2) nm = load_row1(nx, r + 2); }
+            load_p2(p2, r);
+            if constexpr (CBDG_A2_FIRST) {
+                __builtin_amdgcn_sched_barrier(0);
+                nm = load_row1(nx, min(r + 2, y1 + 2));
+            }
         }
 #pragma unroll
         for (int k = 0; k < X1; ++k) { m2[k] = m1[k]; m1[k] = m0[k]; }
@@ -745,9 +769,13 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step3(StepArgs A, const typenam
                 if constexpr (DOT) dots(d + 6, v, q1[k + 1]);
             }
         }
-        if (CBDG_A2_FIRST || r + 2 <= y1 + 2) mask_row1(nx, nm);
+        if (CBDG_PF3 || CBDG_A2_FIRST || r + 2 <= y1 + 2) mask_row1(nx, nm);
 #pragma unroll
         for (int k = 0; k < Y; ++k) { w0[k] = w1[k]; w1[k] = w2[k]; w2[k] = nx[k]; }
+        if constexpr (CBDG_PF3) {
+#pragma unroll
+            for (int k = 0; k < X1; ++k) p2[k] = pn[k];
+        }
     }
 
     if constexpr (DOT) {
