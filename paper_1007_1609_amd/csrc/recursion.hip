@@ -986,6 +986,10 @@ static int launch_step(StepArgs A, hipStream_t st)
 //   W = 8, 1024 workgroups: 196.6 / 103.1; 512 workgroups: 193.1 / 102.2
 //   W = 16 (FP32): 133.8; a_{n-2} prefetched a row ahead: no gain.
 // At W = 8 the FP64 kernel holds 256 VGPRs plus AGPRs, one wave per SIMD.
+// With the a_{n-2} loads ahead of the prefetch (FP64, spread / rows):
+// segments of 64 rows, 512 workgroups 192.7 / 149.7; 32 rows 195.9 / 153.5;
+// 1024 workgroups 195.9 / 153.4; 128 rows, 256 workgroups 191.2 / 147.8
+// (one workgroup per CU at 256x256: fewer widened halo rows).
 #ifndef CBDG_TWO_STEP
 #define CBDG_TWO_STEP 1
 #endif
@@ -996,10 +1000,10 @@ static int launch_step(StepArgs A, hipStream_t st)
 #define CBDG_W2_F32 8
 #endif
 #ifndef CBDG_YS2
-#define CBDG_YS2 64
+#define CBDG_YS2 128
 #endif
 #ifndef CBDG_TGT2
-#define CBDG_TGT2 512
+#define CBDG_TGT2 256
 #endif
 // Two-step passes for complex operators and per-bond coefficients are
 // available but off: on one 1024-vector tile of the 512x512 Peierls/d-wave
