@@ -23,3 +23,64 @@ def test_gmres_zero_rhs():
     from paper_1007_1609_amd.scf import _gmres
     x, used = _gmres(lambda v: v, np.zeros(5), 1e-8)
     assert used == 0 and np.all(x == 0)
+
+
+def _schedule(fast=1, switch_tol=None, tol=1e-6):
+    from paper_1007_1609_amd.scf import _PrecisionSchedule
+    return _PrecisionSchedule(0, fast, switch_tol, tol)
+
+
+def test_precision_schedule_without_a_fast_precision_is_the_plain_test():
+    s = _schedule(fast=None)
+    assert s.current == 0
+    assert not s.done(2e-6) and s.done(5e-7)
+    assert s.fast_evaluations == 0
+    # the same precision given twice is no schedule either
+    assert _schedule(fast=0).current == 0
+
+
+def test_precision_schedule_switches_below_half_the_tolerance():
+    s = _schedule()
+    assert s.switch_tol == 5e-7
+    assert s.current == 1
+    # a reduced-precision residual below tol does not end the loop
+    for r in (1e-1, 1e-3, 8e-7):
+        assert not s.done(r) and s.current == 1
+    assert not s.done(4e-7)          # below switch_tol: next evaluation in FP64
+    assert s.current == 0 and s.fast_evaluations == 4
+    assert not s.done(3e-6)          # FP64 above tol: keep going in FP64
+    assert s.done(9e-7) and s.current == 0
+
+
+def test_precision_schedule_switches_when_the_residual_stalls():
+    s = _schedule(switch_tol=1e-12, tol=1e-9)
+    for r in (1e-2, 1e-3, 5e-5, 3e-6):
+        assert not s.done(r) and s.current == 1
+    assert not s.done(2.9e-6)        # below 1e-4 and not falling: the FP32 floor
+    assert s.current == 0
+    # above 1e-4 a slow phase is not taken for the floor
+    s = _schedule(switch_tol=1e-12, tol=1e-9)
+    assert not s.done(1e-2) and not s.done(0.95e-2) and s.current == 1
+
+
+def test_precision_schedule_default_switch_is_floored():
+    assert _schedule(tol=1e-9).switch_tol == 1e-7
+    assert _schedule(tol=1e-4).switch_tol == 5e-5
+
+
+def test_reverse_pass_accounting_matches_the_library_plan():
+    """Launch and vector-stream counts of the doubling-form reverse pass for
+    the 128x128, N = 512 workload: checkpoint stride 17, 16 segments; the
+    forward is 1 + 127 two-step passes + 1 step, each of the 15 inner
+    segments is recomputed by 7 two-step passes + 1 step, and 256 adjoint
+    steps follow (the kernel trace of that workload counts the same calls)."""
+    import bench_forms
+    streams, launches = bench_forms.adjoint_traffic(512, 128 * 128)
+    assert launches == (1 + 127 + 1) + 15 * (7 + 1) + 256
+    fwd = 1 + 2 + 127 * 4 + 3
+    rec = 15 * (7 * 4 + 3)
+    adj = 254 * 5 + 4 + 3
+    assert streams == fwd + rec + adj
+    # stride 1 stores every vector: no recomputation
+    s1, l1 = bench_forms.adjoint_traffic(512, 128 * 128, ckpt=1)
+    assert l1 == 129 + 256 and s1 == fwd + adj
