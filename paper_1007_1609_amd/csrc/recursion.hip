@@ -54,11 +54,15 @@ namespace cbdg {
 // Three-step passes: a_{n-2} loaded one row ahead, so each trip computes from
 // registers while the next rows of a_{n-1} and a_{n-2} arrive.  FP32, one
 // 1024-vector tile at 256x256: 90.9 -> 85.0 us per moment index (spread
-// start sites), 80.8 -> 75.6 (a block of rows).  The same prefetch in the
-// FP64 two-step pass was slower (W = 8: 192.8 -> 197.3 us, one wave per SIMD
-// with the buffer in AGPRs; W = 4: 226.9 us at two waves per SIMD).
-#ifndef CBDG_PF3
-#define CBDG_PF3 1
+// start sites), 80.8 -> 75.6 (a block of rows).  FP64 three-step (one wave
+// per SIMD, windows partly in AGPRs) is faster without it: 186.9 / 142.2 us
+// against 188.1 / 143.6.  The same prefetch in the FP64 two-step pass was
+// slower too (W = 8: 192.8 -> 197.3 us; W = 4: 226.9 us).
+#ifndef CBDG_PF3_F32
+#define CBDG_PF3_F32 1
+#endif
+#ifndef CBDG_PF3_F64
+#define CBDG_PF3_F64 0
 #endif
 
 #ifndef CBDG_LANE_PAD
@@ -685,15 +689,16 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step3(StepArgs A, const typenam
         for (int k = 0; k < X1; ++k) pr[k] = CBDG_NT_A2 ? ld_nt<T, false>(a2 + (rb + cx[k + 1]) * Bp + b)
                                                        : ld<T, false>(a2 + (rb + cx[k + 1]) * Bp + b);
     };
-    [[maybe_unused]] P pn[CBDG_PF3 ? X1 : 1];
-    if constexpr (CBDG_PF3) load_p2(p2, y0 - 2);
+    constexpr bool PF3 = std::is_same<T, float>::value ? CBDG_PF3_F32 : CBDG_PF3_F64;
+    [[maybe_unused]] P pn[PF3 ? X1 : 1];
+    if constexpr (PF3) load_p2(p2, y0 - 2);
 
 #pragma unroll 1
     for (int r = y0 - 2; r <= y1 + 1; ++r) {
         uint32_t nm = 0;
         uint32_t rok;
         const int64_t rb = row_of(r, rok);
-        if constexpr (CBDG_PF3) {
+        if constexpr (PF3) {
             // a_{n-2} one row ahead: this trip computes with the row loaded on
             // the previous one (rows past the segment clamped, unused)
             nm = load_row1(nx, min(r + 2, y1 + 2));
@@ -769,10 +774,10 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step3(StepArgs A, const typenam
                 if constexpr (DOT) dots(d + 6, v, q1[k + 1]);
             }
         }
-        if (CBDG_PF3 || CBDG_A2_FIRST || r + 2 <= y1 + 2) mask_row1(nx, nm);
+        if (PF3 || CBDG_A2_FIRST || r + 2 <= y1 + 2) mask_row1(nx, nm);
 #pragma unroll
         for (int k = 0; k < Y; ++k) { w0[k] = w1[k]; w1[k] = w2[k]; w2[k] = nx[k]; }
-        if constexpr (CBDG_PF3) {
+        if constexpr (PF3) {
 #pragma unroll
             for (int k = 0; k < X1; ++k) p2[k] = pn[k];
         }
@@ -1087,14 +1092,16 @@ static bool uses_two_step(const cbdg_op *op)
     return CBDG_TWO_STEP && CBDG_TWO_STEP_GEN;
 }
 
-// Three-step passes (k_cheb_step3), used for FP32 only.  One 1024-vector tile
-// of the 256x256 workload, N = 514 by doubling, microseconds per moment index
-// (two-step W = 8: FP64 192.7, FP32 101.7):
+// Three-step passes (k_cheb_step3) for real operators with uniform hopping.
+// One 1024-vector tile of the 256x256 workload, N = 514 by doubling,
+// microseconds per moment index (two-step W = 8: FP64 192.7, FP32 101.7):
 //   FP32: W = 4 94.3 (222 VGPRs, two waves per SIMD), W = 8 111.2, W = 2 135.5
 //   FP64: W = 4 199.1, W = 2 263.0, W = 1 329.6 (the widened register windows
-//         spill into AGPRs: no gain over two steps)
+//         spill into AGPRs)
+// After the load-order change and 128-row segments (spread / rows): FP64
+// two-step 191.4 / 148.0, three-step W = 4 186.9 / 142.2, W = 2 212.6 / 163.5.
 #ifndef CBDG_THREE_STEP_F64
-#define CBDG_THREE_STEP_F64 0
+#define CBDG_THREE_STEP_F64 1
 #endif
 #ifndef CBDG_THREE_STEP_F32
 #define CBDG_THREE_STEP_F32 1
@@ -1157,8 +1164,10 @@ static int launch_step3(StepArgs A, hipStream_t st)
     A.n_strips = sh.n_strips;
     A.ys = sh.ys;
     A.n_segs = sh.n_segs;
-    if (sh.W == 8) return launch_step3_w<T, 8>(A, st);
-    if (sh.W == 4) return launch_step3_w<T, 4>(A, st);
+    // only the table width and the narrower fallbacks are instantiated
+    constexpr int WB = Step3Shape<T>::W;
+    if constexpr (WB >= 8) { if (sh.W == 8) return launch_step3_w<T, 8>(A, st); }
+    if constexpr (WB >= 4) { if (sh.W == 4) return launch_step3_w<T, 4>(A, st); }
     if (sh.W == 2) return launch_step3_w<T, 2>(A, st);
     return launch_step3_w<T, 1>(A, st);
 }
