@@ -1112,9 +1112,30 @@ static bool uses_two_step(const cbdg_op *op)
 #ifndef CBDG_W3_F32
 #define CBDG_W3_F32 4
 #endif
+// Longest row segment and workgroup target of the three-step passes, per
+// type (FP64, spread / rows, us per moment index): 256 rows 163.2 / 126.6,
+// 128 rows 186.6 / 141.9, 64 rows with 512 or 1024 workgroups 191.9 / 147.1 --
+// at 256x256 the 256 workgroups of 256-row segments put exactly one wave on
+// every SIMD for the whole launch.  FP32 (two waves per SIMD): 128 rows
+// 83.1 / 73.6, 256 rows 121.2 / 107.2, 64 rows 84.9 / 75.6.
+#ifndef CBDG_YS3_F64
+#define CBDG_YS3_F64 256
+#endif
+#ifndef CBDG_YS3_F32
+#define CBDG_YS3_F32 128
+#endif
+#ifndef CBDG_TGT3
+#define CBDG_TGT3 256
+#endif
 template <typename T> struct Step3Shape;
-template <> struct Step3Shape<double> { static constexpr int W = CBDG_W3_F64; static constexpr bool ON = CBDG_THREE_STEP_F64; };
-template <> struct Step3Shape<float> { static constexpr int W = CBDG_W3_F32; static constexpr bool ON = CBDG_THREE_STEP_F32; };
+template <> struct Step3Shape<double> {
+    static constexpr int W = CBDG_W3_F64, YS = CBDG_YS3_F64;
+    static constexpr bool ON = CBDG_THREE_STEP_F64;
+};
+template <> struct Step3Shape<float> {
+    static constexpr int W = CBDG_W3_F32, YS = CBDG_YS3_F32;
+    static constexpr bool ON = CBDG_THREE_STEP_F32;
+};
 
 template <typename T>
 static Shape choose_shape3(int Lx, int Ly, int64_t n_chunks)
@@ -1124,8 +1145,8 @@ static Shape choose_shape3(int Lx, int Ly, int64_t n_chunks)
     sh.W = (Lx % WB == 0) ? WB : (Lx % 4 == 0 ? 4 : (Lx % 2 == 0 ? 2 : 1));
     sh.PF = false;
     sh.n_strips = Lx / sh.W;
-    int ys = CBDG_YS2;
-    while (ys > 8 && (int64_t)sh.n_strips * n_chunks * ceil_div(Ly, ys) < CBDG_TGT2) ys /= 2;
+    int ys = Step3Shape<T>::YS;
+    while (ys > 8 && (int64_t)sh.n_strips * n_chunks * ceil_div(Ly, ys) < CBDG_TGT3) ys /= 2;
     sh.ys = ys;
     sh.n_segs = (int)ceil_div(Ly, sh.ys);
     return sh;
