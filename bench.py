@@ -255,7 +255,7 @@ def main():
         bp = (bt + 63) // 64 * 64
         lo = (k % n_tiles) * tile
         nl, moved, streamed = recursion_traffic(sites_np[lo:lo + bt], w.Lx, w.Ly, w.bc_x, w.bc_y,
-                                                steps_per_tile, two_step, three_step=True)
+                                                steps_per_tile, two_step, three_step=bt >= 129)
         launches += nl
         alg_bytes += moved * 2 * bp * s_bytes
         full_bytes += streamed * 2 * bp * s_bytes

@@ -55,9 +55,9 @@ def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step, three_step=F
       two-step     read a_{n-2}, a_{n-1}, write a_n, a_{n+1} inside the light
                    cone of step n+1: 4 x cone(n+1)
       single step  read a_{n-2}, a_{n-1}, write a_n inside cone(n): 3 x cone(n)
-    On real operators with uniform hopping steps 2.. go in threes (FP32) or
-    pairs, the remainder in a pair and/or a single step, as the library
-    issues them.  Returns (launches, pair-elements moved, pair-elements of the
+    On real operators with uniform hopping steps 2.. go in threes (tiles of
+    more than 128 vectors) or pairs, the remainder in a pair and/or a single
+    step, as the library issues them.  Returns (launches, pair-elements moved, pair-elements of the
     plain one-step streaming recursion over the whole lattice, 3 x L2 per
     step)."""
     sites = np.asarray(sites)

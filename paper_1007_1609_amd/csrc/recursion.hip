@@ -1121,6 +1121,12 @@ static bool uses_two_step(const cbdg_op *op)
 #ifndef CBDG_YS3_F64
 #define CBDG_YS3_F64 256
 #endif
+// Tiles of fewer vectors take two-step passes: with one or two waves per row
+// segment the longer serial chain of a three-step trip is not hidden.  256x256,
+// 1024 start sites, time per tile set (two-step / three-step, ms): FP64 64
+// vectors 182.5 / 190.5, 128: 100.9 / 101.0, 256: 71.3 / 60.3, 1024: 62.4 /
+// 53.6; FP32 64: 350 / 386, 128: 184 / 202, 256: 118 / 107, 1024: 104 / 70.
+constexpr int kThreeStepMinVectors = 129;
 #ifndef CBDG_YS3_F32
 #define CBDG_YS3_F32 128
 #endif
@@ -1451,7 +1457,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         A.first = 0;
         A.mu_ee = doubling ? nullptr : mee;
         if constexpr (!C) {
-            while (three && n + 2 <= n_steps) {
+            while (three && Bt >= kThreeStepMinVectors && n + 2 <= n_steps) {
                 A.n = n;
                 A.prev2 = P2;
                 A.prev1 = P1;

@@ -82,22 +82,30 @@ def test_complex_bond_operator_corner(alg):
     _check(w, _block(36, 30, 36, 40, 44), 32, alg)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("alg", ALGS)
 @pytest.mark.parametrize("Lx,Ly,bc,block,tile,N", [
+    # tiles of 128 vectors or fewer: two steps per launch
     (48, 80, {}, (0, 5, 0, 3), 64, 97),                          # corner tile, light cone
     (36, 40, dict(bc_x=W.PERIODIC, bc_y=W.PERIODIC), (0, 4, 0, 4), 16, 64),
-    (64, 24, {}, (0, 3, 0, 24), 128, 66),                        # narrow column, three steps plus a pair
-    (13, 37, {}, (0, 13, 0, 37), 100, 65),                       # ragged strips, odd width
+    (64, 24, {}, (0, 3, 0, 24), 128, 66),                        # narrow column
+    # larger tiles: three steps per launch, then a pair and/or a single step
+    (48, 80, {}, (0, 16, 0, 10), 160, 97),                       # corner block, light cone
+    (36, 40, dict(bc_x=W.PERIODIC, bc_y=W.PERIODIC), (0, 12, 0, 12), 144, 64),
+    (64, 24, {}, (0, 8, 0, 24), 192, 66),                        # full height, narrow in x
+    (13, 37, {}, (0, 13, 0, 37), 200, 65),                       # ragged: tiles 200, 200, 81
 ])
-def test_fp32_multi_step_passes(alg, Lx, Ly, bc, block, tile, N):
-    """FP32 real operators take three steps per launch (plus a pair and a
-    single step for the remainder): moments within 2e-5 of the FP64 oracle."""
+def test_multi_step_passes(prec, alg, Lx, Ly, bc, block, tile, N):
+    """Real operators with uniform hopping take several recursion steps per
+    launch (three for tiles of more than 128 vectors, else two, and a pair
+    and/or a single step for the remainder): moments within 1e-10 (FP64) or
+    2e-5 (FP32 recursion) of the FP64 oracle."""
     w = W.small_random(Lx, Ly, N=N, seed=Lx + Ly + N, **bc)
     sites = _block(Lx, *block)
-    op, g_ee, g_he = gpu_moments(w, sites=sites, tile=tile, precision=1, algorithm=alg)
+    op, g_ee, g_he = gpu_moments(w, sites=sites, tile=tile, precision=prec, algorithm=alg)
     a, b = op.bounds.a, op.bounds.b
     op.close()
     o_ee, o_he = oracle.workload_moments(w, a, b, sites=sites)
     e = max(maxdiff(g_ee, o_ee), maxdiff(g_he, o_he))
-    print("fp32 %dx%d N=%d alg=%d: max error %.2e" % (Lx, Ly, N, alg, e))
-    assert e < 2e-5
+    print("prec %d %dx%d N=%d alg=%d tile=%d: max error %.2e" % (prec, Lx, Ly, N, alg, tile, e))
+    assert e < (TOL_MOMENT if prec == 0 else 2e-5)
