@@ -290,7 +290,13 @@ __global__ void k_grad_reduce(const double *gpart, int nchunk, int64_t L2, doubl
     }
 }
 
-constexpr int kAdjW = 4, kAdjYS = 64;
+#ifndef CBDG_ADJ_YS
+#define CBDG_ADJ_YS 64
+#endif
+#ifndef CBDG_ADJ_TGT
+#define CBDG_ADJ_TGT 2048
+#endif
+constexpr int kAdjW = 4, kAdjYS = CBDG_ADJ_YS;
 
 template <bool HAS1, bool HAS2, int W, bool DBL, bool NXT>
 static int launch_adj_w(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
@@ -298,7 +304,7 @@ static int launch_adj_w(AdjArgs A, const OnSite<double> *ons, hipStream_t st)
     A.n_strips = A.Lx / W;
     const int n_chunks = (int)ceil_div(A.Bt, kBlock);
     A.ys = kAdjYS;
-    while (A.ys > 8 && (int64_t)A.n_strips * n_chunks * ceil_div(A.Ly, A.ys) < 2048) A.ys /= 2;
+    while (A.ys > 8 && (int64_t)A.n_strips * n_chunks * ceil_div(A.Ly, A.ys) < CBDG_ADJ_TGT) A.ys /= 2;
     A.n_segs = (int)ceil_div(A.Ly, A.ys);
     const int64_t nb = (int64_t)A.n_strips * A.n_segs * n_chunks;
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments_backward: launch grid too large");

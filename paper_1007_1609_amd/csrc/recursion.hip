@@ -877,31 +877,45 @@ __global__ __launch_bounds__(kBlock) void k_tile_cone(const int32_t *sites, int 
 // W8+PF 508 us, W8 541, W4+PF 565, W4 556; at 128x128: W4 126, W8+PF 141.
 // complex128 at 512x512: W2+PF 5.27 ms, W4 5.33, W1+PF 5.80; complex64:
 // W8 2.20 ms, W4+PF 2.32.
+// Complex operators (one step per launch): 32-row segments, 2048 workgroups.
+// On one tile of spread start sites (512x512, N = 258) longer segments were
+// faster (512 rows, 1024 workgroups: complex128 982.4 vs 1019.0 us per
+// step), but on the Peierls/d-wave workload (stride-8 grid of start sites,
+// N = 2048) 4840 vs 4770 us per launch: while the light cone is small a
+// strip's active rows are shared by fewer, longer segments.
+#ifndef CBDG_YS_C128
+#define CBDG_YS_C128 32
+#endif
+#ifndef CBDG_YS_C64
+#define CBDG_YS_C64 32
+#endif
+#ifndef CBDG_TGT_C
+#define CBDG_TGT_C 2048
+#endif
 template <typename T, bool C> struct StepShape;
 template <> struct StepShape<double, false> {
-    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 64;
+    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 64, TGT = 2048;
     static constexpr bool PF_BIG = true, PF_SMALL = false;
 };
 template <> struct StepShape<float, false> {
-    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 32;
+    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 32, TGT = 2048;
     static constexpr bool PF_BIG = true, PF_SMALL = false;
 };
 template <> struct StepShape<double, true> {
-    static constexpr int W_BIG = 2, W_SMALL = 2, YS = 32;
+    static constexpr int W_BIG = 2, W_SMALL = 2, YS = CBDG_YS_C128, TGT = CBDG_TGT_C;
     static constexpr bool PF_BIG = true, PF_SMALL = true;
 };
 template <> struct StepShape<float, true> {
-    static constexpr int W_BIG = 8, W_SMALL = 4, YS = 32;
+    static constexpr int W_BIG = 8, W_SMALL = 4, YS = CBDG_YS_C64, TGT = CBDG_TGT_C;
     static constexpr bool PF_BIG = false, PF_SMALL = false;
 };
 
 // Row-segment length: the longest of YS, YS/2, ... (not below 8) that still
 // gives every CU several workgroups; shorter segments cost extra halo rows.
-static int segment_rows(int Ly, int64_t other_blocks, int ys_max)
+static int segment_rows(int Ly, int64_t other_blocks, int ys_max, int64_t target_blocks)
 {
-    constexpr int64_t kTargetBlocks = 2048;
     int ys = ys_max;
-    while (ys > 8 && other_blocks * ceil_div(Ly, ys) < kTargetBlocks) ys /= 2;
+    while (ys > 8 && other_blocks * ceil_div(Ly, ys) < target_blocks) ys /= 2;
     return ys;
 }
 
@@ -926,7 +940,7 @@ static Shape choose_shape(int Lx, int Ly, int64_t n_chunks)
         sh.W = (Lx % 2 == 0) ? 2 : 1; sh.PF = false;
     }
     sh.n_strips = Lx / sh.W;
-    sh.ys = segment_rows(Ly, (int64_t)sh.n_strips * n_chunks, SH::YS);
+    sh.ys = segment_rows(Ly, (int64_t)sh.n_strips * n_chunks, SH::YS, SH::TGT);
     sh.n_segs = (int)ceil_div(Ly, sh.ys);
     return sh;
 }
