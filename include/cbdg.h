@@ -169,8 +169,10 @@ int cbdg_op_destroy(cbdg_op *op);
 int cbdg_op_bounds(const cbdg_op *op, cbdg_bounds *out);
 
 /* Bytes of workspace cbdg_chebyshev_moments needs for tiles of `tile` start
- * vectors at `precision` with `algorithm` (host out): two vector buffers,
- * plus FP64 partial sums for DOUBLING.  EINVAL for DOUBLING when b != 0. */
+ * vectors at `precision` with `algorithm` (host out): the tile's vector
+ * buffers (four for real operators with uniform hopping, whose recursion
+ * advances several steps per launch; two otherwise), plus FP64 partial sums
+ * for DOUBLING.  EINVAL for DOUBLING when b != 0. */
 int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision,
                                 int32_t algorithm, size_t *bytes);
 
