@@ -85,23 +85,29 @@ def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step, three_step=F
     return launches, moved, 3 * L2 * n_steps
 
 
-def adjoint_traffic(N, L2, ckpt=0):
+def adjoint_traffic(N, L2, ckpt=0, tile=1024):
     """Vector streams of the doubling-form reverse pass of one tile (real
     operator, uniform hopping), each a whole-lattice read or write of every
     vector, as the library issues them: the forward a_0 .. a_M keeping the
-    checkpoint pairs (M = N // 2; seed 1 write, first step 2, two-step passes
-    4, single steps 3), the recomputation of each segment's inner vectors
-    (passes 4, a last single step 3), and the adjoint steps m = M .. 1 (read
-    lam_{m+1} and lam_{m+2} where they exist, a_{m-1} and a_m; write lam_m).
+    checkpoint pairs (M = N // 2; seed 1 write, first step 2, three-step
+    passes 4 when the checkpoint stride is a multiple of 3 and the tile has
+    more than 128 vectors, two-step passes 4, single steps 3), the
+    recomputation of each segment's inner vectors (two-step passes 4, a last
+    single step 3), and the adjoint steps m = M .. 1 (read lam_{m+1} and
+    lam_{m+2} where they exist, a_{m-1} and a_m; write lam_m).  The default
+    stride is ceil(sqrt(M + 1)) rounded up to a multiple of 3.
     Returns (streams, launches)."""
     M = N // 2
     top = M
-    k = ckpt if ckpt > 0 else int(math.ceil(math.sqrt(M + 1)))
+    k = ckpt if ckpt > 0 else 3 * -(-int(math.ceil(math.sqrt(M + 1))) // 3)
     J = -(-(top + 1) // k)
+    three = k % 3 == 0 and tile >= 129
     streams, launches = 1, 0
     n = 1
     while n <= top:
-        if n >= 2 and n + 1 <= top:
+        if three and n >= 2 and n + 2 <= top:
+            streams += 4; n += 3
+        elif n >= 2 and n + 1 <= top:
             streams += 4; n += 2
         else:
             streams += 2 if n == 1 else 3; n += 1

@@ -352,7 +352,9 @@ struct Plan {
 };
 
 // Checkpoint stride k = ceil(sqrt(N)) (direct) or ceil(sqrt(M + 1))
-// (doubling) unless given.
+// (doubling), rounded up to a multiple of 3, unless given: three-step passes
+// from a_2 on write the pairs (a_{3m}, a_{3m+1}), which then include every
+// checkpoint pair (a_{jk}, a_{jk+1}).
 static Plan make_plan(int N, int tile, int ckpt_stride, bool dbl)
 {
     Plan p;
@@ -360,7 +362,7 @@ static Plan make_plan(int N, int tile, int ckpt_stride, bool dbl)
     p.top = dbl ? N / 2 : std::max(N - 2, 0);
     p.mtop = dbl ? N / 2 : N - 1;
     const int nvec = p.top + 1;
-    const int kdef = (int)std::ceil(std::sqrt((double)(dbl ? nvec : N)));
+    const int kdef = 3 * (int)ceil_div((int64_t)std::ceil(std::sqrt((double)(dbl ? nvec : N))), 3);
     p.k = ckpt_stride > 0 ? ckpt_stride : std::max(1, kdef);
     p.J = (int)ceil_div(nvec, p.k);
     p.J1 = p.k > 1 ? p.J : 0;
@@ -488,7 +490,26 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
             return nullptr;
         };
         const double2 *p2 = nullptr, *p1 = C0(0);
+        // three-step passes store a_{n+1}, a_{n+2} only; with k a multiple of 3
+        // and the passes starting at n = 2 every checkpoint is among them
+        const bool three = k % 3 == 0 && three_step_f64_real(op, Bt);
         for (int n = 1; n <= top;) {
+            if (three && n >= 2 && n + 2 <= top) {
+                double2 *d1 = dest_of(n + 1, p1, p2, nullptr);
+                double2 *d2 = dest_of(n + 2, p1, p2, d1);
+                S.first = 0;
+                S.n = n;
+                S.prev1 = p1;
+                S.prev2 = p2;
+                S.out = d1;
+                S.out2 = d2;
+                rc = run_step3_f64_real(op, S, st);
+                if (rc) return rc;
+                p2 = d1;
+                p1 = d2;
+                n += 3;
+                continue;
+            }
             if (two && n >= 2 && n + 1 <= top) {
                 double2 *d0 = dest_of(n, p1, p2, nullptr);
                 double2 *d1 = dest_of(n + 1, p1, p2, d0);

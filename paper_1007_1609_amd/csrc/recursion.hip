@@ -1335,6 +1335,22 @@ bool two_step_f64_real(const cbdg_op *op)
     return op->scalar == CBDG_REAL && !op->general && CBDG_TWO_STEP;
 }
 
+bool three_step_f64_real(const cbdg_op *op, int Bt)
+{
+    return two_step_f64_real(op) && Step3Shape<double>::ON && Bt >= kThreeStepMinVectors;
+}
+
+int run_step3_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st)
+{
+    if (!three_step_f64_real(op, A.Bt))
+        return fail(CBDG_EUNSUPPORTED, "three-step pass: needs a real operator with uniform hopping and "
+                    "a tile of at least %d vectors", kThreeStepMinVectors);
+    A.onsite = op->onsite64;
+    A.bonds = op->bonds64;
+    A.first = 0;
+    return launch_step3<double>(A, st);
+}
+
 int run_step2_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st)
 {
     if (!two_step_f64_real(op))

@@ -54,6 +54,13 @@ int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st);
 bool two_step_f64_real(const cbdg_op *op);
 int run_step2_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st);
 
+// Three recursion steps in one launch (same operators, tiles of Bt vectors
+// the library runs three-step passes for): a_{n+1} -> A.out and
+// a_{n+2} -> A.out2 from a_{n-2} and a_{n-1}, n >= 2; a_n is not stored.
+// The same aliasing rules as the two-step pass.
+bool three_step_f64_real(const cbdg_op *op, int Bt);
+int run_step3_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st);
+
 // a_0 = |s_b,e> for the tile's vectors (FP64 real layout); writes mu_0 when
 // mu_ee is not null.
 int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, double *mu_ee, double *mu_he, int N,

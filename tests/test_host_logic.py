@@ -70,17 +70,25 @@ def test_precision_schedule_default_switch_is_floored():
 
 def test_reverse_pass_accounting_matches_the_library_plan():
     """Launch and vector-stream counts of the doubling-form reverse pass for
-    the 128x128, N = 512 workload: checkpoint stride 17, 16 segments; the
-    forward is 1 + 127 two-step passes + 1 step, each of the 15 inner
-    segments is recomputed by 7 two-step passes + 1 step, and 256 adjoint
-    steps follow (the kernel trace of that workload counts the same calls)."""
+    the 128x128, N = 512 workload (M = 256).  Default checkpoint stride 18
+    (ceil(sqrt(257)) = 17 rounded up to a multiple of 3), 15 segments: the
+    forward is 1 step + 85 three-step passes; 14 segments are recomputed by
+    8 two-step passes each, the last (a_254 .. a_256) by a pair and a single
+    step; 256 adjoint steps follow."""
     import bench_forms
     streams, launches = bench_forms.adjoint_traffic(512, 128 * 128)
-    assert launches == (1 + 127 + 1) + 15 * (7 + 1) + 256
-    fwd = 1 + 2 + 127 * 4 + 3
-    rec = 15 * (7 * 4 + 3)
+    assert launches == (1 + 85) + (14 * 8 + 2) + 256
+    fwd = 1 + 2 + 85 * 4
+    rec = 14 * 8 * 4 + 4 + 3
     adj = 254 * 5 + 4 + 3
     assert streams == fwd + rec + adj
-    # stride 1 stores every vector: no recomputation
+    # stride 17 (not a multiple of 3): two-step forward, 1 + 127 passes + 1
+    s17, l17 = bench_forms.adjoint_traffic(512, 128 * 128, ckpt=17)
+    assert l17 == (1 + 127 + 1) + 15 * (7 + 1) + 256
+    assert s17 == (1 + 2 + 127 * 4 + 3) + 15 * (7 * 4 + 3) + adj
+    # stride 1 stores every vector: no recomputation, two-step forward
     s1, l1 = bench_forms.adjoint_traffic(512, 128 * 128, ckpt=1)
-    assert l1 == 129 + 256 and s1 == fwd + adj
+    assert l1 == 129 + 256 and s1 == (1 + 2 + 127 * 4 + 3) + adj
+    # small tiles: two-step forward at stride 18
+    s64, l64 = bench_forms.adjoint_traffic(512, 128 * 128, tile=64)
+    assert l64 == (1 + 127 + 1) + (14 * 8 + 2) + 256

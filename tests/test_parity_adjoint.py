@@ -47,6 +47,8 @@ ALGS = [1, 2]  # direct adjoint, adjoint of the doubling formulas
     (16, 20, 64, 300, 0, 0),     # several 256-lane chunks of one tile
     (12, 14, 41, 64, 2, 0),      # stride 2 (pairs only), odd N
     (12, 14, 44, 64, 5, 0),      # even N, ragged last segment
+    (16, 20, 64, 200, 6, 0),     # three-step checkpointing forward (stride 6), ragged tiles
+    (14, 12, 47, 168, 3, 1),     # three-step forward, stride 3, periodic
 ])
 def test_backward_matches_oracle(Lx, Ly, N, tile, ckpt, bc, alg):
     w = W.small_random(Lx, Ly, N=N, seed=Lx + Ly + N, bc_x=bc, bc_y=bc)
@@ -87,15 +89,20 @@ def test_only_one_cotangent(which, alg):
     assert _rel(ge, oe) < 1e-10 and _rel(gd, od) < 1e-10
 
 
+@pytest.mark.parametrize("tile", [64, 144])
 @pytest.mark.parametrize("alg", ALGS)
-def test_checkpoint_strides_give_identical_bits(alg):
+def test_checkpoint_strides_give_identical_bits(alg, tile):
+    """Every kernel that applies Ht rounds alike, so the gradients do not
+    depend on the checkpoint stride -- nor, with 144-vector tiles, on whether
+    the checkpointing forward takes three steps per launch (strides that are
+    multiples of 3) or two."""
     w = W.small_random(12, 12, N=50, seed=6)
     rng = np.random.default_rng(3)
     n = len(w.start_sites)
     dee, dhe = rng.normal(size=(n, 50)), rng.normal(size=(n, 50))
-    ref = _gpu_backward(w, 50, dee, dhe, 64, 1, algorithm=alg)
-    for k in (2, 3, 7, 25, 26, 49, 50):
-        got = _gpu_backward(w, 50, dee, dhe, 64, k, algorithm=alg)
+    ref = _gpu_backward(w, 50, dee, dhe, tile, 1, algorithm=alg)
+    for k in (2, 3, 6, 7, 25, 26, 49, 50):
+        got = _gpu_backward(w, 50, dee, dhe, tile, k, algorithm=alg)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k
 
 
