@@ -333,7 +333,8 @@ int cbdg_ldos_backward(const double *d_ldos, int64_t n_rows, int32_t N,
                        double *d_mu_ee, void *stream);
 
 /* Bytes of workspace cbdg_chebyshev_moments_backward needs (host out).
- * ckpt_stride 0 selects k = ceil(sqrt(N)). */
+ * ckpt_stride 0 selects k = ceil(sqrt(N)) (direct) or ceil(sqrt(N/2 + 1))
+ * (doubling), rounded up to a multiple of 3. */
 int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
                                  int32_t ckpt_stride, int32_t algorithm, size_t *bytes);
 
@@ -347,8 +348,10 @@ int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
  *   lam_n = w_n + 2 Ht^T lam_{n+1} - lam_{n+2}
  * runs over them, accumulating sum_{n>=1} c_n <lam_n, dHt/dtheta a_{n-1}>
  * (c_1 = 1, c_n = 2).  The sum over start vectors is reduced in a fixed
- * order, so repeated calls give identical bits.
- *   ckpt_stride  k; 0: ceil(sqrt(N)) (DIRECT) or ceil(sqrt(N/2 + 1)) (DOUBLING)
+ * order, so repeated calls give identical bits, whatever the stride.
+ *   ckpt_stride  k; 0: ceil(sqrt(N)) (DIRECT) or ceil(sqrt(N/2 + 1)) (DOUBLING),
+ *                rounded up to a multiple of 3 (the forward then advances
+ *                three steps per launch on tiles of more than 128 vectors)
  *   algorithm    enum cbdg_algorithm.  DOUBLING (AUTO when b == 0, N >= 3)
  *                differentiates the doubling formulas instead: forward and
  *                adjoint run over a_0 .. a_{N/2} only, the cotangent of a_m
