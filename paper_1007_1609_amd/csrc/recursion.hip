@@ -56,7 +56,8 @@ namespace cbdg {
 // 1024-vector tile at 256x256: 90.9 -> 85.0 us per moment index (spread
 // start sites), 80.8 -> 75.6 (a block of rows).  FP64 three-step (one wave
 // per SIMD, windows partly in AGPRs) is faster without it: 186.9 / 142.2 us
-// against 188.1 / 143.6.  The same prefetch in the FP64 two-step pass was
+// against 188.1 / 143.6 at 128-row segments, 163.6 / 127.0 against
+// 169.0 / 131.5 at 256 rows.  The same prefetch in the FP64 two-step pass was
 // slower too (W = 8: 192.8 -> 197.3 us; W = 4: 226.9 us).
 #ifndef CBDG_PF3_F32
 #define CBDG_PF3_F32 1
@@ -1127,7 +1128,9 @@ static bool uses_two_step(const cbdg_op *op)
 #define CBDG_W3_F32 4
 #endif
 // Longest row segment and workgroup target of the three-step passes, per
-// type (FP64, spread / rows, us per moment index): 256 rows 163.2 / 126.6,
+// type (FP64, spread / rows, us per moment index; FP32 widths W = 2 and
+// W = 8 with 256 rows were slower, 111.2 and 105.7 against 82.8 spread):
+// 256 rows 163.2 / 126.6,
 // 128 rows 186.6 / 141.9, 64 rows with 512 or 1024 workgroups 191.9 / 147.1 --
 // at 256x256 the 256 workgroups of 256-row segments put exactly one wave on
 // every SIMD for the whole launch.  FP32 (two waves per SIMD): 128 rows
