@@ -172,15 +172,18 @@ __global__ void k_coefficients(CoefArgs A)
 
 static int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(ceil_div(n, kBlock), 1), 4096); }
 
-static void free_op(cbdg_op *op)
+// Releases the operator and its device arrays; returns the first hipFree
+// error (the other arrays are released all the same).
+static hipError_t free_op(cbdg_op *op)
 {
-    if (!op) return;
-    hipFree(op->onsite64);
-    hipFree(op->onsite32);
-    hipFree(op->bonds64);
-    hipFree(op->bonds32);
-    hipFree(op->scratch);
+    if (!op) return hipSuccess;
+    hipError_t first = hipSuccess;
+    for (void *p : {(void *)op->onsite64, (void *)op->onsite32, op->bonds64, op->bonds32, (void *)op->scratch}) {
+        const hipError_t e = hipFree(p);
+        if (first == hipSuccess) first = e;
+    }
     delete op;
+    return first;
 }
 
 }  // namespace cbdg
@@ -243,10 +246,10 @@ extern "C" int cbdg_build_bdg(const cbdg_lattice *lat, double t, double mu_c,
         hipMalloc(&op->scratch, 256) != hipSuccess ||
         (op->general && (hipMalloc(&op->bonds64, L2 * b64) != hipSuccess ||
                          hipMalloc(&op->bonds32, L2 * b32) != hipSuccess))) {
-        free_op(op);
+        const size_t bytes = L2 * (sizeof(OnSite<double>) + sizeof(OnSite<float>) + (op->general ? b64 + b32 : 0));
+        (void)free_op(op);  // already failing: the first error is reported
         (void)hipGetLastError();
-        return fail(CBDG_ENOMEM, "build_bdg: device allocation of %zu coefficient bytes failed",
-                    L2 * (sizeof(OnSite<double>) + sizeof(OnSite<float>) + (op->general ? b64 + b32 : 0)));
+        return fail(CBDG_ENOMEM, "build_bdg: device allocation of %zu coefficient bytes failed", bytes);
     }
 
     RawInputs in{eps, (const double *)delta, (const double *)delta_bond, peierls,
@@ -263,13 +266,13 @@ extern "C" int cbdg_build_bdg(const cbdg_lattice *lat, double t, double mu_c,
         if (e == hipSuccess) e = hipMemcpyAsync(&bits, op->scratch, sizeof(bits), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
-            free_op(op);
+            (void)free_op(op);  // already failing: the first error is reported
             return fail(CBDG_EHIP, "build_bdg: spectral bound failed: %s", hipGetErrorString(e));
         }
         double R;
         std::memcpy(&R, &bits, sizeof(R));
         if (!std::isfinite(R) || !(R > 0.0)) {
-            free_op(op);
+            (void)free_op(op);  // already failing: the first error is reported
             return fail(CBDG_EINVAL, "build_bdg: spectral bound %g is not positive and finite "
                         "(non-finite inputs, or an operator that is identically zero)", R);
         }
@@ -284,7 +287,7 @@ extern "C" int cbdg_build_bdg(const cbdg_lattice *lat, double t, double mu_c,
     hipLaunchKernelGGL(k_coefficients, dim3(grid_for(op->L2)), dim3(kBlock), 0, st, ca);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
-        free_op(op);
+        (void)free_op(op);  // already failing: the first error is reported
         return fail(CBDG_EHIP, "build_bdg: coefficient kernel failed: %s", hipGetErrorString(e));
     }
     *op_out = op;
@@ -315,7 +318,8 @@ extern "C" int cbdg_op_destroy(cbdg_op *op)
     clear_error();
     if (!op) return CBDG_OK;
     hipError_t e = hipDeviceSynchronize();
-    free_op(op);
+    const hipError_t f = free_op(op);
+    if (e == hipSuccess) e = f;
     if (e != hipSuccess) return fail(CBDG_EHIP, "op_destroy: %s", hipGetErrorString(e));
     return CBDG_OK;
 }
