@@ -32,6 +32,12 @@ def _ptr(t: Optional[torch.Tensor], dtype=None, name="tensor"):
     return t.data_ptr()
 
 
+def _need(t: Optional[torch.Tensor], numel: int, name: str) -> None:
+    """Caller-supplied arrays must hold at least what the call writes or reads."""
+    if t is not None and t.numel() < numel:
+        raise ValueError("%s has %d elements, the call needs %d" % (name, t.numel(), numel))
+
+
 def weights(a: float, b: float, kernel: str = "jackson", lam: float = 0.0, T: float = 0.0,
             E_c: float = 0.0) -> L.cbdg_weights:
     k = {"jackson": L.CBDG_KERNEL_JACKSON, "lorentz": L.CBDG_KERNEL_LORENTZ}[kernel]
@@ -143,9 +149,12 @@ def chebyshev_moments(op: Operator, sites: torch.Tensor, N: int, tile: int,
                             device=sites.device)
     else:
         mu_ee, mu_he = out
+        _need(mu_ee, n * int(N), "mu_ee")
+        _need(mu_he, n * int(N), "mu_he")
     L.cbdg_chebyshev_moments(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N), int(tile),
                              int(precision), int(algorithm), _ptr(ws, None, "workspace"), ws.numel(),
-                             _ptr(mu_ee, torch.float64, "mu_ee"), _ptr(mu_he, None, "mu_he"),
+                             _ptr(mu_ee, torch.float64, "mu_ee"),
+                             _ptr(mu_he, torch.complex128 if op.is_complex else torch.float64, "mu_he"),
                              _stream())
     return mu_ee, mu_he
 
@@ -179,6 +188,10 @@ def bond_gap_update(nb_he: torch.Tensor, op: Operator, w: L.cbdg_weights, U: flo
     every site of op's lattice (rows in site order)."""
     N = nb_he.shape[-1]
     coeff = _coeff_for(w, N, L.CBDG_QTY_GAP, coeff, nb_he.device)
+    _need(nb_he, op.L2 * 4 * N, "nb_he")
+    _need(delta_bond_in, 2 * op.L2, "delta_bond_in")
+    _need(delta_bond_out, 2 * op.L2, "delta_bond_out")
+    _need(coeff, N, "coeff")
     if delta_bond_out is None:
         delta_bond_out = torch.empty_like(delta_bond_in)
     if resid is None:
@@ -195,8 +208,10 @@ def bond_current(op: Operator, nb_ee: torch.Tensor, w: L.cbdg_weights,
                  coeff: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Particle current [2, L2] along the +x and +y bond of every site."""
     N = nb_ee.shape[-1]
+    _need(nb_ee, op.L2 * 4 * N, "nb_ee")
     if coeff is None:
         coeff = sum_coefficients(w, N, L.CBDG_QTY_DENSITY, nb_ee.device)
+    _need(coeff, N, "coeff")
     out = torch.empty((2, op.L2), dtype=torch.float64, device=nb_ee.device)
     ddt = torch.complex128 if op.is_complex else torch.float64
     L.cbdg_bond_current(op.handle, _ptr(nb_ee, ddt, "nb_ee"), int(N), C.byref(w), _ptr(coeff, torch.float64, "coeff"),
@@ -237,6 +252,9 @@ def gap_update(mu_he: torch.Tensor, w: L.cbdg_weights, U: float, delta_in: torch
     n, N = mu_he.shape
     cplx = mu_he.is_complex()
     coeff = _coeff_for(w, N, L.CBDG_QTY_GAP, coeff, mu_he.device)
+    for t, name in ((delta_in, "delta_in"), (delta_out, "delta_out"), (U_rows, "U_rows")):
+        _need(t, n, name)
+    _need(coeff, N, "coeff")
     if delta_out is None:
         delta_out = torch.empty_like(delta_in)
     if resid is None:
@@ -254,6 +272,7 @@ def ldos(mu_ee: torch.Tensor, w: L.cbdg_weights, energies: torch.Tensor,
          out: Optional[torch.Tensor] = None):
     n, N = mu_ee.shape
     nE = int(energies.numel())
+    _need(out, n * nE, "ldos out")
     if out is None:
         out = torch.empty((n, nE), dtype=torch.float64, device=mu_ee.device)
     L.cbdg_ldos(_ptr(mu_ee, torch.float64, "mu_ee"), n, N, C.byref(w),
@@ -269,6 +288,8 @@ def gap_update_backward(d_delta_out: torch.Tensor, N: int, w: L.cbdg_weights, U:
     d_mu = torch.empty((n, N), dtype=torch.float64, device=d_delta_out.device)
     d_in = torch.empty_like(d_delta_out) if want_delta_in else None
     coeff = _coeff_for(w, N, L.CBDG_QTY_GAP, coeff, d_delta_out.device)
+    _need(U_rows, n, "U_rows")
+    _need(coeff, N, "coeff")
     L.cbdg_gap_update_backward(_ptr(d_delta_out, torch.float64, "d_delta_out"), n, int(N), C.byref(w),
                                _ptr(coeff, torch.float64, "coeff"), float(U), _ptr(U_rows, torch.float64, "U_rows"), float(alpha),
                                _ptr(d_mu, torch.float64, "d_mu_he"), _ptr(d_in, torch.float64, "d_delta_in"),
@@ -281,6 +302,8 @@ def density(mu_ee: torch.Tensor, w: L.cbdg_weights, coeff: Optional[torch.Tensor
     """Electron density per site, 2 sum_n g_n c_n mu_ee_n (f(E) weight)."""
     n, N = mu_ee.shape
     coeff = _coeff_for(w, N, L.CBDG_QTY_DENSITY, coeff, mu_ee.device)
+    _need(coeff, N, "coeff")
+    _need(out, n, "density out")
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=mu_ee.device)
     L.cbdg_density(_ptr(mu_ee, torch.float64, "mu_ee"), n, N, C.byref(w), _ptr(coeff, torch.float64, "coeff"),
@@ -292,6 +315,7 @@ def density_backward(d_density: torch.Tensor, N: int, w: L.cbdg_weights,
                      coeff: Optional[torch.Tensor] = None) -> torch.Tensor:
     n = int(d_density.numel())
     coeff = _coeff_for(w, N, L.CBDG_QTY_DENSITY, coeff, d_density.device)
+    _need(coeff, N, "coeff")
     d_mu = torch.empty((n, N), dtype=torch.float64, device=d_density.device)
     L.cbdg_density_backward(_ptr(d_density, torch.float64, "d_density"), n, int(N), C.byref(w),
                             _ptr(coeff, torch.float64, "coeff"), _ptr(d_mu, torch.float64, "d_mu_ee"), _stream())
@@ -300,6 +324,7 @@ def density_backward(d_density: torch.Tensor, N: int, w: L.cbdg_weights,
 
 def ldos_backward(d_ldos: torch.Tensor, N: int, w: L.cbdg_weights, energies: torch.Tensor):
     n, nE = d_ldos.shape
+    _need(energies, nE, "energies")
     d_mu = torch.empty((n, N), dtype=torch.float64, device=d_ldos.device)
     L.cbdg_ldos_backward(_ptr(d_ldos, torch.float64, "d_ldos"), n, int(N), C.byref(w),
                          _ptr(energies, torch.float64, "energies"), nE, _ptr(d_mu, torch.float64, "d_mu_ee"),
@@ -324,6 +349,10 @@ def chebyshev_moments_backward(op: Operator, sites: torch.Tensor, N: int, tile: 
     need = backward_workspace_bytes(op, eff, N, ckpt_stride, algorithm)
     if ws is None or ws.numel() < need:
         ws = workspace(need, sites.device)
+    _need(dmu_ee, n * int(N), "dmu_ee")
+    _need(dmu_he, n * int(N), "dmu_he")
+    _need(grad_eps, op.L2, "grad_eps")
+    _need(grad_delta, op.L2, "grad_delta")
     if grad_eps is None:
         grad_eps = torch.zeros(op.L2, dtype=torch.float64, device=sites.device)
     if grad_delta is None:

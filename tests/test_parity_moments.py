@@ -97,6 +97,31 @@ def test_empty_start_set():
     op.close()
 
 
+def test_binding_rejects_short_or_mistyped_outputs():
+    """Caller-supplied outputs too small for the call, or of the wrong element
+    type, are refused before anything is launched."""
+    import paper_1007_1609_amd as P
+    w = W.small_random(6, 6, N=10, seed=1)
+    op = P.Operator.from_workload(w, DEV)
+    sites = torch.arange(36, dtype=torch.int32, device=DEV)
+    short = torch.empty((35, 10), dtype=torch.float64, device=DEV)
+    full = torch.empty((36, 10), dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        P.chebyshev_moments(op, sites, 10, 64, out=(short, full))
+    with pytest.raises(ValueError):
+        P.chebyshev_moments(op, sites, 10, 64, out=(full, full.to(torch.complex128)))
+    mu_ee, mu_he = P.chebyshev_moments(op, sites, 10, 64, out=(full, torch.empty_like(full)))
+    wts = op.weights()
+    d_in = torch.full((36,), 0.1, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        P.gap_update(mu_he, wts, 2.0, d_in, delta_out=torch.empty(30, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError):
+        P.ldos(mu_ee, wts, torch.zeros(4, dtype=torch.float64, device=DEV),
+               out=torch.empty((36, 3), dtype=torch.float64, device=DEV))
+    torch.cuda.synchronize()
+    op.close()
+
+
 def test_out_of_range_site_gives_nan_row_and_flag():
     import paper_1007_1609_amd as P
     w = W.small_random(6, 6, N=12, seed=1)
