@@ -82,10 +82,24 @@ def cpu_baseline(w, a, b, n_sites: int, threads: int, target_s: float = 15.0):
     t0 = time.perf_counter()
     oracle.moments(H, sites, w.N, n_threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n_sites * w.N / dt, "unit": "moments/s", "cores": oracle.max_threads(),
+    cores = oracle.max_threads()  # the threads that run used (set by the call above)
+    # one thread on a few of the same sites (sets the oracle's thread count to 1)
+    few = sites[:: max(1, n_sites // 3)][:3]
+    t0 = time.perf_counter()
+    oracle.moments(H, few, w.N, n_threads=1)
+    dt1 = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": n_sites * w.N / dt, "unit": "moments/s", "cores": cores,
             "kind": "oracle",
             "sample": "%d start sites spread over the same 256x256 lattice, N=%d, FP64 CSR "
-                      "recursion, %.1f s" % (n_sites, w.N, dt)}
+                      "recursion, %.1f s" % (n_sites, w.N, dt),
+            "value_1thread": len(few) * w.N / dt1, "sample_1thread": "%d of those sites, %.1f s" % (len(few), dt1),
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def log(msg):
