@@ -76,6 +76,22 @@ def test_degenerate_lattices(Lx, Ly):
     _check(w)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("Lx,Ly,tile", [(1, 300, 300), (300, 1, 200), (3, 90, 270), (6, 50, 150)])
+def test_degenerate_lattices_three_step_passes(Lx, Ly, tile, prec):
+    """Tiles of more than 128 vectors on one-row, one-column and narrow
+    lattices: three-step passes with strips of W = 1 or 2 sites, segments
+    longer than the lattice, and the ragged last tile of (300, 1) taking
+    two-step passes."""
+    w = W.small_random(Lx, Ly, N=41, seed=Lx * Ly)
+    op, g_ee, g_he = gpu_moments(w, tile=tile, precision=prec)
+    a, b = op.bounds.a, op.bounds.b
+    op.close()
+    o_ee, o_he = oracle.workload_moments(w, a, b)
+    e = max(maxdiff(g_ee, o_ee), maxdiff(g_he, o_he))
+    assert e <= (TOL_MOMENT if prec == 0 else 2e-5), e
+
+
 @pytest.mark.parametrize("N", [1, 2, 3])
 def test_few_moments(N):
     w = W.small_random(6, 6, N=N, seed=1)
