@@ -212,9 +212,73 @@ def test_jackson_smoothed_delta_is_positive():
         assert abs(np.trapezoid(f, x) - 1.0) < 2e-2
 
 
-def test_lorentz_kernel_endpoints():
-    g = oracle.lorentz(100, 4.0)
-    assert g[0] == 1.0 and abs(g[-1] - np.sinh(4.0 * 0.01) / np.sinh(4.0)) < 1e-15
+def _damped_delta_series(N, lam, x0, x):
+    """sum_{n<N} (2 - delta_n0) g_n T_n(x0) T_n(x) for the Lorentz kernel,
+    summed as geometric series: sinh(lam (1 - n/N)) / sinh(lam)
+    = (r^n - q s^n)/(1 - q) with r = exp(-lam/N), s = exp(lam/N),
+    q = exp(-2 lam), and T_n(x0) T_n(x) = [cos(n(th - th0)) + cos(n(th + th0))]/2,
+    sum_{n<N} (2 - delta_n0) z^n cos(n phi) = 2 Re[(1 - (z e^{i phi})^N)/(1 - z e^{i phi})] - 1."""
+    eps = lam / N
+    r, s, q = np.exp(-eps), np.exp(eps), np.exp(-2.0 * lam)
+    th, th0 = np.arccos(x), np.arccos(x0)
+
+    def geo(z, phi):
+        ze = z * np.exp(1j * phi)
+        return 2.0 * np.real((1.0 - ze ** N) / (1.0 - ze)) - 1.0
+
+    def series(phi):
+        return (geo(r, phi) - q * geo(s, phi)) / (1.0 - q)
+
+    return 0.5 * (series(th - th0) + series(th + th0))
+
+
+def _lorentz_ldos_of_one_level(kernel_fn, N, lam, x0, x):
+    """LDOS of a single level at x0 (moments mu_n = T_n(x0), a = 1, b = 0)
+    through oracle.ldos with the kernel factors of kernel_fn."""
+    mu = ed.cheb_T(np.arange(N), x0)[None, :]
+    orig = oracle.kpm.lorentz
+    try:
+        oracle.kpm.lorentz = kernel_fn
+        return oracle.ldos(mu, x, 1.0, 0.0, kernel="lorentz", lam=lam)[0]
+    finally:
+        oracle.kpm.lorentz = orig
+
+
+@pytest.mark.parametrize("N,lam,x0", [(64, 5.0, 0.3), (1000, 3.0, -0.55), (4000, 4.0, 0.0)])
+def test_lorentz_series_equals_geometric_closed_form(N, lam, x0):
+    # The Lorentz kernel of the kernel equation after eq. (ref2) is a difference
+    # of two geometric sequences in n, so the damped series of one level has a
+    # closed form; pins the kernel (index and N) and the LDOS weights together.
+    x = np.concatenate([np.linspace(-0.95, 0.95, 39), x0 + np.linspace(-0.01, 0.01, 21)])
+    got = _lorentz_ldos_of_one_level(oracle.lorentz, N, lam, x0, x)
+    ref = _damped_delta_series(N, lam, x0, x) / (np.pi * np.sqrt(1.0 - x * x))
+    assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_lorentz_pin_rejects_a_misindexed_kernel():
+    # a kernel shifted by one index, or normalised with N - 1 instead of N,
+    # fails the closed-form check by orders of magnitude
+    N, lam, x0 = 1000, 3.0, -0.55
+    x = x0 + np.linspace(-0.01, 0.01, 21)
+    ref = _damped_delta_series(N, lam, x0, x) / (np.pi * np.sqrt(1.0 - x * x))
+    for bad in (lambda N, lam: np.sinh(lam * (1.0 - (np.arange(N) + 1.0) / N)) / np.sinh(lam),
+                lambda N, lam: np.sinh(lam * (1.0 - np.arange(N) / (N - 1.0))) / np.sinh(lam)):
+        got = _lorentz_ldos_of_one_level(bad, N, lam, x0, x)
+        assert np.max(np.abs(got - ref)) > 1e-4 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("N,lam", [(4000, 4.0), (40000, 8.0)])
+def test_lorentz_damped_level_is_a_lorentzian(N, lam):
+    # The paper's statement under the Lorentz-kernel equation: the damped series
+    # of a delta function is a Lorentzian of width eps = lam/N (rescaled units).
+    # At x0 = 0, to O(eps^2), the deviation is the truncation of the
+    # exp(-eps n) series at n = N and the exp(-2 lam) part of the kernel, each
+    # about exp(-lam) of the peak height.
+    eps = lam / N
+    x = np.linspace(-20 * eps, 20 * eps, 81)
+    got = _lorentz_ldos_of_one_level(oracle.lorentz, N, lam, 0.0, x)
+    lor = eps / np.pi / (x * x + eps * eps)
+    assert np.max(np.abs(got - lor)) < 2.5 * np.exp(-lam) * np.max(lor)
 
 
 @pytest.mark.parametrize("x_c", [1.0, 0.6, 0.13])
@@ -332,6 +396,58 @@ def test_ldos_equals_kernel_broadened_ed():
     Ef = np.linspace(-a * 0.999, a * 0.999, 20001)
     tot = np.trapezoid(oracle.ldos(mu_ee[:3], Ef, a, b), Ef, axis=1)
     assert np.max(np.abs(tot - 1.0)) < 2e-2
+
+
+def _panel_integral(f, lo, hi, h):
+    """int_lo^hi f(E) dE with 8-point Gauss-Legendre panels of width <= h;
+    f maps an array of energies to [len(E), rows]."""
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    edges = np.linspace(lo, hi, int(np.ceil((hi - lo) / h)) + 1)
+    mid, half = 0.5 * (edges[1:] + edges[:-1]), 0.5 * (edges[1:] - edges[:-1])
+    pts = (mid[:, None] + half[:, None] * xg[None, :]).ravel()
+    return (half[:, None] * wg[None, :]).ravel() @ f(pts)
+
+
+def _ldos_level_weight_error(ldos_fn):
+    """Largest error of the spectral weight the LDOS puts around each isolated
+    level: int over [midpoint to the level below, midpoint to the level above]
+    of N_up(E, i) dE must equal |u_k(i)|^2 (eq. (imag1): the spectral function
+    is sum_k |u_k(i)|^2 delta(E - E_k)), up to the Jackson kernel's tails,
+    which at a distance of 30 kernel widths are far below 1e-5."""
+    w = W.small_random(3, 2, N=64, seed=5)
+    _, _, a, b = oracle.workload_bounds(w)
+    Et, V = ed.eig(w, a, b)
+    E = Et * a + b
+    N = 4096
+    mu_ee, _ = oracle.workload_moments(w, a, b, N=N)
+    sig = a * np.pi / N                       # Jackson resolution in energy
+    errs = []
+    for k in range(len(E)):
+        if (k > 0 and E[k] - E[k - 1] < 60 * sig) or (k + 1 < len(E) and E[k + 1] - E[k] < 60 * sig):
+            continue
+        lo = 0.5 * (E[k - 1] + E[k]) if k > 0 else b - 0.9999 * a
+        hi = 0.5 * (E[k + 1] + E[k]) if k + 1 < len(E) else b + 0.9999 * a
+        got = _panel_integral(lambda e: ldos_fn(mu_ee, e, a, b).T, lo, hi, sig / 2)
+        errs.append(np.max(np.abs(got - np.abs(V[:w.L2, k]) ** 2)))
+    assert len(errs) >= 8
+    return max(errs)
+
+
+def test_ldos_puts_each_levels_weight_around_it():
+    # eq. (ldos) with eq. (imag2): the n >= 1 terms carry a factor 2 against
+    # n = 0 (a_n = mu_n / (1 + delta_n0)); the integrated weight of one level
+    # depends on every term of the series
+    assert _ldos_level_weight_error(oracle.ldos) < 1e-5
+
+
+def test_ldos_weight_pin_rejects_a_dropped_factor_two():
+    # a copy of the oracle's LDOS with the factor 2 on n >= 1 replaced by 1
+    def dropped(mu_ee, energies, a, b):
+        N = mu_ee.shape[-1]
+        x = (np.asarray(energies) - b) / a
+        T = ed.cheb_T(np.arange(N), x).T
+        return mu_ee @ (T * oracle.jackson(N)[None, :] / (np.pi * a * np.sqrt(1 - x * x))[:, None]).T
+    assert _ldos_level_weight_error(dropped) > 1e-2
 
 
 # ---------------------------------------------- P10 / P11 / P12: gradients
