@@ -75,7 +75,7 @@ class Operator:
                          _ptr(peierls, torch.float64, "peierls"),
                          C.byref(fb) if fb is not None else None, float(delta_cap), float(eta),
                          _stream(), C.byref(h), C.byref(out))
-        self.handle = h
+        self._handle = h
         self.bounds = Bounds(out.E_min, out.E_max, out.a, out.b)
         self.has_bond = delta_bond is not None
         self._alive = True
@@ -95,6 +95,14 @@ class Operator:
                    complex_=cplx, fixed=fixed, delta_cap=w.delta_cap, eta=w.eta)
 
     @property
+    def handle(self):
+        """The library handle; a closed operator raises instead of handing out
+        the released pointer."""
+        if not getattr(self, "_alive", False):
+            raise ValueError("operator has been closed")
+        return self._handle
+
+    @property
     def L2(self):
         return self.Lx * self.Ly
 
@@ -103,8 +111,9 @@ class Operator:
         return self.scalar == L.CBDG_COMPLEX
 
     def update_delta(self, delta: torch.Tensor, delta_bond: Optional[torch.Tensor] = None):
+        h = self.handle
         ddt = torch.complex128 if self.is_complex else torch.float64
-        L.cbdg_op_update_delta(self.handle, _ptr(delta, ddt, "delta"),
+        L.cbdg_op_update_delta(h, _ptr(delta, ddt, "delta"),
                                _ptr(delta_bond, ddt, "delta_bond"), _stream())
 
     def weights(self, kernel="jackson", lam=0.0, E_c=0.0, T=0.0):
@@ -112,8 +121,8 @@ class Operator:
 
     def close(self):
         if getattr(self, "_alive", False):
-            L.cbdg_op_destroy(self.handle)
-            self._alive = False
+            h, self._handle, self._alive = self._handle, None, False
+            L.cbdg_op_destroy(h)
 
     def __del__(self):
         try:

@@ -49,8 +49,9 @@ class _Moments(torch.autograd.Function):
     def backward(ctx, g_ee, g_he):
         g_ee = None if g_ee is None else g_ee.contiguous()
         g_he = None if g_he is None else g_he.contiguous()
+        # the operator stays alive with the graph (a retained graph may run
+        # backward again); it is released when the graph is freed
         ge, gd = chebyshev_moments_backward(ctx.op, ctx.sites, ctx.N, ctx.tile, g_ee, g_he, ctx.ckpt)
-        ctx.op.close()
         return ge, gd, None, None, None, None, None
 
 

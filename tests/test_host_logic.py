@@ -92,3 +92,19 @@ def test_reverse_pass_accounting_matches_the_library_plan():
     # small tiles: two-step forward at stride 18
     s64, l64 = bench_forms.adjoint_traffic(512, 128 * 128, tile=64)
     assert l64 == (1 + 127 + 1) + (14 * 8 + 2) + 256
+
+
+def test_closed_operator_raises_before_any_library_call():
+    # a released operator hands out no pointer: every wrapper that needs the
+    # handle raises on the host instead of passing freed memory to the library
+    import pytest
+    import paper_1007_1609_amd as P
+    op = object.__new__(P.Operator)
+    op._handle, op._alive = None, False
+    with pytest.raises(ValueError, match="closed"):
+        P.moments_workspace_bytes(op, 64)
+    with pytest.raises(ValueError, match="closed"):
+        P.backward_workspace_bytes(op, 64, 16)
+    with pytest.raises(ValueError, match="closed"):
+        op.update_delta(None)
+    op.close()   # closing twice is a no-op

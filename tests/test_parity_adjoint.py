@@ -198,6 +198,27 @@ def test_autograd_sum_delta_matches_oracle_and_fd():
         assert abs(g_eps[j] - rich) <= 1e-6 * max(1.0, np.max(np.abs(g_eps))), j
 
 
+def test_autograd_second_backward_through_a_retained_graph():
+    # the moments' operator lives as long as the graph: a second backward
+    # through a retained graph runs the reverse pass again and adds the same
+    # gradient
+    P = _P()
+    from paper_1007_1609_amd import autograd as AG
+    w = _small_cfg4(L=16, N=64)
+    _, _, a, b = oracle.workload_bounds(w)
+    geom = AG.Geometry.of(w, a, b)
+    eps = torch.as_tensor(w.eps, device=DEV).requires_grad_(True)
+    delta = torch.as_tensor(w.delta, device=DEV)
+    sites = torch.as_tensor(w.start_sites, device=DEV)
+    mu_ee, mu_he = AG.moments(eps, delta, geom, sites, w.N, w.tile)
+    loss = AG.gap_map(mu_he, delta, w.U, P.weights(a, b)).sum()
+    loss.backward(retain_graph=True)
+    g1 = eps.grad.clone()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert torch.equal(eps.grad, 2.0 * g1)
+
+
 def test_autograd_ldos_at_zero_matches_oracle():
     P = _P()
     from paper_1007_1609_amd import autograd as AG
