@@ -382,24 +382,6 @@ def scf_form(args, dev):
     return line
 
 
-def scf_solve_summary(w, dev, warmup_N=256):
-    """The self-consistent solve of workload w from its initial Delta to
-    max|F(Delta) - Delta| < 1e-6 by the fastest schedule: Anderson mixing,
-    FP32 recursion until the residual is below 5e-7 (an FP64 evaluation ends
-    the loop), plain-mixing warm-up with warmup_N moments down to 1e-2."""
-    op = P.Operator.from_workload(w, dev)
-    d0 = torch.as_tensor(w.delta, device=dev)
-    cb = lambda it, res: log("solve iteration %d residual %.3e" % (it, res))  # noqa: E731
-    r = scf.anderson_mixing(op, w.U, d0, w.N, w.tile, tol=1e-6, max_iter=60, callback=cb,
-                            fast_precision=P.CBDG_FP32_ACC64, warmup_N=warmup_N)
-    op.close()
-    return {"seconds": r.seconds, "converged": bool(r.residual < 1e-6), "residual": r.residual,
-            "passes": r.iterations, "warmup_passes_N%d" % warmup_N: r.warmup_passes,
-            "fp32_passes": r.fast_passes, "fp64_passes": r.iterations - r.fast_passes,
-            "method": "Anderson mixing (depth 5), FP32 recursion first, warm-up with N=%d; "
-                      "ends on an FP64 gap-map evaluation below 1e-6" % warmup_N}
-
-
 def paper_form(args, dev):
     """The paper's two examples as synthetic workloads.
 

@@ -59,7 +59,8 @@ extern "C" {
 #define CBDG_EINVAL       -1  /* bad argument (detected on the host)          */
 #define CBDG_ENOMEM       -2  /* device allocation failed                      */
 #define CBDG_EHIP         -3  /* a HIP runtime call or kernel launch failed    */
-#define CBDG_EBOUNDS      -4  /* spectrum not inside [-1, 1] after rescaling   */
+#define CBDG_EBOUNDS      -4  /* spectrum not inside [-1, 1] after rescaling;
+                                 device-side check, see cbdg_chebyshev_moments */
 #define CBDG_EUNSUPPORTED -5  /* valid request this build does not implement   */
 
 enum cbdg_bc { CBDG_BC_OPEN = 0, CBDG_BC_PERIODIC = 1 };
@@ -194,6 +195,13 @@ int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precisi
  *                algorithm) bytes
  *   mu_ee        out [n_start*N] FP64
  *   mu_he        out [n_start*N] FP64 (REAL) or complex128 (COMPLEX)
+ * Spectral bound (CBDG_EBOUNDS): with the spectrum of Ht inside [-1, 1] every
+ * moment satisfies |mu| <= 1.  The check runs on the device, after each tile,
+ * so that the call stays asynchronous: a moment with |mu| > 1 + tol or not
+ * finite (tol 1e-9 for FP64, 1e-4 for FP32_ACC64 vectors) is stored as NaN.
+ * The call itself cannot return CBDG_EBOUNDS; the NaN reaches the residual of
+ * cbdg_gap_update (NaN), the LDOS and cbdg_check_moments, and the host loop
+ * that reads the residual reports CBDG_EBOUNDS.
  */
 int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
                            int32_t N, int32_t tile, int32_t precision, int32_t algorithm,
@@ -212,7 +220,8 @@ int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_
  *   nb_ee, nb_he  out [n_start*4*N] FP64 (REAL) or complex128 (COMPLEX)
  *   workspace     >= cbdg_moments_workspace_size(op, tile, precision,
  *                 CBDG_ALG_DIRECT) bytes
- * Other arguments and NaN rows for invalid sites as cbdg_chebyshev_moments.
+ * Other arguments, NaN rows for invalid sites and the device-side bound check
+ * (applied to the neighbour moments too) as cbdg_chebyshev_moments.
  */
 int cbdg_chebyshev_moments_nb(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
                               int32_t N, int32_t tile, int32_t precision, void *workspace,

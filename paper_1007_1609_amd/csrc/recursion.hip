@@ -1319,6 +1319,47 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_doubling_reduce(
     }
 }
 
+// Bound of the moments: with the spectrum of Ht inside [-1, 1], every
+// <bra|T_n(Ht)|s,e> of unit vectors has magnitude at most 1.  A moment beyond
+// lim (1 + the precision's rounding allowance) or not finite means the
+// rescaling does not contain the spectrum; it is replaced by NaN, so that
+// every quantity computed from it (gap update residual, LDOS, density) is NaN
+// and the caller sees the failure without a synchronisation here.  Rows of
+// invalid start sites are NaN already.
+__device__ __forceinline__ void bound_entry(double *p, int64_t i, int cplx, double lim)
+{
+    const double nan = __builtin_nan("");
+    if (cplx) {
+        if (!(hypot(p[2 * i], p[2 * i + 1]) <= lim)) { p[2 * i] = nan; p[2 * i + 1] = nan; }
+    } else if (!(fabs(p[i]) <= lim)) {
+        p[i] = nan;
+    }
+}
+
+// ee_c / he_c: the array holds complex128 entries (interleaved) instead of FP64
+__global__ void k_bound_moments(double *__restrict__ ee, double *__restrict__ he, int64_t n, int ee_c, int he_c,
+                                double lim)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bound_entry(ee, i, ee_c, lim);
+        bound_entry(he, i, he_c, lim);
+    }
+}
+
+static int bound_moments(double *ee, double *he, int64_t n, bool ee_c, bool he_c, double lim, hipStream_t st)
+{
+    if (n <= 0) return CBDG_OK;
+    hipLaunchKernelGGL(k_bound_moments, dim3((unsigned)std::min<int64_t>(ceil_div(n, kBlock), 2048)), dim3(kBlock),
+                       0, st, ee, he, n, ee_c ? 1 : 0, he_c ? 1 : 0, lim);
+    CBDG_CHECK_LAUNCH("k_bound_moments");
+    return CBDG_OK;
+}
+
+// Rounding allowance of the bound check: FP64 recursion vectors keep |mu| <= 1
+// to ~1e-13; FP32 vectors to a few 1e-6.
+static double moment_limit(bool f32) { return f32 ? 1.0 + 1e-4 : 1.0 + 1e-9; }
+
 int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st)
 {
     const bool f64 = precision == CBDG_FP64;
@@ -1540,6 +1581,10 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             if (doubling && (rc = reduce(regions1, n, 1))) return rc;
             std::swap(P1, P2);
         }
+        const double lim = moment_limit(std::is_same<T, float>::value);
+        int rc = bound_moments(mee, mhe, (int64_t)Bt * N, false, C, lim, st);
+        if (rc) return rc;
+        if (nb_ee && (rc = bound_moments(A.nb_ee, A.nb_he, (int64_t)Bt * 4 * N, C, C, lim, st))) return rc;
     }
     return CBDG_OK;
 }

@@ -163,6 +163,40 @@ def test_bounds_violation_is_detected():
     assert not ok
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("alg", [1, 2])
+def test_bounds_violation_turns_moments_nan(prec, alg):
+    """The device-side bound check of the moments call: moments beyond
+    1 + tol become NaN (a correct rescaling leaves every moment finite)."""
+    w = W.small_random(8, 8, N=400, seed=4)
+    _, g_ee, g_he = gpu_moments(w, precision=prec, algorithm=alg)
+    assert np.all(np.isfinite(g_ee)) and np.all(np.isfinite(g_he))
+    op, g_ee, g_he = gpu_moments(w, fixed=(0.5 * op_bound(w), 0.0), precision=prec, algorithm=alg)
+    op.close()
+    assert np.isnan(g_ee).any() and np.all(g_ee[:, 0] == 1.0)
+    bad = ~np.isnan(g_ee)
+    assert np.all(np.abs(g_ee[bad]) <= 1.0 + 1e-4)
+
+
+def op_bound(w):
+    _, _, a, _ = oracle.workload_bounds(w)
+    return a
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_scf_reports_ebounds_at_the_first_iteration(prec):
+    import paper_1007_1609_amd as P
+    from paper_1007_1609_amd import scf
+    w = W.config0()
+    op = P.Operator.from_workload(w, DEV, fixed=(0.5 * op_bound(w), 0.0))
+    seen = []
+    with pytest.raises(P.CbdgError) as e:
+        scf.plain_mixing(op, w.U, torch.as_tensor(w.delta, device=DEV), w.N, w.tile, precision=prec,
+                         callback=lambda it, r: seen.append(it))
+    op.close()
+    assert e.value.code == P._lib.CBDG_EBOUNDS and seen == [1]
+
+
 def test_deterministic_bits():
     w = W.small_random(20, 20, N=64, seed=9)
     _, a1, b1 = gpu_moments(w, tile=128)
