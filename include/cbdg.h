@@ -208,6 +208,35 @@ int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_
                            void *workspace, size_t workspace_bytes,
                            double *mu_ee, void *mu_he, void *stream);
 
+/* Size of the per-GPU device array cbdg_chebyshev_moments_static works in. */
+#define CBDG_STATIC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cbdg_chebyshev_moments with its workspace taken from a library-owned device
+ * array of CBDG_STATIC_SCRATCH_BYTES (64 MiB) instead of a caller argument.
+ * The call allocates and frees nothing.  The array is a file-scope device
+ * variable of the library: each GPU the library runs on holds its own copy
+ * until the process ends.
+ *   arguments   as cbdg_chebyshev_moments, without the workspace
+ *   errors      EINVAL when cbdg_moments_workspace_size(op, min(tile, n_start),
+ *               precision, algorithm) exceeds CBDG_STATIC_SCRATCH_BYTES (use
+ *               smaller tiles), or when the current device is not the one the
+ *               operator was built on
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * there; the call writes everything it reads from the array before reading
+ * it.  Calls that overlap on one GPU (several streams or host threads) race
+ * on the array: order them on one stream.  Results are bitwise those of
+ * cbdg_chebyshev_moments with the same tile.
+ */
+int cbdg_chebyshev_moments_static(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                                  int32_t N, int32_t tile, int32_t precision, int32_t algorithm,
+                                  double *mu_ee, void *mu_he, void *stream);
+
+/* CBDG_STATIC_SCRATCH_BYTES as built into the library. */
+size_t cbdg_static_scratch_bytes(void);
+
 /*
  * The moments of cbdg_chebyshev_moments (direct algorithm) and, from the same
  * vectors, the off-diagonal moments between each start site and its four

@@ -62,6 +62,7 @@ SIGNATURES = {
     "cbdg_op_bounds": [_vp, C.POINTER(cbdg_bounds)],
     "cbdg_moments_workspace_size": [_vp, _i32, _i32, _i32, C.POINTER(_sz)],
     "cbdg_chebyshev_moments": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp],
+    "cbdg_chebyshev_moments_static": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp],
     "cbdg_chebyshev_moments_nb": [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp],
     "cbdg_check_moments": [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _vp],
     "cbdg_bond_gap_update": [_vp, _i32, _i32, _i32, _i32, _i32, _i32, C.POINTER(cbdg_weights), _vp, _f64,
@@ -100,6 +101,8 @@ def load():
         fn.restype = C.c_int
     lib.cbdg_last_error.argtypes = []
     lib.cbdg_last_error.restype = C.c_char_p
+    lib.cbdg_static_scratch_bytes.argtypes = []
+    lib.cbdg_static_scratch_bytes.restype = C.c_size_t
     _lib = lib
     return lib
 
@@ -127,6 +130,7 @@ cbdg_op_destroy = _call("cbdg_op_destroy")
 cbdg_op_bounds = _call("cbdg_op_bounds")
 cbdg_moments_workspace_size = _call("cbdg_moments_workspace_size")
 cbdg_chebyshev_moments = _call("cbdg_chebyshev_moments")
+cbdg_chebyshev_moments_static = _call("cbdg_chebyshev_moments_static")
 cbdg_check_moments = _call("cbdg_check_moments")
 cbdg_sum_coefficients = _call("cbdg_sum_coefficients")
 cbdg_density = _call("cbdg_density")
@@ -144,3 +148,7 @@ cbdg_chebyshev_moments_backward = _call("cbdg_chebyshev_moments_backward")
 
 def cbdg_last_error() -> str:
     return load().cbdg_last_error().decode(errors="replace")
+
+
+def cbdg_static_scratch_bytes() -> int:
+    return int(load().cbdg_static_scratch_bytes())

@@ -1761,3 +1761,72 @@ extern "C" int cbdg_check_moments(const double *mu_ee, const void *mu_he, int64_
     CBDG_CHECK_LAUNCH("k_check");
     return CBDG_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Moments without a caller workspace, for callers that cannot allocate device
+// memory.  The workspace lives in a device array of fixed size that each GPU
+// holds for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress reports for the current device (the array's
+// name in host code is not a device address).
+#include <mutex>
+
+static __device__ __align__(256) unsigned char scratch[CBDG_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current).
+static int static_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(CBDG_EINVAL, "chebyshev_moments_static: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CBDG_EHIP, "chebyshev_moments_static: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CBDG_OK;
+}
+
+extern "C" size_t cbdg_static_scratch_bytes(void) { return (size_t)CBDG_STATIC_SCRATCH_BYTES; }
+
+extern "C" int cbdg_chebyshev_moments_static(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                                             int32_t N, int32_t tile, int32_t precision, int32_t algorithm,
+                                             double *mu_ee, void *mu_he, void *stream)
+{
+    clear_error();
+    if (!op) return fail(CBDG_EINVAL, "chebyshev_moments_static: op must not be NULL");
+    if (n_start < 0 || N < 1 || tile < 1)
+        return fail(CBDG_EINVAL, "chebyshev_moments_static: need n_start >= 0, N >= 1, tile >= 1");
+    if (precision != CBDG_FP64 && precision != CBDG_FP32_ACC64)
+        return fail(CBDG_EINVAL, "chebyshev_moments_static: unknown precision %d", precision);
+    int dev = -1;
+    CBDG_CHECK_HIP(hipGetDevice(&dev));
+    if (dev != op->device)
+        return fail(CBDG_EINVAL, "chebyshev_moments_static: the operator lives on device %d, the current device is %d",
+                    op->device, dev);
+    if (n_start == 0) return CBDG_OK;
+    size_t need = 0;
+    const int32_t eff = (int32_t)std::min<int64_t>(tile, n_start);
+    int rc = cbdg_moments_workspace_size(op, eff, precision, algorithm, &need);
+    if (rc) return rc;
+    if (need > (size_t)CBDG_STATIC_SCRATCH_BYTES)
+        return fail(CBDG_EINVAL,
+                    "chebyshev_moments_static: tiles of %d vectors need %zu bytes of workspace, more than the %zu "
+                    "of the static scratch array (use smaller tiles or cbdg_chebyshev_moments)",
+                    eff, need, (size_t)CBDG_STATIC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((rc = static_scratch(dev, &ws))) return rc;
+    // every buffer the recursion reads is written first within the call
+    // (tile buffers cleared per tile, bounding box, partial and run sums), so
+    // the previous call's contents need no clearing
+    return cbdg_chebyshev_moments(op, start_sites, n_start, N, tile, precision, algorithm, ws, need, mu_ee, mu_he,
+                                  stream);
+}
