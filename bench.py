@@ -244,11 +244,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 2 GiB device copy instead (HBM calibration)")
-    ap.add_argument("--form", choices=["scf-step", "complex", "adjoint", "scf", "paper"], default="scf-step",
+    ap.add_argument("--form", choices=["scf-step", "complex", "adjoint", "scf", "paper", "resident"],
+                    default="scf-step",
                     help="scf-step (default): iterations of the self-consistency loop of the 256x256 "
                          "workload; complex: 512x512 Peierls/d-wave LDOS workload; adjoint: 128x128 "
                          "gradients and Newton-Krylov; scf: a self-consistent solve of the 256x256 workload "
-                         "by a chosen method; paper: the paper's two example geometries")
+                         "by a chosen method; paper: the paper's two example geometries; resident: "
+                         "cache-resident persistent tiles vs the streaming path (128x128)")
     ap.add_argument("--scf-method", choices=["plain", "nk-fd", "anderson"], default="plain",
                     help="--form scf: plain mixing, Newton-Krylov with finite-difference products, "
                          "or Anderson mixing")
@@ -284,7 +286,8 @@ def main():
     if args.form != "scf-step":
         import bench_forms
         line = {"complex": bench_forms.complex_form, "adjoint": bench_forms.adjoint_form,
-                "scf": bench_forms.scf_form, "paper": bench_forms.paper_form}[args.form](args, dev)
+                "scf": bench_forms.scf_form, "paper": bench_forms.paper_form,
+                "resident": bench_forms.resident_form}[args.form](args, dev)
         print(json.dumps(line), flush=True)
         return
     N = 1024 if args.precision == "fp64" else 2048

@@ -382,6 +382,66 @@ def scf_form(args, dev):
     return line
 
 
+def resident_form(args, dev, tiles=(64, 128, 256)):
+    """The 128x128 differentiation workload's forward moments (16384 start
+    sites, N = 512, FP64 doubling) with every recursion step of a tile in one
+    persistent launch (tiles whose two buffers stay in the Infinity Cache),
+    beside the HBM-streaming path at the same tile sizes and at its default
+    1024-vector tiles.  Bytes: 3 vectors over the whole lattice per step for
+    the resident launch (it has no light cone), the minimum per launch for
+    the streaming path (bench.launch_bytes)."""
+    from bench import launch_bytes
+    w = W.config4()
+    N = w.N
+    op = P.Operator.from_workload(w, dev)
+    sites = torch.as_tensor(w.start_sites, device=dev)
+    n = sites.numel()
+    out = (torch.empty((n, N), dtype=torch.float64, device=dev), torch.empty((n, N), dtype=torch.float64, device=dev))
+    res = {"workload": "%s: 128x128, 64 impurities, N=%d, all %d start sites, FP64, moment doubling" % (w.name, N, n)}
+    stream = torch.cuda.current_stream()
+    ref = None
+    for tile in tiles:
+        ws = P.workspace(P.resident_workspace_bytes(op, tile), dev)
+        P.chebyshev_moments_resident(op, sites[:tile], N, tile, ws=ws, out=(out[0][:tile], out[1][:tile]))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.chebyshev_moments_resident(op, sites, N, tile, ws=ws, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        steps = N // 2
+        nbytes = 3.0 * steps * w.L2 * 16 * ((tile + 63) // 64 * 64) * (n // tile)
+        res["resident_tile%d" % tile] = {"seconds": t, "moments_per_s": n * N / t,
+                                         "vector_GBps": nbytes / t / 1e9,
+                                         "buffers_MiB": 2 * w.L2 * ((tile + 63) // 64 * 64) * 16 / 2 ** 20}
+        if ref is None:
+            ref = out[0].clone()
+        del ws
+        log("resident tiles of %d: %.3f s" % (tile, t))
+    res["resident_max_abs_diff_between_tilings"] = float((out[0] - ref).abs().max())
+    for tile in tiles + (1024,):
+        ws = P.workspace(P.moments_workspace_bytes(op, tile), dev)
+        P.chebyshev_moments(op, sites[:tile], N, tile, ws=ws, out=(out[0][:tile], out[1][:tile]))
+        torch.cuda.synchronize()
+        ev = []
+        for t0 in range(0, n, tile):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            P.chebyshev_moments(op, sites[t0:t0 + tile], N, tile, ws=ws, out=(out[0][t0:t0 + tile], out[1][t0:t0 + tile]))
+            e1.record(stream)
+            ev.append((e0, e1, min(tile, n - t0)))
+        torch.cuda.synchronize()
+        kern, nl, ms, moved, streamed = launch_bytes(ev, w.start_sites, tile, len(ev), w, N // 2, True, 8)
+        res["streaming_tile%d" % tile] = {"seconds": ms / 1e3, "moments_per_s": n * N / (ms / 1e3),
+                                          "kernel": kern, "min_bytes_GBps": moved / (ms / 1e3) / 1e9,
+                                          "effective_GBps": streamed / (ms / 1e3) / 1e9}
+        del ws
+        log("streaming tiles of %d: %.3f s" % (tile, ms / 1e3))
+    op.close()
+    return res
+
+
 def paper_form(args, dev):
     """The paper's two examples as synthetic workloads.
 

@@ -208,6 +208,41 @@ int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_sites, int64_
                            void *workspace, size_t workspace_bytes,
                            double *mu_ee, void *mu_he, void *stream);
 
+/* Bytes of workspace cbdg_chebyshev_moments_resident needs for tiles of
+ * `tile` vectors (host out): the tile's two vector buffers, the FP64 partial
+ * sums of 16 recursion steps and two control words.  EINVAL / EUNSUPPORTED
+ * as cbdg_chebyshev_moments_resident. */
+int cbdg_resident_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision, size_t *bytes);
+
+/*
+ * The moments of cbdg_chebyshev_moments by moment doubling, with every
+ * recursion step of a tile in one persistent (cooperative) launch, for tiles
+ * whose two vector buffers -- 2 * L2 * round_up(tile, 64) Nambu pairs, 16 B
+ * (FP64) or 8 B (FP32_ACC64) each -- fit in 200 MiB, so that they stay in the
+ * 256 MB Infinity Cache of the GPU: eq. (ref2) with the moments of eqs.
+ * (coeff1)/(coeff2), as the paper's closing remarks note the method needs
+ * only sparse matrix-vector products and little memory.  Steps are separated
+ * by a grid barrier with a bounded wait.
+ *   start_sites, n_start, N, precision, mu_ee, mu_he  as cbdg_chebyshev_moments
+ *   tile        1 .. 256 vectors per tile
+ *   spin_limit  polls of a grid barrier before the launch gives up (0: a
+ *               default of about a second); a barrier that gives up makes
+ *               every workgroup leave the kernel, and the call returns
+ *               CBDG_EHIP with the moments of that tile incomplete
+ *   workspace   >= cbdg_resident_workspace_size(op, min(tile, n_start),
+ *               precision) bytes
+ * Real operators with uniform hopping and on-site pairing only
+ * (EUNSUPPORTED otherwise); b must be 0 (EINVAL otherwise); EINVAL when the
+ * tile's vectors exceed 200 MiB.  The moments agree with
+ * cbdg_chebyshev_moments to rounding (the dot products are summed over other
+ * regions), with the same device-side bound check.  The call synchronises the
+ * stream once per tile to read the barrier's flag.
+ */
+int cbdg_chebyshev_moments_resident(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                                    int32_t N, int32_t tile, int32_t precision, int64_t spin_limit,
+                                    void *workspace, size_t workspace_bytes, double *mu_ee, void *mu_he,
+                                    void *stream);
+
 /* Size of the per-GPU device array cbdg_chebyshev_moments_static works in. */
 #define CBDG_STATIC_SCRATCH_BYTES (64u << 20)
 

@@ -18,7 +18,8 @@ from .api import (Operator, Bounds, weights, chebyshev_moments, check_moments,  
                   gap_update, ldos, gap_update_backward, ldos_backward,
                   chebyshev_moments_backward, moments_workspace_bytes,
                   backward_workspace_bytes, workspace, sum_coefficients, density, density_backward,
-                  chebyshev_moments_nb, bond_gap_update, bond_current)
+                  chebyshev_moments_nb, bond_gap_update, bond_current, chebyshev_moments_resident,
+                  resident_workspace_bytes)
 
 __all__ = [
     "CbdgError", "CBDG_FP64", "CBDG_FP32_ACC64", "CBDG_REAL", "CBDG_COMPLEX", "CBDG_BC_OPEN",
@@ -26,5 +27,5 @@ __all__ = [
     "gap_update", "ldos", "gap_update_backward", "ldos_backward", "chebyshev_moments_backward",
     "moments_workspace_bytes", "backward_workspace_bytes", "workspace", "CBDG_QTY_GAP",
     "CBDG_QTY_DENSITY", "sum_coefficients", "density", "density_backward", "chebyshev_moments_nb",
-    "bond_gap_update", "bond_current",
+    "bond_gap_update", "bond_current", "chebyshev_moments_resident", "resident_workspace_bytes",
 ]

@@ -62,6 +62,8 @@ SIGNATURES = {
     "cbdg_op_bounds": [_vp, C.POINTER(cbdg_bounds)],
     "cbdg_moments_workspace_size": [_vp, _i32, _i32, _i32, C.POINTER(_sz)],
     "cbdg_chebyshev_moments": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp],
+    "cbdg_resident_workspace_size": [_vp, _i32, _i32, C.POINTER(_sz)],
+    "cbdg_chebyshev_moments_resident": [_vp, _vp, _i64, _i32, _i32, _i32, _i64, _vp, _sz, _vp, _vp, _vp],
     "cbdg_chebyshev_moments_static": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp],
     "cbdg_chebyshev_moments_nb": [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp],
     "cbdg_check_moments": [_vp, _vp, _i64, _i32, _i32, _f64, _vp, _vp],
@@ -131,6 +133,8 @@ cbdg_op_bounds = _call("cbdg_op_bounds")
 cbdg_moments_workspace_size = _call("cbdg_moments_workspace_size")
 cbdg_chebyshev_moments = _call("cbdg_chebyshev_moments")
 cbdg_chebyshev_moments_static = _call("cbdg_chebyshev_moments_static")
+cbdg_resident_workspace_size = _call("cbdg_resident_workspace_size")
+cbdg_chebyshev_moments_resident = _call("cbdg_chebyshev_moments_resident")
 cbdg_check_moments = _call("cbdg_check_moments")
 cbdg_sum_coefficients = _call("cbdg_sum_coefficients")
 cbdg_density = _call("cbdg_density")

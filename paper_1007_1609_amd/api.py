@@ -168,6 +168,38 @@ def chebyshev_moments(op: Operator, sites: torch.Tensor, N: int, tile: int,
     return mu_ee, mu_he
 
 
+def resident_workspace_bytes(op: Operator, tile: int, precision: int = L.CBDG_FP64) -> int:
+    n = C.c_size_t()
+    L.cbdg_resident_workspace_size(op.handle, int(tile), int(precision), C.byref(n))
+    return n.value
+
+
+def chebyshev_moments_resident(op: Operator, sites: torch.Tensor, N: int, tile: int,
+                               precision: int = L.CBDG_FP64, ws: Optional[torch.Tensor] = None,
+                               out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None,
+                               spin_limit: int = 0):
+    """Moments by doubling with every recursion step of a tile in one
+    persistent launch (tiles of at most 256 vectors whose buffers fit the
+    Infinity Cache); mu_ee, mu_he [n, N] float64."""
+    n = int(sites.numel())
+    eff = max(1, min(int(tile), n))
+    need = resident_workspace_bytes(op, eff, precision)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, sites.device)
+    if out is None:
+        mu_ee = torch.empty((n, N), dtype=torch.float64, device=sites.device)
+        mu_he = torch.empty((n, N), dtype=torch.float64, device=sites.device)
+    else:
+        mu_ee, mu_he = out
+        _need(mu_ee, n * int(N), "mu_ee")
+        _need(mu_he, n * int(N), "mu_he")
+    L.cbdg_chebyshev_moments_resident(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N), int(tile),
+                                      int(precision), int(spin_limit), _ptr(ws, None, "workspace"), ws.numel(),
+                                      _ptr(mu_ee, torch.float64, "mu_ee"), _ptr(mu_he, torch.float64, "mu_he"),
+                                      _stream())
+    return mu_ee, mu_he
+
+
 def chebyshev_moments_nb(op: Operator, sites: torch.Tensor, N: int, tile: int,
                          precision: int = L.CBDG_FP64, ws: Optional[torch.Tensor] = None):
     """Direct moments plus the neighbour moments nb_ee, nb_he [n, 4, N]

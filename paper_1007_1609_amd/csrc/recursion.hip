@@ -1347,7 +1347,7 @@ __global__ void k_bound_moments(double *__restrict__ ee, double *__restrict__ he
     }
 }
 
-static int bound_moments(double *ee, double *he, int64_t n, bool ee_c, bool he_c, double lim, hipStream_t st)
+int bound_moments(double *ee, double *he, int64_t n, bool ee_c, bool he_c, double lim, hipStream_t st)
 {
     if (n <= 0) return CBDG_OK;
     hipLaunchKernelGGL(k_bound_moments, dim3((unsigned)std::min<int64_t>(ceil_div(n, kBlock), 2048)), dim3(kBlock),
@@ -1358,7 +1358,7 @@ static int bound_moments(double *ee, double *he, int64_t n, bool ee_c, bool he_c
 
 // Rounding allowance of the bound check: FP64 recursion vectors keep |mu| <= 1
 // to ~1e-13; FP32 vectors to a few 1e-6.
-static double moment_limit(bool f32) { return f32 ? 1.0 + 1e-4 : 1.0 + 1e-9; }
+double moment_limit(bool f32) { return f32 ? 1.0 + 1e-4 : 1.0 + 1e-9; }
 
 int run_step(const cbdg_op *op, int precision, StepArgs A, hipStream_t st)
 {

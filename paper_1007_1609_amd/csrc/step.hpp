@@ -61,6 +61,12 @@ int run_step2_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st);
 bool three_step_f64_real(const cbdg_op *op, int Bt);
 int run_step3_f64_real(const cbdg_op *op, StepArgs A, hipStream_t st);
 
+// Device-side bound check of n moment entries (ee_c / he_c: complex128
+// entries): a magnitude beyond lim or a non-finite value becomes NaN.
+int bound_moments(double *ee, double *he, int64_t n, bool ee_c, bool he_c, double lim, hipStream_t st);
+// Its limit: 1 plus the rounding allowance of FP64 or FP32 recursion vectors.
+double moment_limit(bool f32);
+
 // a_0 = |s_b,e> for the tile's vectors (FP64 real layout); writes mu_0 when
 // mu_ee is not null.
 int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, double *mu_ee, double *mu_he, int N,
