@@ -270,10 +270,10 @@ def adjoint_form(args, dev):
     sites = torch.as_tensor(w.start_sites, device=dev)
     wt = P.weights(a, b)
 
-    def forward_backward():
+    def forward_backward(ckpt=0):
         eps = torch.as_tensor(w.eps, device=dev).requires_grad_(True)
         delta = torch.as_tensor(w.delta, device=dev).requires_grad_(True)
-        mu_ee, mu_he = AG.moments(eps, delta, geom, sites, N, tile)
+        mu_ee, mu_he = AG.moments(eps, delta, geom, sites, N, tile, ckpt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         loss = AG.gap_map(mu_he, delta, w.U, wt).sum()
@@ -286,6 +286,11 @@ def adjoint_form(args, dev):
     d0 = torch.as_tensor(w.delta, device=dev)
     (_, _), t_fwd = _timed(lambda: AG.moments(eps0, d0, geom, sites, N, tile))
     g_sum, t_bwd = forward_backward()
+    # every forward vector stored (checkpoint stride 1: no segment
+    # recomputation, about 70 GB of workspace per 1024-vector tile)
+    forward_backward(1)
+    g1, t_bwd1 = forward_backward(1)
+    torch.cuda.empty_cache()
     # dLDOS(0)/dV at the centre site: one start vector
     s0 = w.notes["centre_site"]
     eps = torch.as_tensor(w.eps, device=dev).requires_grad_(True)
@@ -310,7 +315,9 @@ def adjoint_form(args, dev):
         return {"metric": METRIC, "value": n_moments / t_fwd, "unit": "moments/s", "n_gpus": 1,
                 "higher_is_better": True, "dtype": "f64", "data": "synthetic",
                 "config": {"workload": "%s: 128x128, N=%d, reverse pass only" % (w.name, N)},
-                "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse}
+                "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse,
+                "reverse_over_forward": t_bwd / t_fwd, "seconds_reverse_stride1": t_bwd1,
+                "reverse_stride1_over_forward": t_bwd1 / t_fwd}
     # self-consistency: plain mixing vs Newton-Krylov (both to 1e-6)
     op = P.Operator.from_workload(w, dev)
     r = scf.plain_mixing(op, w.U, d0, N, tile, tol=1e-6, max_iter=300)
@@ -336,6 +343,8 @@ def adjoint_form(args, dev):
                                    % (w.name, N, tile)},
             "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse,
             "reverse_over_forward": t_bwd / t_fwd, "seconds_dldos0_dV_centre": t_ldos,
+            "seconds_reverse_stride1": t_bwd1, "reverse_stride1_over_forward": t_bwd1 / t_fwd,
+            "stride1_max_abs_grad_diff": float((g1 - g_sum).abs().max()),
             "grad_norm_inf": float(g_sum.abs().max()), "scf": out}
 
 

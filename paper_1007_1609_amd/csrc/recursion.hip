@@ -69,6 +69,13 @@ namespace cbdg {
 #ifndef CBDG_LANE_PAD
 #define CBDG_LANE_PAD 0
 #endif
+// Unrolling of the three-step row loop.  FP32 (two waves per SIMD), one
+// 1024-vector tile at 256x256, N = 2048: 455.4 us per launch unrolled once,
+// 446.0 twice, 441.0 three times (241 / 252 VGPRs, bits unchanged); the FP64
+// loop is not unrolled by the compiler either way (782 us).
+#ifndef CBDG_U3
+#define CBDG_U3 3
+#endif
 
 
 // MODE 0: moments at the start site; 1: also the moment-doubling partial sums;
@@ -694,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step3(StepArgs A, const typenam
     [[maybe_unused]] P pn[PF3 ? X1 : 1];
     if constexpr (PF3) load_p2(p2, y0 - 2);
 
-#pragma unroll 1
+#pragma unroll CBDG_U3
     for (int r = y0 - 2; r <= y1 + 1; ++r) {
         uint32_t nm = 0;
         uint32_t rok;
