@@ -186,6 +186,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
     if constexpr (HAS2) load_own(l2, pc, y0, true);
     load_own(aprev, ac, y0, true);
 
+    // The (chunk, site) gradient partials of row y, read before the trip's
+    // prefetch loads: the loads complete in issue order, so reading them
+    // where they are updated would wait for the prefetch of the next rows.
+    double gold[W][2];
+    auto load_grad = [&](int y) {
+        if (lane == 0) {
+            const int64_t srow = (int64_t)y * Lx;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                gold[k][0] = gp[2 * (srow + x0 + k)];
+                gold[k][1] = gp[2 * (srow + x0 + k) + 1];
+            }
+        }
+    };
     auto compute_row = [&](int y) {
         const int64_t srow = (int64_t)y * Lx;
 #pragma unroll
@@ -223,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
             ge = wave_sum_f64(ge);
             gd = wave_sum_f64(gd);
             if (lane == 0) {
-                gp[2 * s] += A.cscale * ge;
-                gp[2 * s + 1] += A.cscale * gd;
+                gp[2 * s] = gold[k][0] + A.cscale * ge;
+                gp[2 * s + 1] = gold[k][1] + A.cscale * gd;
             }
         }
     };
@@ -233,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
 #pragma unroll 1
     for (int y = y0; y < y1 - 1; ++y) {
         uint32_t nm = 0, mm = 0;
+        load_grad(y);
         if constexpr (HAS1) nm = load_row(lam1, nx, y + 2);
         if constexpr (DBL) mm = load_row(am, mnx, y + 2);
         if constexpr (HAS2) load_own(l2, pn, y + 1, true);
@@ -251,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
 #pragma unroll
         for (int k = 0; k < W; ++k) { pc[k] = pn[k]; ac[k] = an[k]; }
     }
+    load_grad(y1 - 1);
     compute_row(y1 - 1);
 }
 
