@@ -73,6 +73,63 @@ struct AdjArgs {
     const double *d1;     // [Bt][2] start-site cotangents of mu_ee[1], mu_he[1] (doubling)
 };
 
+// Cotangent coefficients of one doubling step m for one vector:
+//   w_m = cA a_m + cP a_{m+1} + cQ (-a_{m+1,h}, a_{m+1,e})
+//       + cR a_{m-1} + cS (a_{m-1,h}, -a_{m-1,e}) + (we, wh) at the start site
+struct AdjCoef { double cA, cP, cQ, cR, cS, we, wh; };
+
+__device__ __forceinline__ AdjCoef adj_coef(const AdjArgs &A, int m, uint32_t b, bool active)
+{
+    AdjCoef c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int N = A.N;
+    const int64_t row = (int64_t)b * N;
+    auto gee = [&](int i) { return (active && A.dmu_ee && i >= 2 && i < N) ? A.dmu_ee[row + i] : 0.0; };
+    auto ghe = [&](int i) { return (active && A.dmu_he && i >= 2 && i < N) ? A.dmu_he[row + i] : 0.0; };
+    const double sg = (m & 1) ? -2.0 : 2.0;  // 2(-1)^m
+    c.cA = 4.0 * gee(2 * m);
+    c.cP = 2.0 * gee(2 * m + 1);
+    c.cQ = -sg * ghe(2 * m + 1);
+    if (m >= 2) { c.cR = 2.0 * gee(2 * m - 1); c.cS = sg * ghe(2 * m - 1); }
+    if (m == 1 && active) { c.we = A.d1[2 * b]; c.wh = A.d1[2 * b + 1]; }
+    return c;
+}
+
+// lam_n at one site from hl = (Ht lam_{n+1})(s), l2 = lam_{n+2}(s), the forward
+// vectors mk = a_n(s), ac = a_{n-1}(s), q = a_{n+1}(s) and the cotangent
+// (direct form: we, wh only).  The multiply-adds are written out and no other
+// contraction is allowed, so a site's rounding is fixed by this function and
+// not by how the compiler schedules the kernel around it.
+template <bool HAS1, bool HAS2, bool DBL, bool NXT>
+__device__ __forceinline__ Pair<double, false> adj_site(const Pair<double, false> &hl, const Pair<double, false> &l2,
+                                                        const Pair<double, false> &mk, const Pair<double, false> &ac,
+                                                        const Pair<double, false> &q, const AdjCoef &c, bool hit)
+{
+#pragma clang fp contract(off)
+    Pair<double, false> lam{0.0, 0.0};
+    if constexpr (HAS1) { lam.e = 2.0 * hl.e; lam.h = 2.0 * hl.h; }
+    if constexpr (HAS2) { lam.e = lam.e - l2.e; lam.h = lam.h - l2.h; }
+    if constexpr (DBL) {
+        lam.e = lam.e + __builtin_fma(c.cA, mk.e, __builtin_fma(c.cR, ac.e, c.cS * ac.h));
+        lam.h = lam.h + __builtin_fma(c.cA, mk.h, __builtin_fma(c.cR, ac.h, -(c.cS * ac.e)));
+    }
+    if constexpr (NXT) {
+        lam.e = lam.e + __builtin_fma(c.cP, q.e, -(c.cQ * q.h));
+        lam.h = lam.h + __builtin_fma(c.cP, q.h, c.cQ * q.e);
+    }
+    lam.e = lam.e + (hit ? c.we : 0.0);
+    lam.h = lam.h + (hit ? c.wh : 0.0);
+    return lam;
+}
+
+// The lane's terms of dL/deps and dL/dDelta at one site: lam_n . dHt a_{n-1}.
+__device__ __forceinline__ void adj_grad_terms(const Pair<double, false> &lam, const Pair<double, false> &ac, bool active,
+                                               double &ge, double &gd)
+{
+#pragma clang fp contract(off)
+    ge = active ? __builtin_fma(lam.e, ac.e, -(lam.h * ac.h)) : 0.0;
+    gd = active ? __builtin_fma(lam.e, ac.h, lam.h * ac.e) : 0.0;
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
 #pragma unroll
@@ -110,24 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
     S *lo = reinterpret_cast<S *>(A.out);
     const double th = A.th;
     const int my_site = active ? A.sites[b] : -1;
-    double we = 0.0, wh = 0.0;
-    // doubling: w_m = cA a_m + cP a_{m+1} + cQ (-a_{m+1,h}, a_{m+1,e})
-    //               + cR a_{m-1} + cS (a_{m-1,h}, -a_{m-1,e})
-    [[maybe_unused]] double cA = 0.0, cP = 0.0, cQ = 0.0, cR = 0.0, cS = 0.0;
+    AdjCoef cf{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if constexpr (DBL) {
-        const int m = A.n, N = A.N;
-        const int64_t row = (int64_t)b * N;
-        auto gee = [&](int i) { return (active && A.dmu_ee && i >= 2 && i < N) ? A.dmu_ee[row + i] : 0.0; };
-        auto ghe = [&](int i) { return (active && A.dmu_he && i >= 2 && i < N) ? A.dmu_he[row + i] : 0.0; };
-        const double sg = (m & 1) ? -2.0 : 2.0;  // 2(-1)^m
-        cA = 4.0 * gee(2 * m);
-        cP = 2.0 * gee(2 * m + 1);
-        cQ = -sg * ghe(2 * m + 1);
-        if (m >= 2) { cR = 2.0 * gee(2 * m - 1); cS = sg * ghe(2 * m - 1); }
-        if (m == 1 && active) { we = A.d1[2 * b]; wh = A.d1[2 * b + 1]; }
+        cf = adj_coef(A, A.n, b, active);
     } else {
-        we = (active && A.dmu_ee) ? A.dmu_ee[(int64_t)b * A.N + A.n] : 0.0;
-        wh = (active && A.dmu_he) ? A.dmu_he[(int64_t)b * A.N + A.n] : 0.0;
+        cf.we = (active && A.dmu_ee) ? A.dmu_ee[(int64_t)b * A.N + A.n] : 0.0;
+        cf.wh = (active && A.dmu_he) ? A.dmu_he[(int64_t)b * A.N + A.n] : 0.0;
     }
     const S *am = reinterpret_cast<const S *>(A.acur);
     double *gp = A.gpart + (int64_t)c64 * A.L2 * 2;
@@ -205,40 +250,25 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(AdjArgs A, const double2 *_
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const int64_t s = srow + x0 + k;
-            P lam = zero_pair<double, false>();
             [[maybe_unused]] OnSite<double> o;
             if constexpr (HAS1 || NXT) o = ons[s];
-            if constexpr (HAS1) {
-                const P yv = apply_uniform<double, false>(o, th, cur[k + 1], cur[k], cur[k + 2], up[k + 1], dn[k + 1]);
-                lam.e = 2.0 * yv.e;
-                lam.h = 2.0 * yv.h;
-            }
-            if constexpr (HAS2) {
-                lam.e -= pc[k].e;
-                lam.h -= pc[k].h;
-            }
-            if constexpr (DBL) {
-                const P &mk = mcur[k + 1];
-                lam.e += cA * mk.e + cR * ac[k].e + cS * ac[k].h;
-                lam.h += cA * mk.h + cR * ac[k].h - cS * ac[k].e;
-            }
+            P hl = zero_pair<double, false>(), q = zero_pair<double, false>();
+            if constexpr (HAS1) hl = apply_uniform<double, false>(o, th, cur[k + 1], cur[k], cur[k + 2], up[k + 1], dn[k + 1]);
             if constexpr (NXT) {
                 const P yq = apply_uniform<double, false>(o, th, mcur[k + 1], mcur[k], mcur[k + 2], mup[k + 1], mdn[k + 1]);
-                const P q = cheb_combine<double, false>(yq, ac[k], false);
-                lam.e += cP * q.e - cQ * q.h;
-                lam.h += cP * q.h + cQ * q.e;
+                q = cheb_combine<double, false>(yq, ac[k], false);
             }
-            const bool hit = s == my_site;
-            lam.e += hit ? we : 0.0;
-            lam.h += hit ? wh : 0.0;
+            [[maybe_unused]] const P mk = DBL ? mcur[k + 1] : zero_pair<double, false>();
+            const P lam = adj_site<HAS1, HAS2, DBL, NXT>(hl, HAS2 ? pc[k] : zero_pair<double, false>(), mk, ac[k], q,
+                                                         cf, s == my_site);
             st_nt<double, false>(lo + s * Bp + b, lam);
-            double ge = active ? (lam.e * ac[k].e - lam.h * ac[k].h) : 0.0;
-            double gd = active ? (lam.e * ac[k].h + lam.h * ac[k].e) : 0.0;
+            double ge, gd;
+            adj_grad_terms(lam, ac[k], active, ge, gd);
             ge = wave_sum_f64(ge);
             gd = wave_sum_f64(gd);
             if (lane == 0) {
-                gp[2 * s] = gold[k][0] + A.cscale * ge;
-                gp[2 * s + 1] = gold[k][1] + A.cscale * gd;
+                gp[2 * s] = __builtin_fma(A.cscale, ge, gold[k][0]);
+                gp[2 * s + 1] = __builtin_fma(A.cscale, gd, gold[k][1]);
             }
         }
     };
