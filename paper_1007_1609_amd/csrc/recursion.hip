@@ -1151,6 +1151,12 @@ static bool uses_two_step(const cbdg_op *op)
 // vectors 182.5 / 190.5, 128: 100.9 / 101.0, 256: 71.3 / 60.3, 1024: 62.4 /
 // 53.6; FP32 64: 350 / 386, 128: 184 / 202, 256: 118 / 107, 1024: 104 / 70.
 constexpr int kThreeStepMinVectors = 129;
+// Tiles of at least this many vectors take the vector-contiguous passes when
+// the lattice fits them.
+#ifndef CBDG_VC_MIN
+#define CBDG_VC_MIN 1
+#endif
+constexpr int kVcMinVectors = CBDG_VC_MIN;
 #ifndef CBDG_YS3_F32
 #define CBDG_YS3_F32 128
 #endif
@@ -1454,16 +1460,92 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
     double *part = reinterpret_cast<double *>(cone) + kConeDoubles;
     double *part_b = part + (doubling ? Rmax * K * Bp_max : 0);
     double *part_c = part_b + (doubling ? Rmax * K * Bp_max : 0);
-    double *part2 = part_c + (doubling ? Rmax * K * Bp_max : 0);
+    double *part2 = part + (doubling ? kMaxPassSteps * Rmax * K * Bp_max : 0);
     const void *onsite = std::is_same<T, double>::value ? (const void *)op->onsite64 : (const void *)op->onsite32;
     const void *bonds = std::is_same<T, double>::value ? op->bonds64 : op->bonds32;
     const int he_mult = C ? 2 : 1;
+    const int64_t pstride = Rmax * K * Bp_max, ostride = (int64_t)kMaxGroups * K * Bp_max;
+    // moments 2m-1, 2m for the steps m = n .. n+ns-1 of one launch, whose
+    // partials sit pstride doubles apart from `part` on
+    auto reduce = [&](int64_t regions, int n, int ns, int Bt, int64_t Bp, double *mee, double *mhe) -> int {
+        int64_t per = 0, groups = 0;
+        doubling_groups(regions, &per, &groups);
+        hipLaunchKernelGGL((k_doubling_groups<C>),
+                           dim3((unsigned)ceil_div(Bt, kBlock), (unsigned)groups, (unsigned)ns),
+                           dim3(kBlock), 0, st, part, regions, per, Bp, Bt, part2, pstride, ostride);
+        CBDG_CHECK_LAUNCH("k_doubling_groups");
+        hipLaunchKernelGGL((k_doubling_reduce<C>), dim3((unsigned)ceil_div(Bt, kWave), (unsigned)ns),
+                           dim3(kRedWaves * kWave), 0, st, part2, groups, Bp, Bt, n, N, mee, mhe, ostride);
+        CBDG_CHECK_LAUNCH("k_doubling_reduce");
+        return CBDG_OK;
+    };
+    // Vector-contiguous passes (real uniform operators, doubling, Lx = 64 W):
+    // the same four buffers, vector b from pair b * L2 on; their packed
+    // coefficients follow the run sums.
+    void *vc_coef = part2 + kMaxPassSteps * (int64_t)kMaxGroups * K * Bp_max;
+    constexpr bool f32 = std::is_same<T, float>::value;
+    auto vc_tile = [&](int Bt) -> bool {
+        return !C && !op->general && doubling && !nb_ee && two && vc_width(op->Lx, f32) > 0 && Bt >= kVcMinVectors;
+    };
+    auto run_tile_vc = [&](int Bt, int64_t Bp, const int32_t *ts, double *mee, double *mhe) -> int {
+        using SR = typename Storage<T, false>::type;
+        const int64_t nz = (int64_t)Bt * L2;
+        const unsigned zgrid = (unsigned)std::min<int64_t>(ceil_div(nz, kBlock), 8192);
+        for (int i = 0; i < 4; ++i) {
+            hipLaunchKernelGGL((k_zero<T, false>), dim3(zgrid), dim3(kBlock), 0, st, reinterpret_cast<SR *>(buf[i]), nz);
+            CBDG_CHECK_LAUNCH("k_zero");
+        }
+        int rc = launch_vc_seed(buf[0], L2, op->Lx, f32, Bt, L2, ts, mee, mhe, N, st);
+        if (rc) return rc;
+        VcArgs V{};
+        V.coef = vc_coef;
+        V.th = op->t / op->bounds.a;
+        V.Lx = op->Lx; V.Ly = op->Ly; V.bcx = op->bc_x; V.bcy = op->bc_y;
+        V.Dv = L2; V.Bt = Bt; V.Bp = (int)Bp; V.N = N;
+        V.sites = ts; V.mu_ee = mee; V.mu_he = mhe;
+        const int KS = vc_steps(f32);
+        const int segs1 = (int)std::min<int64_t>(vc_segments(op->Ly, Bt, 1), Rmax);
+        const int segsK = (int)std::min<int64_t>(vc_segments(op->Ly, Bt, KS), Rmax);
+        const int n_steps = N / 2;
+        S *P2 = buf[0], *P1 = buf[1], *Q0 = buf[2], *Q1 = buf[3];
+        V.part = part; V.pstride = pstride;
+        V.n = 1; V.a1 = P2; V.a2 = P2; V.out = P1; V.n_segs = segs1;
+        if ((rc = launch_vc(V, 1, f32, st)) || (rc = reduce(segs1, 1, 1, Bt, Bp, mee, mhe))) return rc;
+        int n = 2;
+        V.n_segs = segsK;
+        for (; n + KS - 1 <= n_steps; n += KS) {
+            V.n = n; V.a2 = P2; V.a1 = P1; V.out = Q0; V.out2 = Q1;
+            if ((rc = launch_vc(V, KS, f32, st)) || (rc = reduce(segsK, n, KS, Bt, Bp, mee, mhe))) return rc;
+            std::swap(P2, Q0);
+            std::swap(P1, Q1);
+        }
+        V.n_segs = segs1;
+        for (; n <= n_steps; ++n) {
+            V.n = n; V.a1 = P1; V.a2 = P2; V.out = P2;
+            if ((rc = launch_vc(V, 1, f32, st)) || (rc = reduce(segs1, n, 1, Bt, Bp, mee, mhe))) return rc;
+            std::swap(P1, P2);
+        }
+        return CBDG_OK;
+    };
+    if (n_start > 0 && vc_tile((int)std::min<int64_t>(tile, n_start))) {
+        int rc = launch_vc_coef(onsite, vc_coef, op->Lx, f32, L2, st);
+        if (rc) return rc;
+    }
     for (int64_t t0 = 0; t0 < n_start; t0 += tile) {
         const int Bt = (int)std::min<int64_t>(tile, n_start - t0);
         const int64_t Bp = lane_stride(Bt);
         double *mee = mu_ee + t0 * N;
         double *mhe = mu_he + t0 * N * he_mult;
         const int32_t *ts = sites + t0;
+        if constexpr (!C) {
+            if (vc_tile(Bt)) {
+                int rc = run_tile_vc(Bt, Bp, ts, mee, mhe);
+                if (rc) return rc;
+                if ((rc = bound_moments(mee, mhe, (int64_t)Bt * N, false, false, moment_limit(std::is_same<T, float>::value), st)))
+                    return rc;
+                continue;
+            }
+        }
         const int64_t nz = L2 * Bp;
         const unsigned zgrid = (unsigned)std::min<int64_t>(ceil_div(nz, kBlock), 8192);
         for (int i = 0; i < nbuf; ++i) {
@@ -1504,21 +1586,6 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             const Shape sh3 = choose_shape3<T>(op->Lx, op->Ly, chunks);
             regions3 = (int64_t)sh3.n_strips * sh3.n_segs;
         }
-        // moments 2m-1, 2m for the steps m = n .. n+ns-1 of one launch, whose
-        // partials sit Rmax*K*Bp_max apart from `part` on
-        const int64_t pstride = Rmax * K * Bp_max, ostride = (int64_t)kMaxGroups * K * Bp_max;
-        auto reduce = [&](int64_t regions, int n, int ns) -> int {
-            int64_t per = 0, groups = 0;
-            doubling_groups(regions, &per, &groups);
-            hipLaunchKernelGGL((k_doubling_groups<C>),
-                               dim3((unsigned)ceil_div(Bt, kBlock), (unsigned)groups, (unsigned)ns),
-                               dim3(kBlock), 0, st, part, regions, per, Bp, Bt, part2, pstride, ostride);
-            CBDG_CHECK_LAUNCH("k_doubling_groups");
-            hipLaunchKernelGGL((k_doubling_reduce<C>), dim3((unsigned)ceil_div(Bt, kWave), (unsigned)ns),
-                               dim3(kRedWaves * kWave), 0, st, part2, groups, Bp, Bt, n, N, mee, mhe, ostride);
-            CBDG_CHECK_LAUNCH("k_doubling_reduce");
-            return CBDG_OK;
-        };
         // P2 holds a_{n-2}, P1 a_{n-1}; Q0, Q1 are free (two-step passes)
         S *P2 = buf[0], *P1 = buf[1], *Q0 = buf[2], *Q1 = buf[3];
         int n = 1;
@@ -1532,7 +1599,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             A.mu_ee = mee;
             int rc = op->general ? launch_step<T, C, true>(A, st) : launch_step<T, C, false>(A, st);
             if (rc) return rc;
-            if (doubling && (rc = reduce(regions1, 1, 1))) return rc;
+            if (doubling && (rc = reduce(regions1, 1, 1, Bt, Bp, mee, mhe))) return rc;
             n = 2;
         }
         A.first = 0;
@@ -1549,7 +1616,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
                 A.part_c = doubling ? part_c : nullptr;
                 int rc = launch_step3<T>(A, st);
                 if (rc) return rc;
-                if (doubling && (rc = reduce(regions3, n, 3))) return rc;
+                if (doubling && (rc = reduce(regions3, n, 3, Bt, Bp, mee, mhe))) return rc;
                 std::swap(P2, Q0);
                 std::swap(P1, Q1);
                 n += 3;
@@ -1572,7 +1639,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             else rc = launch_step2<T, false, false>(A, st);
 #endif
             if (rc) return rc;
-            if (doubling && (rc = reduce(regions2, n, 2))) return rc;
+            if (doubling && (rc = reduce(regions2, n, 2, Bt, Bp, mee, mhe))) return rc;
             std::swap(P2, Q0);
             std::swap(P1, Q1);
             n += 2;
@@ -1585,7 +1652,7 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             A.part = doubling ? part : nullptr;
             int rc = op->general ? launch_step<T, C, true>(A, st) : launch_step<T, C, false>(A, st);
             if (rc) return rc;
-            if (doubling && (rc = reduce(regions1, n, 1))) return rc;
+            if (doubling && (rc = reduce(regions1, n, 1, Bt, Bp, mee, mhe))) return rc;
             std::swap(P1, P2);
         }
         const double lim = moment_limit(std::is_same<T, float>::value);
@@ -1654,9 +1721,17 @@ static int64_t doubling_partial_bytes(const cbdg_op *op, int tile, int precision
         R = cplx ? std::max(max_regions<float, true>(op->Lx, op->Ly, tile), two ? max_regions2<float, true>(op->Lx, op->Ly, tile) : 0)
                  : std::max({max_regions<float, false>(op->Lx, op->Ly, tile), two ? max_regions2<float, false>(op->Lx, op->Ly, tile) : 0,
                              three ? max_regions3<float>(op->Lx, op->Ly, tile) : 0});
-    // partials of up to three steps, then run sums of up to three steps at a
-    // stride of kMaxGroups runs
-    return (3 * R + 3 * (int64_t)kMaxGroups) * K * lane_stride(tile) * (int64_t)sizeof(double);
+    // partials of up to kMaxPassSteps steps, then their run sums at a stride
+    // of kMaxGroups runs
+    return kMaxPassSteps * (R + (int64_t)kMaxGroups) * K * lane_stride(tile) * (int64_t)sizeof(double);
+}
+
+// Packed coefficients of the vector-contiguous passes (operators they run on)
+static size_t vc_coef_bytes(const cbdg_op *op, int precision)
+{
+    const bool f32 = precision != CBDG_FP64;
+    if (op->scalar != CBDG_REAL || op->general || !uses_two_step(op) || !vc_width(op->Lx, f32)) return 0;
+    return (size_t)op->L2 * 2 * (f32 ? sizeof(float) : sizeof(double));
 }
 
 static size_t tile_buffer_bytes(const cbdg_op *op, int64_t tile, int precision)
@@ -1678,7 +1753,7 @@ extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int3
     int rc = resolve_algorithm(op, algorithm, 3, "moments_workspace_size", &doubling);
     if (rc) return rc;
     *bytes = tile_buffer_bytes(op, tile, precision) + kConeDoubles * sizeof(double);
-    if (doubling) *bytes += (size_t)doubling_partial_bytes(op, tile, precision);
+    if (doubling) *bytes += (size_t)doubling_partial_bytes(op, tile, precision) + vc_coef_bytes(op, precision);
     return CBDG_OK;
 }
 
@@ -1702,7 +1777,7 @@ extern "C" int cbdg_chebyshev_moments(const cbdg_op *op, const int32_t *start_si
         return fail(CBDG_EINVAL, "chebyshev_moments: start_sites, mu_ee, mu_he and workspace must not be NULL");
     const int64_t eff_tile = std::min<int64_t>(tile, n_start);
     size_t need = tile_buffer_bytes(op, eff_tile, precision) + kConeDoubles * sizeof(double);
-    if (doubling) need += (size_t)doubling_partial_bytes(op, (int)eff_tile, precision);
+    if (doubling) need += (size_t)doubling_partial_bytes(op, (int)eff_tile, precision) + vc_coef_bytes(op, precision);
     if (workspace_bytes < need)
         return fail(CBDG_EINVAL, "chebyshev_moments: workspace of %zu bytes is smaller than the %zu needed",
                     workspace_bytes, need);

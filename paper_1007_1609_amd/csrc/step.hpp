@@ -67,6 +67,46 @@ int bound_moments(double *ee, double *he, int64_t n, bool ee_c, bool he_c, doubl
 // Its limit: 1 plus the rounding allowance of FP64 or FP32 recursion vectors.
 double moment_limit(bool f32);
 
+// Most steps one pass of any kind takes (partials and run sums are sized for it).
+constexpr int kMaxPassSteps = 8;
+
+// Passes over a tile stored vector-contiguous (vector b in the pairs
+// b*Dv .. b*Dv + L2 - 1, row after row, column x = lW + k of a row at k*64 + l
+// for W = Lx/64; real operators with uniform hopping, moment doubling): one
+// wavefront per vector and row segment, each vector clipped to its own light
+// cone.  A pass of `steps` = 1 writes a_n (A.out, may alias A.a2; n = 1: a_1 =
+// Ht a_0 and moment 1) and the partials of step n; `steps` = K = vc_steps()
+// writes a_{n+K-2} (A.out) and a_{n+K-1} (A.out2) from a_{n-2} (A.a2) and
+// a_{n-1} (A.a1) and the partials of steps n .. n+K-1 ([n_segs][3][Bp] each).
+struct VcArgs {
+    const void *a1, *a2;
+    void *out, *out2;
+    const void *coef;    // packed (de, Delta/a) per site, in the passes' row layout
+    double th;           // t/a
+    int Lx, Ly, bcx, bcy;
+    int64_t Dv;          // pairs per vector
+    int Bt, Bp;          // vectors; lane stride of the partials
+    int n, N;
+    int n_segs, nblocks;
+    const int32_t *sites;
+    double *part;        // partials of step n + j at part + j * pstride
+    int64_t pstride;
+    double *mu_ee, *mu_he;  // first step: moment 1 of each row
+};
+// Lanes per row: a vector-contiguous pass needs Lx = 64 W with W in the
+// instantiated set; 0 when the lattice does not fit.
+int vc_width(int Lx, bool f32);
+// Row segments per vector of a pass over a tile of Bt vectors.
+int vc_segments(int Ly, int Bt, int steps);
+int launch_vc(const VcArgs &A, int steps, bool f32, hipStream_t st);
+// Steps of one multi-step vector-contiguous pass (3 .. kMaxPassSteps).
+int vc_steps(bool f32);
+// a_0 and the zeroth moments of a tile (buffer zeroed beforehand)
+int launch_vc_seed(void *a0, int64_t Dv, int Lx, bool f32, int Bt, int64_t L2, const int32_t *sites, double *mu_ee,
+                   double *mu_he, int N, hipStream_t st);
+// the packed coefficients (L2 pairs of the recursion's type) from the operator's
+int launch_vc_coef(const void *onsite, void *coef, int Lx, bool f32, int64_t L2, hipStream_t st);
+
 // a_0 = |s_b,e> for the tile's vectors (FP64 real layout); writes mu_0 when
 // mu_ee is not null.
 int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, double *mu_ee, double *mu_he, int N,

@@ -1,0 +1,689 @@
+// Chebyshev recursion of eq. (ref2) over a tile stored vector-contiguous,
+// for real operators with uniform hopping and moment doubling.
+//
+// Vector b occupies the pairs b*Dv .. b*Dv + L2 - 1, one row after the
+// other.  A wavefront holds one vector and one segment of rows; lane l owns
+// the W = Lx/64 neighbouring columns lW .. lW+W-1 of every row.  Inside a row
+// the pairs are ordered so that every load and store instruction of a
+// wavefront moves one contiguous 1 KB block (16 bytes per lane; pair_pos).  The x-neighbours of a lane's outer columns are
+// the outer columns of lanes l-1 and l+1, moved across the wavefront by DPP
+// wave shifts (rotations for periodic x).  Against the vector-major passes
+// (lanes = vectors, strips widened by the halo of every fused step):
+//   - a three-step pass computes the intermediate vectors a_n and a_{n+1}
+//     once per site; only the two rows at each end of a row segment are
+//     computed twice;
+//   - a lane holds W pairs per row instead of W + 6, so the FP64 three-step
+//     pass runs two wavefronts per SIMD;
+//   - a vector is clipped to its own light cone: a_n vanishes outside the
+//     diamond |x - x_b| + |y - y_b| <= n around its start site, rows outside
+//     it are skipped, and lanes outside it neither read nor write (their
+//     buffer offsets are pushed past the buffer-resource range, where loads
+//     return zero and stores are dropped);
+//   - the per-site coefficients (de, Delta/a) are vector loads from a packed
+//     copy in the same row layout (L1/L2 hits: every vector reads the same
+//     copy) instead of wave-uniform scalar loads; with b = 0 (the doubling
+//     identities need it) the hole diagonal is exactly -de.
+// Every site's value is computed by the same apply_uniform/cheb_combine
+// arithmetic as the vector-major kernels, so the vectors are bitwise the
+// same; the doubling partials are summed in another (fixed) order.
+//
+// Buffers outside the light cones hold zeros: the tile's buffers are zeroed
+// before the first step, and a pass that writes a vector into a buffer
+// covers the whole cone of the vector that buffer held before (an earlier
+// step, a smaller diamond).
+#include "step.hpp"
+
+#include <algorithm>
+
+namespace cbdg {
+
+namespace {
+
+#ifndef CBDG_VC_WG
+#define CBDG_VC_WG 4
+#endif
+constexpr int kVcWaves = CBDG_VC_WG;       // vectors per workgroup
+constexpr int kVcBlock = kVcWaves * kWave;
+constexpr unsigned kOut = 0x80000000u;     // a byte offset past every buffer range
+constexpr int kRsrcWord3 = 0x00020000;     // gfx9 buffer descriptor: 32-bit data format
+
+// DPP controls of the whole-wavefront shifts by one lane
+constexpr int kShl1 = 0x130;  // lane i <- lane i+1 (lane 63 <- 0)
+constexpr int kRol1 = 0x134;  // lane i <- lane i+1 (lane 63 <- lane 0)
+constexpr int kShr1 = 0x138;  // lane i <- lane i-1 (lane 0 <- 0)
+constexpr int kRor1 = 0x13C;  // lane i <- lane i-1 (lane 0 <- lane 63)
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ Pair<T, false> dpp_pair(const Pair<T, false> &p)
+{
+    return Pair<T, false>{dpp<CTRL>(p.e), dpp<CTRL>(p.h)};
+}
+
+typedef unsigned U4 __attribute__((ext_vector_type(4)));
+typedef unsigned U2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const void *base, int64_t b, int64_t Dv)
+{
+    const char *p = reinterpret_cast<const char *>(base) + b * Dv * (int64_t)(2 * sizeof(T));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)(Dv * 2 * sizeof(T)), kRsrcWord3);
+}
+
+// Every access moves 16 bytes per lane: one FP64 pair or two FP32 pairs
+// (kPer pairs).  Inside a row, chunk j of lane l (its pairs k = j*kPer ..
+// j*kPer + kPer - 1) sits at (j*64 + l)*kPer, so the j-th chunks of all lanes
+// are one contiguous 1 KB block.
+template <typename T> constexpr int kPer = 16 / (2 * (int)sizeof(T));
+template <typename T> __host__ __device__ constexpr int pair_pos(int lane, int k)
+{
+    return ((k / kPer<T>) * kWave + lane) * kPer<T> + k % kPer<T>;
+}
+
+// Cache policy of the vector streams: nontemporal (2) for FP64, where each
+// row of a vector is read or written once per pass and the streams stay out
+// of the caches' way (FP64, 256x256, one 1024-vector tile: 107.2 -> 99.3 ms);
+// FP32 runs faster with ordinary accesses (136.2 ms against 160.9).
+#ifndef CBDG_VC_NT_F64
+#define CBDG_VC_NT_F64 2
+#endif
+#ifndef CBDG_VC_NT_F32
+#define CBDG_VC_NT_F32 0
+#endif
+template <typename T> constexpr int kAux = sizeof(T) == 8 ? CBDG_VC_NT_F64 : CBDG_VC_NT_F32;
+
+// the chunk of kPer pairs at byte offset off
+template <typename T>
+__device__ __forceinline__ void bld(__amdgpu_buffer_rsrc_t r, unsigned off, Pair<T, false> *p)
+{
+    const U4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kAux<T>);
+    if constexpr (sizeof(T) == 8) {
+        p[0].e = __hiloint2double((int)v[1], (int)v[0]);
+        p[0].h = __hiloint2double((int)v[3], (int)v[2]);
+    } else {
+        p[0].e = __uint_as_float(v[0]); p[0].h = __uint_as_float(v[1]);
+        p[1].e = __uint_as_float(v[2]); p[1].h = __uint_as_float(v[3]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned off, const Pair<T, false> *p)
+{
+    U4 v;
+    if constexpr (sizeof(T) == 8) {
+        v = U4{(unsigned)__double2loint(p[0].e), (unsigned)__double2hiint(p[0].e), (unsigned)__double2loint(p[0].h),
+               (unsigned)__double2hiint(p[0].h)};
+    } else {
+        v = U4{__float_as_uint(p[0].e), __float_as_uint(p[0].h), __float_as_uint(p[1].e), __float_as_uint(p[1].h)};
+    }
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kAux<T>);
+}
+
+// Geometry of one wavefront: its vector's start site and its row segment.
+// Rows are virtual (periodic y: taken modulo Ly), so a segment with its halo
+// rows is always a run of consecutive integers.
+template <bool BCX, bool BCY>
+struct VcGeo {
+    int Lx, Ly;
+    int xi, yi;  // start site
+    int lo;      // the lane's first column
+    int lane;
+
+    __device__ int dy(int v) const
+    {
+        int d = v - yi;
+        if constexpr (BCY) {
+            d %= Ly;
+            if (d < 0) d += Ly;
+            return min(d, Ly - d);
+        }
+        return d < 0 ? -d : d;
+    }
+    __device__ bool in_lattice(int v) const { return BCY || (v >= 0 && v < Ly); }
+    __device__ int phys(int v) const
+    {
+        if constexpr (!BCY) return v;
+        const int r = v % Ly;
+        return r < 0 ? r + Ly : r;
+    }
+    // byte offset of the lane's first pair in row v of a vector that vanishes
+    // outside the diamond of radius R, or past the range where it vanishes
+    // (a select on the computed offset, so no lane branches)
+    template <typename T, int W>
+    __device__ unsigned offset(int v, int R) const
+    {
+        const int rr = R - dy(v);
+        const unsigned at = (unsigned)((phys(v) * Lx + lane * kPer<T>) * (int)(2 * sizeof(T)));
+        bool ok = in_lattice(v) & (rr >= 0);
+        if constexpr (!BCX) ok = ok & (lo <= xi + rr) & (lo + W - 1 >= xi - rr);
+        const unsigned keep = 0u - (unsigned)ok;
+        return (at & keep) | (kOut & ~keep);
+    }
+    // the lane's first packed coefficient pair of row v (row 0 for rows
+    // outside an open lattice, whose results are masked)
+    template <typename T>
+    __device__ int64_t coef_row(int v) const { return (int64_t)(in_lattice(v) ? phys(v) : 0) * Lx + lane * kPer<T>; }
+};
+
+template <typename T, int W>
+__device__ __forceinline__ void load_row(__amdgpu_buffer_rsrc_t r, unsigned off, Pair<T, false> *out)
+{
+#pragma unroll
+    for (int j = 0; j < W / kPer<T>; ++j) bld<T>(r, off + j * (unsigned)(kWave * 16), out + j * kPer<T>);
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void store_row(__amdgpu_buffer_rsrc_t r, unsigned off, const Pair<T, false> *v)
+{
+#pragma unroll
+    for (int j = 0; j < W / kPer<T>; ++j) bst<T>(r, off + j * (unsigned)(kWave * 16), v + j * kPer<T>);
+}
+
+// (de, Delta/a) of the lane's W sites of one row, 16 bytes per load
+template <typename T, int W>
+__device__ __forceinline__ void load_coef(const typename Storage<T, false>::type *pc, int64_t at,
+                                          typename Storage<T, false>::type *o)
+{
+    using S = typename Storage<T, false>::type;
+#pragma unroll
+    for (int j = 0; j < W / kPer<T>; ++j) {
+        if constexpr (sizeof(T) == 8) {
+            o[j] = pc[at + j * kWave];
+        } else {
+            const float4 v = *reinterpret_cast<const float4 *>(pc + at + j * kWave * 2);
+            o[2 * j] = S{v.x, v.y};
+            o[2 * j + 1] = S{v.z, v.w};
+        }
+    }
+}
+
+// Ht applied to row `c` (rows `d` below and `u` above), x-halo across lanes
+template <typename T, int W, bool BCX>
+__device__ __forceinline__ void apply_row(const typename Storage<T, false>::type *cf, T th, const Pair<T, false> *c,
+                                          const Pair<T, false> *d, const Pair<T, false> *u, Pair<T, false> *y)
+{
+    const Pair<T, false> hl = dpp_pair<BCX ? kRor1 : kShr1>(c[W - 1]);
+    const Pair<T, false> hr = dpp_pair<BCX ? kRol1 : kShl1>(c[0]);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const OnSite<T> o{cf[k].x, -cf[k].x, cf[k].y, T(0)};
+        y[k] = apply_uniform<T, false>(o, th, c[k], k > 0 ? c[k - 1] : hl, k < W - 1 ? c[k + 1] : hr, d[k], u[k]);
+    }
+}
+
+// <v|v>, <v|c> and B(v, c) of one site added to the partial sums, as two
+// fused multiply-adds each (no other contraction: the sums do not depend on
+// how the compiler schedules a pass)
+__device__ __forceinline__ void dots3(double *acc, double e, double h, double ce, double ch)
+{
+    acc[0] = __builtin_fma(h, h, __builtin_fma(e, e, acc[0]));
+    acc[1] = __builtin_fma(h, ch, __builtin_fma(e, ce, acc[1]));
+    acc[2] = __builtin_fma(-h, ce, __builtin_fma(e, ch, acc[2]));
+}
+
+// Sum over the wavefront in a fixed order (the same butterfly in every lane);
+// lane 0 stores its result.
+template <int K>
+__device__ __forceinline__ void wave_sum(double *d)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) d[k] += __shfl_xor(d[k], off, kWave);
+    }
+}
+
+// Common prologue: the wavefront's vector, start site and row segment for a
+// pass whose last step has light-cone radius m.  Returns false when the
+// wavefront has nothing to compute (its partials are written as zeros then,
+// in `nparts` arrays).
+template <bool BCX, bool BCY>
+struct VcWave {
+    int b, seg, lane, y0, y1;
+    VcGeo<BCX, BCY> g;
+};
+
+template <bool BCX, bool BCY>
+__device__ __forceinline__ bool vc_wave(const VcArgs &A, int m, int nparts, VcWave<BCX, BCY> &w)
+{
+    const int lb = xcd_remap(blockIdx.x, A.nblocks);
+    w.seg = lb % A.n_segs;
+    const int grp = lb / A.n_segs;
+    w.lane = threadIdx.x % kWave;
+    w.b = grp * kVcWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (w.b >= A.Bt) return false;
+    const int Lx = A.Lx, Ly = A.Ly;
+    const int si = A.sites[w.b];
+    int ylo = 0, yhi = -1;
+    if (si >= 0 && si < Lx * Ly) {
+        w.g.yi = si / Lx;
+        w.g.xi = si - w.g.yi * Lx;
+        if constexpr (BCY) {
+            if (2 * m + 1 >= Ly) { ylo = 0; yhi = Ly - 1; }
+            else { ylo = w.g.yi - m; yhi = w.g.yi + m; }
+        } else {
+            ylo = max(0, w.g.yi - m);
+            yhi = min(Ly - 1, w.g.yi + m);
+        }
+    }
+    const int per = max(4, (yhi - ylo + 1 + A.n_segs - 1) / A.n_segs);
+    w.y0 = ylo + w.seg * per;
+    w.y1 = min(w.y0 + per, yhi + 1);
+    if (w.y0 >= w.y1) {
+        if (w.lane < 3 * nparts)
+            A.part[(w.lane / 3) * A.pstride + ((int64_t)w.seg * 3 + w.lane % 3) * A.Bp + w.b] = 0.0;
+        return false;
+    }
+    w.g.Lx = Lx; w.g.Ly = Ly;
+    return true;
+}
+
+}  // namespace
+
+// One step: a_n (FIRST: a_1 = Ht a_0 and moment 1) and the doubling partials
+// <a_n|a_n>, <a_n|a_{n-1}>, B(a_n, a_{n-1}) of the wavefront's rows.  Each
+// trip issues the coefficient loads of its row before the loads of the rows
+// the next trip needs, so waiting for the former leaves the latter in flight.
+template <typename T, int W, bool BCX, bool BCY, bool FIRST>
+__global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
+{
+    using P = Pair<T, false>;
+    using S = typename Storage<T, false>::type;
+    VcWave<BCX, BCY> w;
+    const int n = A.n;
+    if (!vc_wave(A, n, 1, w)) return;
+    w.g.lo = w.lane * W;
+    w.g.lane = w.lane;
+    const auto &g = w.g;
+    const auto r1 = vec_rsrc<T>(A.a1, w.b, A.Dv);
+    const auto r2 = vec_rsrc<T>(A.a2, w.b, A.Dv);
+    const auto ro = vec_rsrc<T>(A.out, w.b, A.Dv);
+    const S *pc = reinterpret_cast<const S *>(A.coef);
+    const T th = T(A.th);
+    const int y0 = w.y0, y1 = w.y1;
+
+    P w0[W], w1[W], w2[W], nx[W], p2[W], pn[W], v[W];
+    S c0[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) p2[k] = pn[k] = zero_pair<T, false>();
+    load_row<T, W>(r1, g.template offset<T, W>(y0 - 1, n - 1), w0);
+    load_row<T, W>(r1, g.template offset<T, W>(y0, n - 1), w1);
+    load_row<T, W>(r1, g.template offset<T, W>(y0 + 1, n - 1), w2);
+    if constexpr (!FIRST) load_row<T, W>(r2, g.template offset<T, W>(y0, n - 2), p2);
+    double d[3] = {0.0, 0.0, 0.0};
+    P mv = zero_pair<T, false>();
+    bool found = false;
+    const int kx = g.xi % W;
+    const bool own_lane = w.lane == g.xi / W;
+#pragma unroll 1
+    for (int r = y0; r < y1; ++r) {
+        load_coef<T, W>(pc, g.template coef_row<T>(r), c0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!FIRST) load_row<T, W>(r2, g.template offset<T, W>(min(r + 1, y1 - 1), n - 2), pn);
+        load_row<T, W>(r1, g.template offset<T, W>(min(r + 2, y1), n - 1), nx);
+        apply_row<T, W, BCX>(c0, th, w1, w0, w2, v);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            v[k] = cheb_combine<T, false>(v[k], p2[k], FIRST);
+            dots3(d, (double)v[k].e, (double)v[k].h, (double)w1[k].e, (double)w1[k].h);
+        }
+        store_row<T, W>(ro, g.template offset<T, W>(r, n), v);
+        if constexpr (FIRST) {
+            if (g.phys(r) == g.yi) {
+#pragma unroll
+                for (int k = 0; k < W; ++k) mv = select_pair<T, false>(k == kx, v[k], mv);
+                found = own_lane;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            w0[k] = w1[k]; w1[k] = w2[k]; w2[k] = nx[k];
+            if constexpr (!FIRST) p2[k] = pn[k];
+        }
+    }
+    if constexpr (FIRST) {
+        if (found && A.mu_ee) {
+            const int64_t m = (int64_t)w.b * A.N + 1;
+            A.mu_ee[m] = (double)mv.e;
+            A.mu_he[m] = (double)mv.h;
+        }
+    }
+    wave_sum<3>(d);
+    if (w.lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) A.part[((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[k];
+    }
+}
+
+// Steps per pass and the wavefronts per SIMD the compiler must fit (its
+// registers: 512 / waves per lane).
+#ifndef CBDG_VC_K_F64
+#define CBDG_VC_K_F64 6
+#endif
+#ifndef CBDG_VC_K_F32
+#define CBDG_VC_K_F32 7
+#endif
+#ifndef CBDG_VC_OCC_F64
+#define CBDG_VC_OCC_F64 1
+#endif
+#ifndef CBDG_VC_OCC_F32
+#define CBDG_VC_OCC_F32 1
+#endif
+template <typename T> constexpr int kVcSteps = sizeof(T) == 8 ? CBDG_VC_K_F64 : CBDG_VC_K_F32;
+template <typename T, int K> struct VcOcc {
+    static constexpr int waves = sizeof(T) == 8 ? CBDG_VC_OCC_F64 : CBDG_VC_OCC_F32;
+};
+
+// K steps in one pass: a_n .. a_{n+K-1} from a_{n-2} and a_{n-1}; the last
+// two (a_{n+K-2}, a_{n+K-1}, what the next pass reads) are stored, the others
+// stay in registers.  Trip r computes row r - j of level j (a_{n+j}) for
+// j = 0 .. K-1: level j needs rows r-j-1 .. r-j+1 of level j-1 and row r-j
+// of level j-2 (a_{n-1} and a_{n-2} for the first two levels), so every
+// level keeps a window of its three newest rows.  Level j is computed on the
+// segment's rows and K-1-j more at each end.
+// Each trip loads the coefficient rows it needs first, then the a_{n-2} row
+// and the a_{n-1} row of a later trip.  The a_{n-1} rows sit in a ring of four
+// and the a_{n-2} rows in a ring of two, rotated by unrolling the loop four
+// times: a register that a load is still filling is never copied, so no trip
+// waits for the loads it issued itself.  The trip count is rounded up to a
+// multiple of four; the extra trips compute rows past the segment that are
+// neither stored nor summed.
+template <typename T, int W, bool BCX, bool BCY, int K>
+__global__ __launch_bounds__(kVcBlock) __attribute__((amdgpu_waves_per_eu(VcOcc<T, K>::waves)))
+void k_vc_pass(VcArgs A)
+{
+    static_assert(K >= 3, "a pass of K steps keeps the windows of levels 0 .. K-2");
+    using P = Pair<T, false>;
+    using S = typename Storage<T, false>::type;
+    VcWave<BCX, BCY> w;
+    const int n = A.n;
+    if (!vc_wave(A, n + K - 1, K, w)) return;
+    w.g.lo = w.lane * W;
+    w.g.lane = w.lane;
+    const auto &g = w.g;
+    const auto r1 = vec_rsrc<T>(A.a1, w.b, A.Dv);
+    const auto r2 = vec_rsrc<T>(A.a2, w.b, A.Dv);
+    const auto ro1 = vec_rsrc<T>(A.out, w.b, A.Dv);
+    const auto ro2 = vec_rsrc<T>(A.out2, w.b, A.Dv);
+    const S *pc = reinterpret_cast<const S *>(A.coef);
+    const T th = T(A.th);
+    const int y0 = w.y0, y1 = w.y1;
+
+    P wa[W], wb[W], wc[W], wd[W];   // ring of a_{n-1} rows
+    P pa[W], pb[W];                 // ring of a_{n-2} rows
+    P lv[K - 1][3][W];              // level j: rows r-j-2, r-j-1, r-j
+    // Coefficient rows r-K+1 .. r in a ring in LDS (slot = row mod K), one
+    // row loaded per trip into registers one trip ahead of its use
+    constexpr int NQ = W / kPer<T>;  // 16-byte chunks per lane and row
+    __shared__ U4 ring_all[kVcWaves][K][NQ][kWave];
+    U4 (*ring)[NQ][kWave] = ring_all[threadIdx.x / kWave];
+    const U4 *pc4 = reinterpret_cast<const U4 *>(A.coef);
+    auto coef_chunks = [&](int v, U4 *cp) __attribute__((always_inline)) {
+        const int64_t at = g.template coef_row<T>(v) / kPer<T>;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) cp[q] = pc4[at + q * kWave];
+    };
+    auto slot = [&](int v) -> int { return (v % K + K) % K; };
+    U4 cpre[NQ];
+    for (int v = y0 - 2 * (K - 1); v < y0 - (K - 1); ++v) {
+        coef_chunks(v, cpre);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ring[slot(v)][q][w.lane] = cpre[q];
+    }
+    coef_chunks(y0 - (K - 1), cpre);
+    load_row<T, W>(r1, g.template offset<T, W>(y0 - K, n - 1), wa);
+    load_row<T, W>(r1, g.template offset<T, W>(y0 - K + 1, n - 1), wb);
+    load_row<T, W>(r1, g.template offset<T, W>(y0 - K + 2, n - 1), wc);
+    load_row<T, W>(r2, g.template offset<T, W>(y0 - K + 1, n - 2), pa);
+#pragma unroll
+    for (int j = 0; j < K - 1; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < W; ++k) lv[j][i][k] = zero_pair<T, false>();
+    double d[3 * K];
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) d[i] = 0.0;
+
+    // one trip: w0, w1, w2 = a_{n-1} rows r-1, r, r+1; row r+2 is loaded into
+    // w3; p = a_{n-2} row r; row r+1 is loaded into pn
+    auto trip = [&](int r, const P *w0, const P *w1, const P *w2, P *w3, const P *p, P *pn)
+                    __attribute__((always_inline)) {
+        {
+            const int sr = slot(r);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) ring[sr][q][w.lane] = cpre[q];
+        }
+        coef_chunks(r + 1, cpre);
+        __builtin_amdgcn_sched_barrier(0);
+        load_row<T, W>(r2, g.template offset<T, W>(r + 1, n - 2), pn);
+        load_row<T, W>(r1, g.template offset<T, W>(r + 2, n - 1), w3);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int s = r - j;
+            S cj[W];  // coefficients of row s
+            {
+                const int ss = slot(s);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const U4 u = ring[ss][q][w.lane];
+                    if constexpr (sizeof(T) == 8) {
+                        cj[q] = S{__hiloint2double((int)u[1], (int)u[0]), __hiloint2double((int)u[3], (int)u[2])};
+                    } else {
+                        cj[2 * q] = S{__uint_as_float(u[0]), __uint_as_float(u[1])};
+                        cj[2 * q + 1] = S{__uint_as_float(u[2]), __uint_as_float(u[3])};
+                    }
+                }
+            }
+            // center, lower and upper rows of level j-1 and row s of level j-2
+            const P *cc = j == 0 ? w1 : lv[j - 1][1];
+            const P *dd = j == 0 ? w0 : lv[j - 1][0];
+            const P *uu = j == 0 ? w2 : lv[j - 1][2];
+            const P *pp = j == 0 ? p : (j == 1 ? w0 : lv[j - 2][0]);
+            const bool own = s >= y0 && s < y1;
+            if (j < K - 1) {
+#pragma unroll
+                for (int k = 0; k < W; ++k) { lv[j][0][k] = lv[j][1][k]; lv[j][1][k] = lv[j][2][k]; }
+                P *v = lv[j][2];
+                // A row past an open edge must come out zero.  Its own pairs
+                // on the level below and two levels below are zero already
+                // (loaded as zero, or computed so on earlier trips), so with
+                // the hopping switched off for it the stencil gives zero
+                // without a mask: no other row reaches it.
+                apply_row<T, W, BCX>(cj, g.in_lattice(s) ? th : T(0), cc, dd, uu, v);
+#pragma unroll
+                for (int k = 0; k < W; ++k) v[k] = cheb_combine<T, false>(v[k], pp[k], false);
+                if (own) {
+#pragma unroll
+                    for (int k = 0; k < W; ++k)
+                        dots3(d + 3 * j, (double)v[k].e, (double)v[k].h, (double)cc[k].e, (double)cc[k].h);
+                    if (j == K - 2) store_row<T, W>(ro1, g.template offset<T, W>(s, n + j), v);
+                }
+            } else if (own) {
+                // the last level, stored chunk by chunk
+                const unsigned off = g.template offset<T, W>(s, n + j);
+                const P hl = dpp_pair<BCX ? kRor1 : kShr1>(cc[W - 1]);
+                const P hr = dpp_pair<BCX ? kRol1 : kShl1>(cc[0]);
+#pragma unroll
+                for (int q = 0; q < W / kPer<T>; ++q) {
+                    P v[kPer<T>];
+#pragma unroll
+                    for (int i = 0; i < kPer<T>; ++i) {
+                        const int k = q * kPer<T> + i;
+                        const OnSite<T> o{cj[k].x, -cj[k].x, cj[k].y, T(0)};
+                        v[i] = cheb_combine<T, false>(
+                            apply_uniform<T, false>(o, th, cc[k], k > 0 ? cc[k - 1] : hl, k < W - 1 ? cc[k + 1] : hr,
+                                                    dd[k], uu[k]),
+                            pp[k], false);
+                        dots3(d + 3 * j, (double)v[i].e, (double)v[i].h, (double)cc[k].e, (double)cc[k].h);
+                    }
+                    bst<T>(ro2, off + q * (unsigned)(kWave * 16), v);
+                }
+            }
+        }
+    };
+    const int r0 = y0 - (K - 1), trips = (y1 + K - 2) - r0 + 1;
+    const int r_end = r0 + 4 * ((trips + 3) / 4);
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll 1
+    for (int r = r0; r < r_end; r += 4) {
+        trip(r, wa, wb, wc, wd, pa, pb);
+        trip(r + 1, wb, wc, wd, wa, pb, pa);
+        trip(r + 2, wc, wd, wa, wb, pa, pb);
+        trip(r + 3, wd, wa, wb, wc, pb, pa);
+    }
+    wave_sum<3 * K>(d);
+    if (w.lane == 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) A.part[j * A.pstride + ((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[3 * j + k];
+        }
+    }
+}
+
+// a_0 = |s_b, e> in the vector-contiguous layout (the buffer is zero), and the
+// zeroth moments; an invalid start site leaves its vector zero and its moment
+// row NaN.
+template <typename T>
+__global__ void k_vc_seed(typename Storage<T, false>::type *a0, int64_t Dv, int Lx, int W, int Bt, int64_t L2,
+                          const int32_t *sites, double *mu_ee, double *mu_he, int N)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bt) return;
+    const int64_t s = sites[b];
+    const int64_t m = (int64_t)b * N;
+    if (s < 0 || s >= L2) {
+        const double nan = __builtin_nan("");
+        for (int n = 0; n < N; ++n) { mu_ee[m + n] = nan; mu_he[m + n] = nan; }
+        return;
+    }
+    const int64_t y = s / Lx, x = s % Lx;
+    a0[b * Dv + y * Lx + pair_pos<T>((int)(x / W), (int)(x % W))] = typename Storage<T, false>::type{T(1), T(0)};
+    mu_ee[m] = 1.0;
+    mu_he[m] = 0.0;
+}
+
+// Packed (de, Delta/a) of every site in the row layout of the passes.
+template <typename T>
+__global__ void k_vc_coef(const OnSite<T> *__restrict__ ons, typename Storage<T, false>::type *__restrict__ pc,
+                          int Lx, int W, int64_t L2)
+{
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < L2; s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = s / Lx, x = s % Lx;
+        const OnSite<T> o = ons[s];
+        pc[y * Lx + pair_pos<T>((int)(x / W), (int)(x % W))] = typename Storage<T, false>::type{o.de, o.dr};
+    }
+}
+
+#ifndef CBDG_VC
+#define CBDG_VC 1
+#endif
+// Wavefronts a pass aims for: enough row segments per vector that a tile
+// of Bt vectors gives at least this many.
+#ifndef CBDG_VC_WAVES
+#define CBDG_VC_WAVES 1024
+#endif
+
+int vc_width(int Lx, bool f32)
+{
+    if (!CBDG_VC || Lx % kWave) return 0;
+    const int W = Lx / kWave;
+    if (f32) return (W == 2 || W == 4) ? W : 0;  // two FP32 pairs per access
+    return (W == 1 || W == 2 || W == 4) ? W : 0;
+}
+
+int vc_segments(int Ly, int Bt, int steps)
+{
+    (void)steps;
+    const int want = (int)ceil_div(CBDG_VC_WAVES, std::max(Bt, 1));
+    return std::max(1, std::min(want, Ly / 16));
+}
+
+template <typename T, int W, bool BCX, bool BCY>
+static int launch_vc_w(VcArgs A, int steps, hipStream_t st)
+{
+    const int64_t nb = ceil_div(A.Bt, kVcWaves) * (int64_t)A.n_segs;
+    if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
+    A.nblocks = (int)nb;
+    constexpr int K = kVcSteps<T>;
+    if (steps == K) hipLaunchKernelGGL((k_vc_pass<T, W, BCX, BCY, K>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    else if (A.n == 1) hipLaunchKernelGGL((k_vc_step1<T, W, BCX, BCY, true>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    else hipLaunchKernelGGL((k_vc_step1<T, W, BCX, BCY, false>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    CBDG_CHECK_LAUNCH(steps == 1 ? "k_vc_step1" : "k_vc_pass");
+    return CBDG_OK;
+}
+
+template <typename T, int W>
+static int launch_vc_bc(const VcArgs &A, int steps, hipStream_t st)
+{
+    if (A.bcx) return A.bcy ? launch_vc_w<T, W, true, true>(A, steps, st) : launch_vc_w<T, W, true, false>(A, steps, st);
+    return A.bcy ? launch_vc_w<T, W, false, true>(A, steps, st) : launch_vc_w<T, W, false, false>(A, steps, st);
+}
+
+template <typename T>
+static int launch_vc_t(const VcArgs &A, int steps, hipStream_t st)
+{
+    switch (vc_width(A.Lx, std::is_same<T, float>::value)) {
+    case 1:
+        if constexpr (std::is_same<T, double>::value) return launch_vc_bc<T, 1>(A, steps, st);
+        break;
+    case 2: return launch_vc_bc<T, 2>(A, steps, st);
+    case 4: return launch_vc_bc<T, 4>(A, steps, st);
+    default: break;
+    }
+    return fail(CBDG_EUNSUPPORTED, "vector-contiguous pass: Lx = %d is not 64 times a supported width", A.Lx);
+}
+
+int launch_vc_seed(void *a0, int64_t Dv, int Lx, bool f32, int Bt, int64_t L2, const int32_t *sites, double *mu_ee,
+                   double *mu_he, int N, hipStream_t st)
+{
+    const int W = vc_width(Lx, f32);
+    if (!W) return fail(CBDG_EUNSUPPORTED, "vector-contiguous pass: Lx = %d does not fit", Lx);
+    if (f32)
+        hipLaunchKernelGGL((k_vc_seed<float>), dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st,
+                           reinterpret_cast<float2 *>(a0), Dv, Lx, W, Bt, L2, sites, mu_ee, mu_he, N);
+    else
+        hipLaunchKernelGGL((k_vc_seed<double>), dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st,
+                           reinterpret_cast<double2 *>(a0), Dv, Lx, W, Bt, L2, sites, mu_ee, mu_he, N);
+    CBDG_CHECK_LAUNCH("k_vc_seed");
+    return CBDG_OK;
+}
+
+int launch_vc_coef(const void *onsite, void *coef, int Lx, bool f32, int64_t L2, hipStream_t st)
+{
+    const int W = vc_width(Lx, f32);
+    if (!W) return fail(CBDG_EUNSUPPORTED, "vector-contiguous pass: Lx = %d does not fit", Lx);
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(L2, kBlock), 4096);
+    if (f32)
+        hipLaunchKernelGGL((k_vc_coef<float>), dim3(grid), dim3(kBlock), 0, st,
+                           reinterpret_cast<const OnSite<float> *>(onsite), reinterpret_cast<float2 *>(coef), Lx, W, L2);
+    else
+        hipLaunchKernelGGL((k_vc_coef<double>), dim3(grid), dim3(kBlock), 0, st,
+                           reinterpret_cast<const OnSite<double> *>(onsite), reinterpret_cast<double2 *>(coef), Lx, W, L2);
+    CBDG_CHECK_LAUNCH("k_vc_coef");
+    return CBDG_OK;
+}
+
+int vc_steps(bool f32) { return f32 ? kVcSteps<float> : kVcSteps<double>; }
+
+int launch_vc(const VcArgs &A, int steps, bool f32, hipStream_t st)
+{
+    if (steps != 1 && steps != vc_steps(f32)) return fail(CBDG_EINVAL, "vector-contiguous pass: %d steps", steps);
+    if (A.Dv * 16 > INT32_MAX) return fail(CBDG_EINVAL, "vector-contiguous pass: lattice too large");
+    return f32 ? launch_vc_t<float>(A, steps, st) : launch_vc_t<double>(A, steps, st);
+}
+
+}  // namespace cbdg
