@@ -135,24 +135,35 @@ def copy_probe(dev, nbytes=2 << 30, reps=8):
                       "avg_ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
 
 
-def recursion_plan(real_uniform: bool, bt: int, s_bytes: int):
-    """(kernel name, two-step, three-step) of the passes the library issues for
-    a tile of bt vectors: real operators with uniform hopping advance three
-    steps per launch on tiles of more than 128 vectors and two on smaller
-    ones; other operators one step per launch."""
+# Steps per launch of the vector-contiguous passes (FP64, FP32 recursion)
+VC_STEPS = {8: 6, 4: 7}
+
+
+def recursion_plan(real_uniform: bool, bt: int, s_bytes: int, Lx: int = 0, doubling: bool = True):
+    """(kernel name, layout, steps per launch) of the passes the library
+    issues for a tile of bt vectors.  Real operators with uniform hopping
+    under moment doubling on lattices with Lx = 64 W (FP64: W = 1, 2, 4;
+    FP32: W = 2, 4) take the vector-contiguous passes, six (FP64) or seven
+    (FP32) steps per launch; other real uniform operators the vector-major
+    passes, three steps per launch on tiles of more than 128 vectors and two
+    on smaller ones; other operators one step per launch."""
     t = "double" if s_bytes == 8 else "float"
+    W = Lx // 64 if Lx % 64 == 0 else 0
+    if real_uniform and doubling and W in ((1, 2, 4) if s_bytes == 8 else (2, 4)):
+        K = VC_STEPS[s_bytes]
+        return "k_vc_pass<%s> (%d recursion steps per launch, one wavefront per vector)" % (t, K), "vc", K
     if not real_uniform:
-        return "k_cheb_step<%s> (one recursion step per launch)" % t, False, False
+        return "k_cheb_step<%s> (one recursion step per launch)" % t, "vm", 1
     if bt >= 129:
-        return "k_cheb_step3<%s> (three recursion steps per launch)" % t, True, True
-    return "k_cheb_step2<%s> (two recursion steps per launch)" % t, True, False
+        return "k_cheb_step3<%s> (three recursion steps per launch)" % t, "vm", 3
+    return "k_cheb_step2<%s> (two recursion steps per launch)" % t, "vm", 2
 
 
-def launch_bytes(tile_events, sites_np, tile, n_tiles, w, steps_per_tile, real_uniform, s_bytes):
+def launch_bytes(tile_events, sites_np, tile, n_tiles, w, steps_per_tile, real_uniform, s_bytes, doubling=True):
     """Launches, their summed duration (ms) and bytes over the timed tiles:
-    the minimum each launch must move (vectors inside the light cone) and the
-    bytes of the one-step streaming recursion over the whole lattice."""
-    from bench_forms import recursion_traffic
+    the minimum each launch must move (vectors inside their light cones) and
+    the bytes of the one-step streaming recursion over the whole lattice."""
+    from bench_forms import recursion_traffic, vc_traffic
     launches = 0
     kern_ms = 0.0
     moved_b = streamed_b = 0.0
@@ -161,13 +172,19 @@ def launch_bytes(tile_events, sites_np, tile, n_tiles, w, steps_per_tile, real_u
         kern_ms += e0.elapsed_time(e1)
         bp = (bt + 63) // 64 * 64
         lo = (k % n_tiles) * tile
-        name, two, three = recursion_plan(real_uniform, bt, s_bytes)
+        name, layout, K = recursion_plan(real_uniform, bt, s_bytes, w.Lx, doubling)
         kernel = kernel or name
-        nl, moved, streamed = recursion_traffic(sites_np[lo:lo + bt], w.Lx, w.Ly, w.bc_x, w.bc_y,
-                                                steps_per_tile, two, three_step=three)
+        ts = sites_np[lo:lo + bt]
+        if layout == "vc":
+            nl, moved, streamed = vc_traffic(ts, w.Lx, w.Ly, w.bc_x, w.bc_y, steps_per_tile, K)
+            moved_b += moved * 2 * s_bytes
+            streamed_b += streamed * 2 * s_bytes
+        else:
+            nl, moved, streamed = recursion_traffic(ts, w.Lx, w.Ly, w.bc_x, w.bc_y, steps_per_tile, K >= 2,
+                                                    three_step=K == 3)
+            moved_b += moved * 2 * bp * s_bytes
+            streamed_b += streamed * 2 * bp * s_bytes
         launches += nl
-        moved_b += moved * 2 * bp * s_bytes
-        streamed_b += streamed * 2 * bp * s_bytes
     return kernel, launches, kern_ms, moved_b, streamed_b
 
 
@@ -372,13 +389,13 @@ def main():
     value = moments_per_step * args.steps / (ms_total / 1e3)
 
     # Roofline of the dominant recursion kernel: the bytes each launch must
-    # move (its input and output vectors inside the light cone of the tile's
-    # start sites, 2 components x s bytes per (site, vector)) over the average
-    # launch duration; beside it the bytes the plain one-step recursion would
-    # stream over the whole lattice (3 vectors per recursion step).
+    # move (its input and output vectors inside their light cones, 2
+    # components x s bytes per (site, vector)) over the average launch
+    # duration; beside it the bytes the plain one-step recursion would stream
+    # over the whole lattice (3 vectors per recursion step).
     sites_np = np.arange(n_sites, dtype=np.int32)
     kernel, launches, kern_ms, moved_b, streamed_b = launch_bytes(
-        tile_events, sites_np, tile, n_tiles, w, steps_per_tile, True, s_bytes)
+        tile_events, sites_np, tile, n_tiles, w, steps_per_tile, True, s_bytes, doubling)
     avg_launch_ms = kern_ms / launches
     bytes_per_launch = moved_b / launches
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
@@ -419,8 +436,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "basis": "bytes each launch must move: its input and output vectors inside the light cone "
-                     "of the tile's start sites (multi-step passes: 2 read, 2 written)",
+            "basis": "bytes each launch must move: its input and output vectors inside their light cones "
+                     "(vector-contiguous passes: each vector's own diamond; vector-major passes: the box of "
+                     "the tile's start sites; multi-step passes read 2 vectors and write 2)",
             "bytes_per_launch": bytes_per_launch,
             "effective_GBps": effective,
             "effective_frac": effective / HBM_PEAK_GBS,

@@ -45,6 +45,83 @@ def _cone_sites(x, y, Lx, Ly, bc_x, bc_y, n):
     return max(rows, 0) * max(cols, 0)
 
 
+def diamond_sites(x, y, Lx, Ly, bc_x, bc_y, R):
+    """Summed over the start sites (x, y): the lattice sites within lattice
+    (Manhattan) distance R of each, where a_R of a start vector can be
+    non-zero (Ht couples nearest neighbours).  On an open lattice: the
+    diamond's 2R^2 + 2R + 1 sites less the m^2 past each edge it crosses by m
+    rows or columns, plus the (m+1)(m+2)/2 past each pair of adjacent edges
+    it crosses with m = R - (distance to both edges) - 2 >= 0.  Periodic
+    directions are counted row by row."""
+    x = np.asarray(x, dtype=np.int64)
+    y = np.asarray(y, dtype=np.int64)
+    if R < 0 or x.size == 0:
+        return 0
+    if not bc_x and not bc_y:
+        lx, rx, ly, ry = x, Lx - 1 - x, y, Ly - 1 - y   # distances to the four edges
+        c = np.full(x.shape, 2 * R * R + 2 * R + 1, dtype=np.int64)
+        for e in (lx, rx, ly, ry):
+            m = np.maximum(R - e, 0)
+            c -= m * m
+        for ex in (lx, rx):
+            for ey in (ly, ry):
+                m = R - ex - ey - 2
+                c += np.where(m >= 0, (m + 1) * (m + 2) // 2, 0)
+        return int(c.sum())
+
+    def width(r):
+        if bc_x:
+            return np.full(x.shape, min(2 * r + 1, Lx), dtype=np.int64)
+        return np.minimum(x + r, Lx - 1) - np.maximum(x - r, 0) + 1
+
+    total = 0
+    if bc_y:
+        for d in range(0, min(R, Ly // 2) + 1):
+            mult = 1 if d == 0 or 2 * d == Ly else 2
+            total += mult * int(width(R - d).sum())
+    else:
+        for dy in range(-R, R + 1):
+            ok = (y + dy >= 0) & (y + dy < Ly)
+            total += int(np.where(ok, width(R - abs(dy)), 0).sum())
+    return total
+
+
+def vc_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, K):
+    """Launches of one tile in the vector-contiguous passes (one wavefront per
+    vector, each clipped to its own light cone) and the Nambu pairs they must
+    move through HBM at minimum, summed over the tile's vectors:
+      first step   read a_0, write a_1: D(0) + D(1)
+      K-step pass  read a_{n-2}, a_{n-1}, write a_{n+K-2}, a_{n+K-1}:
+                   D(n-2) + D(n-1) + D(n+K-2) + D(n+K-1)
+      single step  read a_{n-2}, a_{n-1}, write a_n: D(n-2) + D(n-1) + D(n)
+    with D(R) the sites within distance R of the vector's start site.  Steps
+    2.. go K at a time, the remainder one at a time.  Returns (launches, pairs
+    moved, pairs of the plain one-step streaming recursion, 3 x L2 per step
+    and vector)."""
+    sites = np.asarray(sites)
+    sites = sites[(sites >= 0) & (sites < Lx * Ly)]
+    x, y = sites % Lx, sites // Lx
+    if n_steps < 1 or sites.size == 0:
+        return 0, 0, 0
+    cache = {}
+
+    def D(R):
+        if R not in cache:
+            cache[R] = diamond_sites(x, y, Lx, Ly, bc_x, bc_y, R)
+        return cache[R]
+    launches, moved = 1, D(0) + D(1)
+    n = 2
+    while n + K - 1 <= n_steps:
+        launches += 1
+        moved += D(n - 2) + D(n - 1) + D(n + K - 2) + D(n + K - 1)
+        n += K
+    while n <= n_steps:
+        launches += 1
+        moved += D(n - 2) + D(n - 1) + D(n)
+        n += 1
+    return launches, moved, 3 * Lx * Ly * n_steps * sites.size
+
+
 def recursion_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, two_step, three_step=False):
     """Recursion launches of one tile as the library issues them, and the
     vector elements (site x vector, in units of one Nambu pair per vector)

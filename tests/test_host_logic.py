@@ -1,5 +1,6 @@
 """Host-side pieces of the product that need no GPU."""
 import numpy as np
+import pytest
 
 
 def test_gmres_solves_nonsymmetric_system():
@@ -92,6 +93,57 @@ def test_reverse_pass_accounting_matches_the_library_plan():
     # small tiles: two-step forward at stride 18
     s64, l64 = bench_forms.adjoint_traffic(512, 128 * 128, tile=64)
     assert l64 == (1 + 127 + 1) + (14 * 8 + 2) + 256
+
+
+def _diamond_brute(x, y, Lx, Ly, bcx, bcy, R):
+    X, Y = np.meshgrid(np.arange(Lx), np.arange(Ly))
+    tot = 0
+    for xi, yi in zip(x, y):
+        dx, dy = np.abs(X - xi), np.abs(Y - yi)
+        if bcx:
+            dx = np.minimum(dx, Lx - dx)
+        if bcy:
+            dy = np.minimum(dy, Ly - dy)
+        tot += int(((dx + dy) <= R).sum())
+    return tot
+
+
+@pytest.mark.parametrize("Lx,Ly", [(7, 5), (16, 9), (64, 3), (10, 10), (8, 8)])
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_light_cone_site_count_is_exact(Lx, Ly, bcx, bcy):
+    """The closed form (open lattice) and the row sums (periodic directions)
+    of the sites within lattice distance R of each start site, against a
+    brute-force count, for radii from 0 to past the lattice's diameter."""
+    import bench_forms
+    rng = np.random.default_rng(Lx * Ly + 2 * bcx + bcy)
+    x, y = rng.integers(0, Lx, 7), rng.integers(0, Ly, 7)
+    for R in (0, 1, 2, 3, 4, 5, 8, 13, 30):
+        assert bench_forms.diamond_sites(x, y, Lx, Ly, bcx, bcy, R) == _diamond_brute(x, y, Lx, Ly, bcx, bcy, R)
+
+
+def test_vector_contiguous_pass_schedule():
+    """N/2 steps as the first step, passes of K steps from step 2 and single
+    steps for the rest; bytes per pass = cones of a_{n-2}, a_{n-1} read and
+    of a_{n+K-2}, a_{n+K-1} written."""
+    import bench_forms
+    L, sites = 256, np.array([0, 300, 65535])
+    for N, K, passes, singles in ((1024, 6, 85, 1), (2048, 7, 146, 1), (1024, 3, 170, 1), (14, 6, 1, 0),
+                                  (12, 6, 0, 5)):
+        launches, moved, streamed = bench_forms.vc_traffic(sites, L, L, 0, 0, N // 2, K)
+        assert launches == 1 + passes + singles
+        assert streamed == 3 * L * L * (N // 2) * 3
+
+        def D(R):
+            return bench_forms.diamond_sites(sites % L, sites // L, L, L, 0, 0, R)
+        want = D(0) + D(1)
+        n = 2
+        for _ in range(passes):
+            want += D(n - 2) + D(n - 1) + D(n + K - 2) + D(n + K - 1)
+            n += K
+        for _ in range(singles):
+            want += D(n - 2) + D(n - 1) + D(n)
+            n += 1
+        assert n == N // 2 + 1 and moved == want
 
 
 def test_closed_operator_raises_before_any_library_call():
