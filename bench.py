@@ -136,15 +136,15 @@ def copy_probe(dev, nbytes=2 << 30, reps=8):
 
 
 # Steps per launch of the vector-contiguous passes (FP64, FP32 recursion)
-VC_STEPS = {8: 6, 4: 7}
+VC_STEPS = {8: 7, 4: 7}
 
 
 def recursion_plan(real_uniform: bool, bt: int, s_bytes: int, Lx: int = 0, doubling: bool = True):
     """(kernel name, layout, steps per launch) of the passes the library
     issues for a tile of bt vectors.  Real operators with uniform hopping
     under moment doubling on lattices with Lx = 64 W (FP64: W = 1, 2, 4;
-    FP32: W = 2, 4) take the vector-contiguous passes, six (FP64) or seven
-    (FP32) steps per launch; other real uniform operators the vector-major
+    FP32: W = 2, 4) take the vector-contiguous passes, seven steps per
+    launch; other real uniform operators the vector-major
     passes, three steps per launch on tiles of more than 128 vectors and two
     on smaller ones; other operators one step per launch."""
     t = "double" if s_bytes == 8 else "float"

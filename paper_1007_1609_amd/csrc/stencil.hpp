@@ -215,20 +215,22 @@ __device__ __forceinline__ Pair<T, C> apply_uniform(const OnSite<T> &o, T th, co
     return y;
 }
 
-// out = 2 y - p   (or y on the first step)
+// out = 2 y - p   (or y on the first step), one fused multiply-add per
+// component: 2y is exact, so fma(2, y, -p) rounds 2y - p exactly as the
+// product followed by the subtraction would
 template <typename T, bool C>
 __device__ __forceinline__ Pair<T, C> cheb_combine(const Pair<T, C> &y, const Pair<T, C> &p, bool first)
 {
 #pragma clang fp contract(off)
     Pair<T, C> o;
     if constexpr (C) {
-        o.er = first ? y.er : T(2) * y.er - p.er;
-        o.ei = first ? y.ei : T(2) * y.ei - p.ei;
-        o.hr = first ? y.hr : T(2) * y.hr - p.hr;
-        o.hi = first ? y.hi : T(2) * y.hi - p.hi;
+        o.er = first ? y.er : fma_t(T(2), y.er, -p.er);
+        o.ei = first ? y.ei : fma_t(T(2), y.ei, -p.ei);
+        o.hr = first ? y.hr : fma_t(T(2), y.hr, -p.hr);
+        o.hi = first ? y.hi : fma_t(T(2), y.hi, -p.hi);
     } else {
-        o.e = first ? y.e : T(2) * y.e - p.e;
-        o.h = first ? y.h : T(2) * y.h - p.h;
+        o.e = first ? y.e : fma_t(T(2), y.e, -p.e);
+        o.h = first ? y.h : fma_t(T(2), y.h, -p.h);
     }
     return o;
 }

@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 // Steps per pass and the wavefronts per SIMD the compiler must fit (its
 // registers: 512 / waves per lane).
 #ifndef CBDG_VC_K_F64
-#define CBDG_VC_K_F64 6
+#define CBDG_VC_K_F64 7
 #endif
 #ifndef CBDG_VC_K_F32
 #define CBDG_VC_K_F32 7
@@ -381,6 +381,23 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 #define CBDG_VC_OCC_F32 1
 #endif
 template <typename T> constexpr int kVcSteps = sizeof(T) == 8 ? CBDG_VC_K_F64 : CBDG_VC_K_F32;
+// Trips ahead that the a_{n-1} and a_{n-2} rows are loaded
+#ifndef CBDG_VC_D1_F64
+#define CBDG_VC_D1_F64 1
+#endif
+#ifndef CBDG_VC_D2_F64
+#define CBDG_VC_D2_F64 1
+#endif
+#ifndef CBDG_VC_D1_F32
+#define CBDG_VC_D1_F32 3
+#endif
+#ifndef CBDG_VC_D2_F32
+#define CBDG_VC_D2_F32 2
+#endif
+template <typename T> struct VcDepth {
+    static constexpr int a1 = sizeof(T) == 8 ? CBDG_VC_D1_F64 : CBDG_VC_D1_F32;
+    static constexpr int a2 = sizeof(T) == 8 ? CBDG_VC_D2_F64 : CBDG_VC_D2_F32;
+};
 template <typename T, int K> struct VcOcc {
     static constexpr int waves = sizeof(T) == 8 ? CBDG_VC_OCC_F64 : CBDG_VC_OCC_F32;
 };
@@ -420,8 +437,11 @@ void k_vc_pass(VcArgs A)
     const T th = T(A.th);
     const int y0 = w.y0, y1 = w.y1;
 
-    P wa[W], wb[W], wc[W], wd[W];   // ring of a_{n-1} rows
-    P pa[W], pb[W];                 // ring of a_{n-2} rows
+    // a_{n-1} rows r-1 .. r+1 and the D1 rows in flight; a_{n-2} row r and
+    // the D2 rows in flight
+    constexpr int D1 = VcDepth<T>::a1, D2 = VcDepth<T>::a2;
+    constexpr int R1 = 3 + D1, R2 = 1 + D2;
+    P ra[R1][W], rp[R2][W];
     P lv[K - 1][3][W];              // level j: rows r-j-2, r-j-1, r-j
     // Coefficient rows r-K+1 .. r in a ring in LDS (slot = row mod K), one
     // row loaded per trip into registers one trip ahead of its use
@@ -442,10 +462,11 @@ void k_vc_pass(VcArgs A)
         for (int q = 0; q < NQ; ++q) ring[slot(v)][q][w.lane] = cpre[q];
     }
     coef_chunks(y0 - (K - 1), cpre);
-    load_row<T, W>(r1, g.template offset<T, W>(y0 - K, n - 1), wa);
-    load_row<T, W>(r1, g.template offset<T, W>(y0 - K + 1, n - 1), wb);
-    load_row<T, W>(r1, g.template offset<T, W>(y0 - K + 2, n - 1), wc);
-    load_row<T, W>(r2, g.template offset<T, W>(y0 - K + 1, n - 2), pa);
+    const int r0 = y0 - (K - 1);
+#pragma unroll
+    for (int i = 0; i < R1 - 1; ++i) load_row<T, W>(r1, g.template offset<T, W>(r0 - 1 + i, n - 1), ra[i]);
+#pragma unroll
+    for (int i = 0; i < R2 - 1; ++i) load_row<T, W>(r2, g.template offset<T, W>(r0 + i, n - 2), rp[i]);
 #pragma unroll
     for (int j = 0; j < K - 1; ++j)
 #pragma unroll
@@ -456,8 +477,8 @@ void k_vc_pass(VcArgs A)
 #pragma unroll
     for (int i = 0; i < 3 * K; ++i) d[i] = 0.0;
 
-    // one trip: w0, w1, w2 = a_{n-1} rows r-1, r, r+1; row r+2 is loaded into
-    // w3; p = a_{n-2} row r; row r+1 is loaded into pn
+    // one trip: w0, w1, w2 = a_{n-1} rows r-1, r, r+1; row r+1+D1 is loaded
+    // into w3; p = a_{n-2} row r; row r+D2 is loaded into pn
     auto trip = [&](int r, const P *w0, const P *w1, const P *w2, P *w3, const P *p, P *pn)
                     __attribute__((always_inline)) {
         {
@@ -467,8 +488,8 @@ void k_vc_pass(VcArgs A)
         }
         coef_chunks(r + 1, cpre);
         __builtin_amdgcn_sched_barrier(0);
-        load_row<T, W>(r2, g.template offset<T, W>(r + 1, n - 2), pn);
-        load_row<T, W>(r1, g.template offset<T, W>(r + 2, n - 1), w3);
+        load_row<T, W>(r2, g.template offset<T, W>(r + D2, n - 2), pn);
+        load_row<T, W>(r1, g.template offset<T, W>(r + 1 + D1, n - 1), w3);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -534,15 +555,18 @@ void k_vc_pass(VcArgs A)
             }
         }
     };
-    const int r0 = y0 - (K - 1), trips = (y1 + K - 2) - r0 + 1;
-    const int r_end = r0 + 4 * ((trips + 3) / 4);
+    // the rings rotate by unrolling: U trips per iteration, U a multiple of
+    // both ring lengths
+    constexpr int U = R1 % R2 == 0 ? R1 : R1 * R2;
+    const int trips = (y1 + K - 2) - r0 + 1;
+    const int r_end = r0 + U * ((trips + U - 1) / U);
     __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
-    for (int r = r0; r < r_end; r += 4) {
-        trip(r, wa, wb, wc, wd, pa, pb);
-        trip(r + 1, wb, wc, wd, wa, pb, pa);
-        trip(r + 2, wc, wd, wa, wb, pa, pb);
-        trip(r + 3, wd, wa, wb, wc, pb, pa);
+    for (int r = r0; r < r_end; r += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            trip(r + u, ra[u % R1], ra[(u + 1) % R1], ra[(u + 2) % R1], ra[(u + R1 - 1) % R1], rp[u % R2],
+                 rp[(u + R2 - 1) % R2]);
     }
     wave_sum<3 * K>(d);
     if (w.lane == 0) {
