@@ -95,7 +95,8 @@ def vc_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, K):
                    D(n-2) + D(n-1) + D(n+K-2) + D(n+K-1)
       single step  read a_{n-2}, a_{n-1}, write a_n: D(n-2) + D(n-1) + D(n)
     with D(R) the sites within distance R of the vector's start site.  Steps
-    2.. go K at a time, the remainder one at a time.  Returns (launches, pairs
+    2.. go K at a time, a remainder of two or more in one shorter pass, a
+    remainder of one as a single step.  Returns (launches, pairs
     moved, pairs of the plain one-step streaming recursion, 3 x L2 per step
     and vector)."""
     sites = np.asarray(sites)
@@ -115,6 +116,11 @@ def vc_traffic(sites, Lx, Ly, bc_x, bc_y, n_steps, K):
         launches += 1
         moved += D(n - 2) + D(n - 1) + D(n + K - 2) + D(n + K - 1)
         n += K
+    rest = n_steps - n + 1
+    if rest >= 2:  # one shorter pass
+        launches += 1
+        moved += D(n - 2) + D(n - 1) + D(n + rest - 2) + D(n + rest - 1)
+        n += rest
     while n <= n_steps:
         launches += 1
         moved += D(n - 2) + D(n - 1) + D(n)

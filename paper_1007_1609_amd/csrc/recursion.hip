@@ -1519,6 +1519,13 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             std::swap(P2, Q0);
             std::swap(P1, Q1);
         }
+        if (n_steps - n + 1 >= 2) {
+            // the steps left, fewer than a full pass, in one shorter pass
+            const int rest = n_steps - n + 1;
+            V.n = n; V.a2 = P2; V.a1 = P1; V.out = Q0; V.out2 = Q1;
+            if ((rc = launch_vc(V, rest, f32, st)) || (rc = reduce(segsK, n, rest, Bt, Bp, mee, mhe))) return rc;
+            n += rest;
+        }
         V.n_segs = segs1;
         for (; n <= n_steps; ++n) {
             V.n = n; V.a1 = P1; V.a2 = P2; V.out = P2;

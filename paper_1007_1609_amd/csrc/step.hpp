@@ -75,9 +75,10 @@ constexpr int kMaxPassSteps = 8;
 // for W = Lx/64; real operators with uniform hopping, moment doubling): one
 // wavefront per vector and row segment, each vector clipped to its own light
 // cone.  A pass of `steps` = 1 writes a_n (A.out, may alias A.a2; n = 1: a_1 =
-// Ht a_0 and moment 1) and the partials of step n; `steps` = K = vc_steps()
-// writes a_{n+K-2} (A.out) and a_{n+K-1} (A.out2) from a_{n-2} (A.a2) and
-// a_{n-1} (A.a1) and the partials of steps n .. n+K-1 ([n_segs][3][Bp] each).
+// Ht a_0 and moment 1) and the partials of step n; `steps` = K = 2 ..
+// vc_steps() writes a_{n+K-2} (A.out) and a_{n+K-1} (A.out2) from a_{n-2}
+// (A.a2) and a_{n-1} (A.a1) and the partials of steps n .. n+K-1
+// ([n_segs][3][Bp] each).
 struct VcArgs {
     const void *a1, *a2;
     void *out, *out2;
@@ -88,6 +89,7 @@ struct VcArgs {
     int Bt, Bp;          // vectors; lane stride of the partials
     int n, N;
     int n_segs, nblocks;
+    int nlev;            // steps of a shorter last pass (set by launch_vc)
     const int32_t *sites;
     double *part;        // partials of step n + j at part + j * pstride
     int64_t pstride;
@@ -99,7 +101,7 @@ int vc_width(int Lx, bool f32);
 // Row segments per vector of a pass over a tile of Bt vectors.
 int vc_segments(int Ly, int Bt, int steps);
 int launch_vc(const VcArgs &A, int steps, bool f32, hipStream_t st);
-// Steps of one multi-step vector-contiguous pass (3 .. kMaxPassSteps).
+// Steps of a full multi-step vector-contiguous pass (3 .. kMaxPassSteps).
 int vc_steps(bool f32);
 // a_0 and the zeroth moments of a tile (buffer zeroed beforehand)
 int launch_vc_seed(void *a0, int64_t Dv, int Lx, bool f32, int Bt, int64_t L2, const int32_t *sites, double *mu_ee,

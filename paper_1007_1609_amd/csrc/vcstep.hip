@@ -416,7 +416,8 @@ template <typename T, int K> struct VcOcc {
 // waits for the loads it issued itself.  The trip count is rounded up to a
 // multiple of four; the extra trips compute rows past the segment that are
 // neither stored nor summed.
-template <typename T, int W, bool BCX, bool BCY, int K>
+// VAR: a shorter last pass of A.nlev (2 .. K-1) levels, the rest skipped.
+template <typename T, int W, bool BCX, bool BCY, int K, bool VAR>
 __global__ __launch_bounds__(kVcBlock) __attribute__((amdgpu_waves_per_eu(VcOcc<T, K>::waves)))
 void k_vc_pass(VcArgs A)
 {
@@ -425,7 +426,8 @@ void k_vc_pass(VcArgs A)
     using S = typename Storage<T, false>::type;
     VcWave<BCX, BCY> w;
     const int n = A.n;
-    if (!vc_wave(A, n + K - 1, K, w)) return;
+    const int nlev = VAR ? A.nlev : K;
+    if (!vc_wave(A, n + nlev - 1, nlev, w)) return;
     w.g.lo = w.lane * W;
     w.g.lane = w.lane;
     const auto &g = w.g;
@@ -514,7 +516,9 @@ void k_vc_pass(VcArgs A)
             const P *uu = j == 0 ? w2 : lv[j - 1][2];
             const P *pp = j == 0 ? p : (j == 1 ? w0 : lv[j - 2][0]);
             const bool own = s >= y0 && s < y1;
-            if (j < K - 1) {
+            if (VAR && j >= nlev) {
+                // past the last level of a shorter pass
+            } else if (j < K - 1) {
 #pragma unroll
                 for (int k = 0; k < W; ++k) { lv[j][0][k] = lv[j][1][k]; lv[j][1][k] = lv[j][2][k]; }
                 P *v = lv[j][2];
@@ -530,7 +534,8 @@ void k_vc_pass(VcArgs A)
 #pragma unroll
                     for (int k = 0; k < W; ++k)
                         dots3(d + 3 * j, (double)v[k].e, (double)v[k].h, (double)cc[k].e, (double)cc[k].h);
-                    if (j == K - 2) store_row<T, W>(ro1, g.template offset<T, W>(s, n + j), v);
+                    if (j == nlev - 2) store_row<T, W>(ro1, g.template offset<T, W>(s, n + j), v);
+                    if (VAR && j == nlev - 1) store_row<T, W>(ro2, g.template offset<T, W>(s, n + j), v);
                 }
             } else if (own) {
                 // the last level, stored chunk by chunk
@@ -572,8 +577,11 @@ void k_vc_pass(VcArgs A)
     if (w.lane == 0) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
+            if (j < nlev) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) A.part[j * A.pstride + ((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[3 * j + k];
+                for (int k = 0; k < 3; ++k)
+                    A.part[j * A.pstride + ((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[3 * j + k];
+            }
         }
     }
 }
@@ -643,8 +651,12 @@ static int launch_vc_w(VcArgs A, int steps, hipStream_t st)
     if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments: launch grid too large");
     A.nblocks = (int)nb;
     constexpr int K = kVcSteps<T>;
-    if (steps == K) hipLaunchKernelGGL((k_vc_pass<T, W, BCX, BCY, K>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
-    else if (A.n == 1) hipLaunchKernelGGL((k_vc_step1<T, W, BCX, BCY, true>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    if (steps == K) {
+        hipLaunchKernelGGL((k_vc_pass<T, W, BCX, BCY, K, false>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    } else if (steps >= 2) {
+        A.nlev = steps;
+        hipLaunchKernelGGL((k_vc_pass<T, W, BCX, BCY, K, true>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    } else if (A.n == 1) hipLaunchKernelGGL((k_vc_step1<T, W, BCX, BCY, true>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
     else hipLaunchKernelGGL((k_vc_step1<T, W, BCX, BCY, false>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
     CBDG_CHECK_LAUNCH(steps == 1 ? "k_vc_step1" : "k_vc_pass");
     return CBDG_OK;
@@ -705,7 +717,7 @@ int vc_steps(bool f32) { return f32 ? kVcSteps<float> : kVcSteps<double>; }
 
 int launch_vc(const VcArgs &A, int steps, bool f32, hipStream_t st)
 {
-    if (steps != 1 && steps != vc_steps(f32)) return fail(CBDG_EINVAL, "vector-contiguous pass: %d steps", steps);
+    if (steps < 1 || steps > vc_steps(f32)) return fail(CBDG_EINVAL, "vector-contiguous pass: %d steps", steps);
     if (A.Dv * 16 > INT32_MAX) return fail(CBDG_EINVAL, "vector-contiguous pass: lattice too large");
     return f32 ? launch_vc_t<float>(A, steps, st) : launch_vc_t<double>(A, steps, st);
 }

@@ -122,15 +122,15 @@ def test_light_cone_site_count_is_exact(Lx, Ly, bcx, bcy):
 
 
 def test_vector_contiguous_pass_schedule():
-    """N/2 steps as the first step, passes of K steps from step 2 and single
-    steps for the rest; bytes per pass = cones of a_{n-2}, a_{n-1} read and
-    of a_{n+K-2}, a_{n+K-1} written."""
+    """N/2 steps as the first step, passes of K steps from step 2, the
+    remainder in one shorter pass (two or more steps) or a single step; bytes
+    per pass = cones of a_{n-2}, a_{n-1} read and of the last two written."""
     import bench_forms
     L, sites = 256, np.array([0, 300, 65535])
-    for N, K, passes, singles in ((1024, 6, 85, 1), (2048, 7, 146, 1), (1024, 3, 170, 1), (14, 6, 1, 0),
-                                  (12, 6, 0, 5)):
+    for N, K, passes, tail, singles in ((1024, 7, 73, 0, 0), (2048, 7, 146, 0, 1), (1024, 6, 85, 0, 1),
+                                        (512, 7, 36, 3, 0), (14, 6, 1, 0, 0), (12, 6, 0, 5, 0), (6, 3, 0, 2, 0)):
         launches, moved, streamed = bench_forms.vc_traffic(sites, L, L, 0, 0, N // 2, K)
-        assert launches == 1 + passes + singles
+        assert launches == 1 + passes + (tail > 0) + singles
         assert streamed == 3 * L * L * (N // 2) * 3
 
         def D(R):
@@ -140,6 +140,9 @@ def test_vector_contiguous_pass_schedule():
         for _ in range(passes):
             want += D(n - 2) + D(n - 1) + D(n + K - 2) + D(n + K - 1)
             n += K
+        if tail:
+            want += D(n - 2) + D(n - 1) + D(n + tail - 2) + D(n + tail - 1)
+            n += tail
         for _ in range(singles):
             want += D(n - 2) + D(n - 1) + D(n)
             n += 1
