@@ -48,6 +48,22 @@ def test_vc_matches_oracle_and_direct(Lx, Ly, bcx, bcy, tile, N):
     assert np.all(he[:, 0::2] == 0)
 
 
+@pytest.mark.parametrize("Lx,Ly,bcx,bcy,N", [
+    (64, 1, 0, 0, 30),      # one row: every halo row is outside the lattice
+    (64, 2, 0, 0, 31),      # two rows
+    (64, 3, 0, 1, 33),      # three rows, periodic in y (the fewest a periodic direction has)
+    (128, 1, 1, 0, 24),     # one periodic row
+    (256, 3, 0, 0, 16),
+])
+def test_vc_degenerate_lattices(Lx, Ly, bcx, bcy, N):
+    w = W.small_random(Lx, Ly, N=N, seed=Lx + Ly + 7 * bcy, bc_x=bcx, bc_y=bcy)
+    ee, he, a, b = _run(w, N, 100)
+    d_ee, d_he, _, _ = _run(w, N, 100, algorithm=DIRECT)
+    o_ee, o_he = oracle.workload_moments(w, a, b)
+    assert maxdiff(ee, o_ee) <= TOL_MOMENT and maxdiff(he, o_he) <= TOL_MOMENT
+    assert maxdiff(ee, d_ee) <= 1e-12 and maxdiff(he, d_he) <= 1e-12
+
+
 @pytest.mark.parametrize("N", list(range(4, 22)) + [25, 26, 33, 34, 40])
 def test_vc_every_split_of_the_steps(N):
     """N/2 steps taken as the first step, passes of several steps and the
