@@ -173,7 +173,8 @@ int cbdg_op_bounds(const cbdg_op *op, cbdg_bounds *out);
  * vectors at `precision` with `algorithm` (host out): the tile's vector
  * buffers (four for real operators with uniform hopping, whose recursion
  * advances several steps per launch; two otherwise), plus FP64 partial sums
- * for DOUBLING.  EINVAL for DOUBLING when b != 0. */
+ * for DOUBLING and, where the vector-contiguous passes apply, a packed copy
+ * of the coefficients.  EINVAL for DOUBLING when b != 0. */
 int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision,
                                 int32_t algorithm, size_t *bytes);
 
@@ -182,7 +183,11 @@ int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precisi
  * of eq. (ref2):  a_0 = |s,e>,  a_1 = Ht a_0,  a_n = 2 Ht a_{n-1} - a_{n-2},
  * mu_ee[k][n] = <s,e|a_n>,  mu_he[k][n] = <s,h|a_n>.
  * The start vectors are processed in tiles of `tile` vectors; all tiles run
- * inside this call.
+ * inside this call.  Real operators with uniform hopping under DOUBLING on
+ * lattices with Lx = 64 W (FP64: W = 1, 2, 4; FP32_ACC64: W = 2, 4) store a
+ * tile vector by vector and fuse seven recursion steps per launch, each
+ * vector clipped to its own light cone; the site values equal those of the
+ * other passes bit for bit, the doubling sums agree to rounding.
  *   start_sites  [n_start] int32 lattice sites (duplicates allowed)
  *   n_start      >= 0 (0: nothing is done)
  *   N            number of moments, >= 1

@@ -5,24 +5,26 @@
 // other.  A wavefront holds one vector and one segment of rows; lane l owns
 // the W = Lx/64 neighbouring columns lW .. lW+W-1 of every row.  Inside a row
 // the pairs are ordered so that every load and store instruction of a
-// wavefront moves one contiguous 1 KB block (16 bytes per lane; pair_pos).  The x-neighbours of a lane's outer columns are
-// the outer columns of lanes l-1 and l+1, moved across the wavefront by DPP
-// wave shifts (rotations for periodic x).  Against the vector-major passes
-// (lanes = vectors, strips widened by the halo of every fused step):
-//   - a three-step pass computes the intermediate vectors a_n and a_{n+1}
-//     once per site; only the two rows at each end of a row segment are
-//     computed twice;
-//   - a lane holds W pairs per row instead of W + 6, so the FP64 three-step
-//     pass runs two wavefronts per SIMD;
+// wavefront moves one contiguous 1 KB block (16 bytes per lane; pair_pos).
+// The x-neighbours of a lane's outer columns are the outer columns of lanes
+// l-1 and l+1, moved across the wavefront by DPP wave shifts (rotations for
+// periodic x).  Against the vector-major passes (lanes = vectors, strips
+// widened by the halo of every fused step):
+//   - a pass of K steps computes each intermediate vector once per site;
+//     only the K-1 rows at each end of a row segment are computed twice, so
+//     K = 7 fused steps cost little more arithmetic than seven single steps
+//     while the vectors cross HBM 4 times instead of 21;
+//   - a lane holds W pairs per row instead of W + 6, so the seven three-row
+//     windows of a pass fit one wavefront per SIMD (part in AGPRs);
 //   - a vector is clipped to its own light cone: a_n vanishes outside the
 //     diamond |x - x_b| + |y - y_b| <= n around its start site, rows outside
 //     it are skipped, and lanes outside it neither read nor write (their
 //     buffer offsets are pushed past the buffer-resource range, where loads
 //     return zero and stores are dropped);
-//   - the per-site coefficients (de, Delta/a) are vector loads from a packed
-//     copy in the same row layout (L1/L2 hits: every vector reads the same
-//     copy) instead of wave-uniform scalar loads; with b = 0 (the doubling
-//     identities need it) the hole diagonal is exactly -de.
+//   - the per-site coefficients (de, Delta/a) come from a packed copy in the
+//     same row layout (every vector reads the same copy, from L2) through a
+//     ring in LDS instead of wave-uniform scalar loads; with b = 0 (the
+//     doubling identities need it) the hole diagonal is exactly -de.
 // Every site's value is computed by the same apply_uniform/cheb_combine
 // arithmetic as the vector-major kernels, so the vectors are bitwise the
 // same; the doubling partials are summed in another (fixed) order.
@@ -367,7 +369,12 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 }
 
 // Steps per pass and the wavefronts per SIMD the compiler must fit (its
-// registers: 512 / waves per lane).
+// registers: 512 / waves per lane).  One 1024-vector tile of the 256x256
+// workload (first / middle tile, ms; FP64 at N = 1024, FP32 at N = 2048):
+// FP64 three steps 99 / 117, four 81 / 95, five 69 / 80, six 55 / 65, seven
+// 46.7 / 54.9, eight 47.4 / 55.4; FP32 five 85 / 91, six 78 / 85, seven
+// 72 / 78, eight 73 / 79.  At one wavefront per SIMD the registers hold the
+// windows of all levels (part in AGPRs); two per SIMD would need K <= 3.
 #ifndef CBDG_VC_K_F64
 #define CBDG_VC_K_F64 7
 #endif
@@ -381,7 +388,9 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 #define CBDG_VC_OCC_F32 1
 #endif
 template <typename T> constexpr int kVcSteps = sizeof(T) == 8 ? CBDG_VC_K_F64 : CBDG_VC_K_F32;
-// Trips ahead that the a_{n-1} and a_{n-2} rows are loaded
+// Trips ahead that the a_{n-1} and a_{n-2} rows are loaded (FP64 six steps:
+// 55.0 ms one and one, 51.9 three and two; at seven steps the deeper rings
+// no longer fit the registers.  FP32 seven steps: 73.2 -> 71.9)
 #ifndef CBDG_VC_D1_F64
 #define CBDG_VC_D1_F64 1
 #endif
@@ -409,13 +418,14 @@ template <typename T, int K> struct VcOcc {
 // of level j-2 (a_{n-1} and a_{n-2} for the first two levels), so every
 // level keeps a window of its three newest rows.  Level j is computed on the
 // segment's rows and K-1-j more at each end.
-// Each trip loads the coefficient rows it needs first, then the a_{n-2} row
-// and the a_{n-1} row of a later trip.  The a_{n-1} rows sit in a ring of four
-// and the a_{n-2} rows in a ring of two, rotated by unrolling the loop four
-// times: a register that a load is still filling is never copied, so no trip
-// waits for the loads it issued itself.  The trip count is rounded up to a
-// multiple of four; the extra trips compute rows past the segment that are
-// neither stored nor summed.
+// Each trip stores the coefficient row loaded on the trip before into the
+// LDS ring and loads the next one, then loads the a_{n-2} and a_{n-1} rows
+// of later trips.  The a_{n-1} rows sit in a ring of 3 + D1 and the a_{n-2}
+// rows in a ring of 1 + D2, rotated by unrolling the loop U times: a register
+// that a load is still filling is never copied, so no trip waits for the
+// loads it issued itself.  The trip count is rounded up to a multiple of U;
+// the extra trips compute rows past the segment that are neither stored nor
+// summed.
 // VAR: a shorter last pass of A.nlev (2 .. K-1) levels, the rest skipped.
 template <typename T, int W, bool BCX, bool BCY, int K, bool VAR>
 __global__ __launch_bounds__(kVcBlock) __attribute__((amdgpu_waves_per_eu(VcOcc<T, K>::waves)))
@@ -435,7 +445,6 @@ void k_vc_pass(VcArgs A)
     const auto r2 = vec_rsrc<T>(A.a2, w.b, A.Dv);
     const auto ro1 = vec_rsrc<T>(A.out, w.b, A.Dv);
     const auto ro2 = vec_rsrc<T>(A.out2, w.b, A.Dv);
-    const S *pc = reinterpret_cast<const S *>(A.coef);
     const T th = T(A.th);
     const int y0 = w.y0, y1 = w.y1;
 
