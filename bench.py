@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("stencil.hpp", "step.hpp", "recursion.hip", "common.hpp"):
+    for f in ("stencil.hpp", "step.hpp", "recursion.hip", "vcstep.hip", "common.hpp"):
         with open(os.path.join(ROOT, "paper_1007_1609_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

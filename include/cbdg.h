@@ -186,8 +186,8 @@ int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precisi
  * inside this call.  Real operators with uniform hopping under DOUBLING on
  * lattices with Lx = 64 W (FP64: W = 1, 2, 4; FP32_ACC64: W = 2, 4) store a
  * tile vector by vector and fuse seven recursion steps per launch, each
- * vector clipped to its own light cone; the site values equal those of the
- * other passes bit for bit, the doubling sums agree to rounding.
+ * vector clipped to its own light cone; the site values and doubling sums
+ * agree with those of the other passes to rounding.
  *   start_sites  [n_start] int32 lattice sites (duplicates allowed)
  *   n_start      >= 0 (0: nothing is done)
  *   N            number of moments, >= 1

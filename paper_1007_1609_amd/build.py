@@ -1,4 +1,5 @@
-"""Compiles libcbdg.so (the HIP kernels and the C ABI) for gfx950 in-tree.
+"""Compiles libcbdg.so (the HIP kernels and the C ABI) for gfx950 in-tree, and
+the native runner cbdg_moments_run (host code that calls the C ABI) beside it.
 
     python paper_1007_1609_amd/build.py
 """
@@ -15,6 +16,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcbdg.so")
+RUNNER = os.path.join(HERE, "cbdg_moments_run")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+CXX = os.environ.get("CXX", "g++")
 OBJ = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("CBDG_OFFLOAD_ARCH", "gfx950")
 
@@ -52,9 +56,25 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
+    build_runner()
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", RUNNER)
     return LIB
+
+
+def build_runner() -> str:
+    """The native runner of one moments call (host code only, linked to
+    libcbdg.so in the same folder)."""
+    src = os.path.join(CSRC, "moments_run.cpp")
+    tmp = RUNNER + ".tmp%d" % os.getpid()
+    cmd = [CXX, "-O2", "-std=c++17", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
+           "-I", INCLUDE, src, "-L", HERE, "-lcbdg", "-L", os.path.join(ROCM, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("runner build failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, RUNNER)
+    return RUNNER
 
 
 if __name__ == "__main__":

@@ -1487,14 +1487,13 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
     auto vc_tile = [&](int Bt) -> bool {
         return !C && !op->general && doubling && !nb_ee && two && vc_width(op->Lx, f32) > 0 && Bt >= kVcMinVectors;
     };
+    // No clearing: the passes read nothing the tile has not written.  With
+    // one row segment per vector a pass writes its moments itself; with more
+    // the reduction kernels add the segments' partials.
     auto run_tile_vc = [&](int Bt, int64_t Bp, const int32_t *ts, double *mee, double *mhe) -> int {
-        using SR = typename Storage<T, false>::type;
-        const int64_t nz = (int64_t)Bt * L2;
-        const unsigned zgrid = (unsigned)std::min<int64_t>(ceil_div(nz, kBlock), 8192);
-        for (int i = 0; i < 4; ++i) {
-            hipLaunchKernelGGL((k_zero<T, false>), dim3(zgrid), dim3(kBlock), 0, st, reinterpret_cast<SR *>(buf[i]), nz);
-            CBDG_CHECK_LAUNCH("k_zero");
-        }
+        auto vc_reduce = [&](int segs, int n, int ns) -> int {
+            return segs == 1 ? CBDG_OK : reduce(segs, n, ns, Bt, Bp, mee, mhe);
+        };
         int rc = launch_vc_seed(buf[0], L2, op->Lx, f32, Bt, L2, ts, mee, mhe, N, st);
         if (rc) return rc;
         VcArgs V{};
@@ -1510,12 +1509,12 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
         S *P2 = buf[0], *P1 = buf[1], *Q0 = buf[2], *Q1 = buf[3];
         V.part = part; V.pstride = pstride;
         V.n = 1; V.a1 = P2; V.a2 = P2; V.out = P1; V.n_segs = segs1;
-        if ((rc = launch_vc(V, 1, f32, st)) || (rc = reduce(segs1, 1, 1, Bt, Bp, mee, mhe))) return rc;
+        if ((rc = launch_vc(V, 1, f32, st)) || (rc = vc_reduce(segs1, 1, 1))) return rc;
         int n = 2;
         V.n_segs = segsK;
         for (; n + KS - 1 <= n_steps; n += KS) {
             V.n = n; V.a2 = P2; V.a1 = P1; V.out = Q0; V.out2 = Q1;
-            if ((rc = launch_vc(V, KS, f32, st)) || (rc = reduce(segsK, n, KS, Bt, Bp, mee, mhe))) return rc;
+            if ((rc = launch_vc(V, KS, f32, st)) || (rc = vc_reduce(segsK, n, KS))) return rc;
             std::swap(P2, Q0);
             std::swap(P1, Q1);
         }
@@ -1523,16 +1522,16 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             // the steps left, fewer than a full pass, in one shorter pass
             const int rest = n_steps - n + 1;
             V.n = n; V.a2 = P2; V.a1 = P1; V.out = Q0; V.out2 = Q1;
-            if ((rc = launch_vc(V, rest, f32, st)) || (rc = reduce(segsK, n, rest, Bt, Bp, mee, mhe))) return rc;
+            if ((rc = launch_vc(V, rest, f32, st)) || (rc = vc_reduce(segsK, n, rest))) return rc;
             n += rest;
         }
         V.n_segs = segs1;
         for (; n <= n_steps; ++n) {
             V.n = n; V.a1 = P1; V.a2 = P2; V.out = P2;
-            if ((rc = launch_vc(V, 1, f32, st)) || (rc = reduce(segs1, n, 1, Bt, Bp, mee, mhe))) return rc;
+            if ((rc = launch_vc(V, 1, f32, st)) || (rc = vc_reduce(segs1, n, 1))) return rc;
             std::swap(P1, P2);
         }
-        return CBDG_OK;
+        return bound_moments(mee, mhe, (int64_t)Bt * N, false, false, moment_limit(f32), st);
     };
     if (n_start > 0 && vc_tile((int)std::min<int64_t>(tile, n_start))) {
         int rc = launch_vc_coef(onsite, vc_coef, op->Lx, f32, L2, st);
@@ -1548,8 +1547,6 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             if (vc_tile(Bt)) {
                 int rc = run_tile_vc(Bt, Bp, ts, mee, mhe);
                 if (rc) return rc;
-                if ((rc = bound_moments(mee, mhe, (int64_t)Bt * N, false, false, moment_limit(std::is_same<T, float>::value), st)))
-                    return rc;
                 continue;
             }
         }
@@ -1914,8 +1911,9 @@ extern "C" int cbdg_chebyshev_moments_static(const cbdg_op *op, const int32_t *s
     void *ws = nullptr;
     if ((rc = static_scratch(dev, &ws))) return rc;
     // every buffer the recursion reads is written first within the call
-    // (tile buffers cleared per tile, bounding box, partial and run sums), so
-    // the previous call's contents need no clearing
+    // (tile buffers cleared per tile or written before they are read,
+    // bounding box, partial and run sums), so the previous call's contents
+    // need no clearing
     return cbdg_chebyshev_moments(op, start_sites, n_start, N, tile, precision, algorithm, ws, need, mu_ee, mu_he,
                                   stream);
 }

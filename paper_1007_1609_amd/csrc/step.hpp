@@ -78,7 +78,9 @@ constexpr int kMaxPassSteps = 8;
 // Ht a_0 and moment 1) and the partials of step n; `steps` = K = 2 ..
 // vc_steps() writes a_{n+K-2} (A.out) and a_{n+K-1} (A.out2) from a_{n-2}
 // (A.a2) and a_{n-1} (A.a1) and the partials of steps n .. n+K-1
-// ([n_segs][3][Bp] each).
+// ([n_segs][3][Bp] each), or with n_segs = 1 the moments 2m-1 and 2m of
+// those steps m themselves.  The passes read only what the tile's earlier
+// passes (and the seed) wrote: the buffers need no clearing.
 struct VcArgs {
     const void *a1, *a2;
     void *out, *out2;
@@ -103,7 +105,7 @@ int vc_segments(int Ly, int Bt, int steps);
 int launch_vc(const VcArgs &A, int steps, bool f32, hipStream_t st);
 // Steps of a full multi-step vector-contiguous pass (3 .. kMaxPassSteps).
 int vc_steps(bool f32);
-// a_0 and the zeroth moments of a tile (buffer zeroed beforehand)
+// a_0 (its whole start row) and the zeroth moments of a tile
 int launch_vc_seed(void *a0, int64_t Dv, int Lx, bool f32, int Bt, int64_t L2, const int32_t *sites, double *mu_ee,
                    double *mu_he, int N, hipStream_t st);
 // the packed coefficients (L2 pairs of the recursion's type) from the operator's

@@ -21,18 +21,22 @@
 //     it are skipped, and lanes outside it neither read nor write (their
 //     buffer offsets are pushed past the buffer-resource range, where loads
 //     return zero and stores are dropped);
-//   - the per-site coefficients (de, Delta/a) come from a packed copy in the
-//     same row layout (every vector reads the same copy, from L2) through a
-//     ring in LDS instead of wave-uniform scalar loads; with b = 0 (the
-//     doubling identities need it) the hole diagonal is exactly -de.
-// Every site's value is computed by the same apply_uniform/cheb_combine
-// arithmetic as the vector-major kernels, so the vectors are bitwise the
-// same; the doubling partials are summed in another (fixed) order.
+//   - the per-site coefficients (2 de, 2 Delta/a) come from a packed copy in
+//     the same row layout (every vector reads the same copy, from L2) through
+//     a ring in LDS instead of wave-uniform scalar loads; with b = 0 (the
+//     doubling identities need it) the hole diagonal is exactly -de, and the
+//     factor 2 of eq. (ref2), folded into the coefficients, saves the product
+//     by t/a and the separate combination with a_{n-2} of every component.
+// The first step and single steps compute a site exactly as the vector-major
+// kernels do; the passes of several steps round 2 Ht a_{n-1} - a_{n-2} in
+// three fused multiply-adds instead, and the doubling partials are summed in
+// another (fixed) order.
 //
-// Buffers outside the light cones hold zeros: the tile's buffers are zeroed
-// before the first step, and a pass that writes a vector into a buffer
-// covers the whole cone of the vector that buffer held before (an earlier
-// step, a smaller diamond).
+// Nothing is read that the tile has not written: a load of a_m covers the
+// rows of the diamond of radius m (on open rows only the lanes the diamond
+// touches), the store of a_m the same rows and lanes (with the zeros a lane
+// holds outside the diamond), and a_0 is seeded as its whole start row.
+// The buffers need no clearing between tiles.
 #include "step.hpp"
 
 #include <algorithm>
@@ -224,6 +228,48 @@ __device__ __forceinline__ void apply_row(const typename Storage<T, false>::type
     }
 }
 
+// Whether the passes of several steps fold the factor 2 of eq. (ref2) into
+// their coefficients (2 de, 2 Delta/a and 2 t/a are exact): 2 Ht c - p of a
+// component is then three fused multiply-adds after the neighbour sum
+// instead of a product, two fused multiply-adds and the combination (FP32,
+// 256x256, 16 tiles of 1024 vectors at N = 2048: 1203 -> 1148 ms; FP64 at
+// N = 1024 unchanged within the run-to-run spread, 3189 / 3214 ms).
+#ifndef CBDG_VC_FOLD
+#define CBDG_VC_FOLD 1
+#endif
+template <typename T> constexpr T kCoefScale = CBDG_VC_FOLD ? T(2) : T(1);
+
+// 2 Ht c - p at one site from the doubled coefficients cf = (2 de, 2 Delta/a)
+// and th2 = 2 t/a (the hole diagonal is -2 de)
+template <typename T>
+__device__ __forceinline__ Pair<T, false> step_site(const typename Storage<T, false>::type &cf, T th2,
+                                                     const Pair<T, false> &c, const Pair<T, false> &l,
+                                                     const Pair<T, false> &r, const Pair<T, false> &d,
+                                                     const Pair<T, false> &u, const Pair<T, false> &p)
+{
+#pragma clang fp contract(off)
+    const T se = (l.e + r.e) + (d.e + u.e), sh = (l.h + r.h) + (d.h + u.h);
+    Pair<T, false> y;
+    y.e = fma_t(cf.x, c.e, fma_t(cf.y, c.h, fma_t(-th2, se, -p.e)));
+    y.h = fma_t(-cf.x, c.h, fma_t(cf.y, c.e, fma_t(th2, sh, -p.h)));
+    return y;
+}
+
+// one site of a pass: 2 Ht c - p from the ring's coefficients
+template <typename T>
+__device__ __forceinline__ Pair<T, false> pass_site(const typename Storage<T, false>::type &cf, T th,
+                                                     const Pair<T, false> &c, const Pair<T, false> &l,
+                                                     const Pair<T, false> &r, const Pair<T, false> &d,
+                                                     const Pair<T, false> &u, const Pair<T, false> &p)
+{
+    if constexpr (CBDG_VC_FOLD) {
+        return step_site<T>(cf, th, c, l, r, d, u, p);
+    } else {
+        const OnSite<T> o{cf.x, -cf.x, cf.y, T(0)};
+        return cheb_combine<T, false>(apply_uniform<T, false>(o, th, c, l, r, d, u), p, false);
+    }
+}
+
 // <v|v>, <v|c> and B(v, c) of one site added to the partial sums, as two
 // fused multiply-adds each (no other contraction: the sums do not depend on
 // how the compiler schedules a pass)
@@ -243,6 +289,27 @@ __device__ __forceinline__ void wave_sum(double *d)
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
         for (int k = 0; k < K; ++k) d[k] += __shfl_xor(d[k], off, kWave);
+    }
+}
+
+// With one row segment per vector the wavefront's sums are the whole dot
+// products of step m, and its lane 0 writes the moments of the doubling
+// identities itself (the arithmetic of the reduction kernels, which the
+// passes need for two or more segments):
+//   mu_ee[2m] = 2 <a_m|a_m> - mu_ee[0],  mu_he[2m] = 0,
+//   mu_ee[2m-1] = 2 <a_m|a_{m-1}> - mu_ee[1],
+//   mu_he[2m-1] = 2 (-1)^m B(a_m, a_{m-1}) - mu_he[1]   (m >= 2).
+__device__ __forceinline__ void vc_moments(const VcArgs &A, int b, int m, const double *dm)
+{
+    const int64_t row = (int64_t)b * A.N;
+    const double s0 = 0.0 + dm[0], s1 = 0.0 + dm[1], s2 = 0.0 + dm[2];
+    if (2 * m < A.N) {
+        A.mu_ee[row + 2 * m] = 2.0 * s0 - A.mu_ee[row];
+        A.mu_he[row + 2 * m] = 0.0;
+    }
+    if (m >= 2 && 2 * m - 1 < A.N) {
+        A.mu_ee[row + 2 * m - 1] = 2.0 * s1 - A.mu_ee[row + 1];
+        A.mu_he[row + 2 * m - 1] = ((m & 1) ? -2.0 : 2.0) * s2 - A.mu_he[row + 1];
     }
 }
 
@@ -331,6 +398,10 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 #pragma unroll 1
     for (int r = y0; r < y1; ++r) {
         load_coef<T, W>(pc, g.template coef_row<T>(r), c0);
+        if constexpr (CBDG_VC_FOLD) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) { c0[k].x *= T(0.5); c0[k].y *= T(0.5); }
+        }
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (!FIRST) load_row<T, W>(r2, g.template offset<T, W>(min(r + 1, y1 - 1), n - 2), pn);
         load_row<T, W>(r1, g.template offset<T, W>(min(r + 2, y1), n - 1), nx);
@@ -363,8 +434,12 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
     }
     wave_sum<3>(d);
     if (w.lane == 0) {
+        if (A.n_segs == 1) {
+            vc_moments(A, w.b, n, d);
+        } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) A.part[((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[k];
+            for (int k = 0; k < 3; ++k) A.part[((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[k];
+        }
     }
 }
 
@@ -380,6 +455,12 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 #endif
 #ifndef CBDG_VC_K_F32
 #define CBDG_VC_K_F32 7
+#endif
+// Coefficient ring of 8 slots (a power of two: the slot of a row is a mask
+// of its index, not a remainder by K = 7) instead of K; 131 KB of LDS per
+// workgroup of four FP64 wavefronts at W = 4
+#ifndef CBDG_VC_RING_POW2
+#define CBDG_VC_RING_POW2 1
 #endif
 #ifndef CBDG_VC_OCC_F64
 #define CBDG_VC_OCC_F64 1
@@ -445,7 +526,7 @@ void k_vc_pass(VcArgs A)
     const auto r2 = vec_rsrc<T>(A.a2, w.b, A.Dv);
     const auto ro1 = vec_rsrc<T>(A.out, w.b, A.Dv);
     const auto ro2 = vec_rsrc<T>(A.out2, w.b, A.Dv);
-    const T th = T(A.th);
+    const T th = kCoefScale<T> * T(A.th);
     const int y0 = w.y0, y1 = w.y1;
 
     // a_{n-1} rows r-1 .. r+1 and the D1 rows in flight; a_{n-2} row r and
@@ -454,10 +535,12 @@ void k_vc_pass(VcArgs A)
     constexpr int R1 = 3 + D1, R2 = 1 + D2;
     P ra[R1][W], rp[R2][W];
     P lv[K - 1][3][W];              // level j: rows r-j-2, r-j-1, r-j
-    // Coefficient rows r-K+1 .. r in a ring in LDS (slot = row mod K), one
-    // row loaded per trip into registers one trip ahead of its use
+    // Coefficient rows r-K+1 .. r in a ring in LDS of KR >= K slots (slot =
+    // row mod KR), one row loaded per trip into registers one trip ahead of
+    // its use
     constexpr int NQ = W / kPer<T>;  // 16-byte chunks per lane and row
-    __shared__ U4 ring_all[kVcWaves][K][NQ][kWave];
+    constexpr int KR = CBDG_VC_RING_POW2 ? (K <= 4 ? 4 : 8) : K;
+    __shared__ U4 ring_all[kVcWaves][KR][NQ][kWave];
     U4 (*ring)[NQ][kWave] = ring_all[threadIdx.x / kWave];
     const U4 *pc4 = reinterpret_cast<const U4 *>(A.coef);
     auto coef_chunks = [&](int v, U4 *cp) __attribute__((always_inline)) {
@@ -465,7 +548,10 @@ void k_vc_pass(VcArgs A)
 #pragma unroll
         for (int q = 0; q < NQ; ++q) cp[q] = pc4[at + q * kWave];
     };
-    auto slot = [&](int v) -> int { return (v % K + K) % K; };
+    auto slot = [&](int v) -> int {
+        if constexpr (KR == 4 || KR == 8) return v & (KR - 1);
+        else return (v % KR + KR) % KR;
+    };
     U4 cpre[NQ];
     for (int v = y0 - 2 * (K - 1); v < y0 - (K - 1); ++v) {
         coef_chunks(v, cpre);
@@ -536,9 +622,13 @@ void k_vc_pass(VcArgs A)
                 // (loaded as zero, or computed so on earlier trips), so with
                 // the hopping switched off for it the stencil gives zero
                 // without a mask: no other row reaches it.
-                apply_row<T, W, BCX>(cj, g.in_lattice(s) ? th : T(0), cc, dd, uu, v);
+                const T ths = g.in_lattice(s) ? th : T(0);
+                const P hl = dpp_pair<BCX ? kRor1 : kShr1>(cc[W - 1]);
+                const P hr = dpp_pair<BCX ? kRol1 : kShl1>(cc[0]);
 #pragma unroll
-                for (int k = 0; k < W; ++k) v[k] = cheb_combine<T, false>(v[k], pp[k], false);
+                for (int k = 0; k < W; ++k)
+                    v[k] = pass_site<T>(cj[k], ths, cc[k], k > 0 ? cc[k - 1] : hl, k < W - 1 ? cc[k + 1] : hr,
+                                        dd[k], uu[k], pp[k]);
                 if (own) {
 #pragma unroll
                     for (int k = 0; k < W; ++k)
@@ -557,11 +647,8 @@ void k_vc_pass(VcArgs A)
 #pragma unroll
                     for (int i = 0; i < kPer<T>; ++i) {
                         const int k = q * kPer<T> + i;
-                        const OnSite<T> o{cj[k].x, -cj[k].x, cj[k].y, T(0)};
-                        v[i] = cheb_combine<T, false>(
-                            apply_uniform<T, false>(o, th, cc[k], k > 0 ? cc[k - 1] : hl, k < W - 1 ? cc[k + 1] : hr,
-                                                    dd[k], uu[k]),
-                            pp[k], false);
+                        v[i] = pass_site<T>(cj[k], th, cc[k], k > 0 ? cc[k - 1] : hl, k < W - 1 ? cc[k + 1] : hr,
+                                            dd[k], uu[k], pp[k]);
                         dots3(d + 3 * j, (double)v[i].e, (double)v[i].h, (double)cc[k].e, (double)cc[k].h);
                     }
                     bst<T>(ro2, off + q * (unsigned)(kWave * 16), v);
@@ -587,17 +674,21 @@ void k_vc_pass(VcArgs A)
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (j < nlev) {
+                if (A.n_segs == 1) {
+                    vc_moments(A, w.b, n + j, d + 3 * j);
+                } else {
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    A.part[j * A.pstride + ((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[3 * j + k];
+                    for (int k = 0; k < 3; ++k)
+                        A.part[j * A.pstride + ((int64_t)w.seg * 3 + k) * A.Bp + w.b] = d[3 * j + k];
+                }
             }
         }
     }
 }
 
-// a_0 = |s_b, e> in the vector-contiguous layout (the buffer is zero), and the
-// zeroth moments; an invalid start site leaves its vector zero and its moment
-// row NaN.
+// a_0 = |s_b, e> in the vector-contiguous layout, and the zeroth moments; an
+// invalid start site leaves its vector untouched (no pass reads or writes it)
+// and its moment row NaN.
 template <typename T>
 __global__ void k_vc_seed(typename Storage<T, false>::type *a0, int64_t Dv, int Lx, int W, int Bt, int64_t L2,
                           const int32_t *sites, double *mu_ee, double *mu_he, int N)
@@ -611,8 +702,12 @@ __global__ void k_vc_seed(typename Storage<T, false>::type *a0, int64_t Dv, int 
         for (int n = 0; n < N; ++n) { mu_ee[m + n] = nan; mu_he[m + n] = nan; }
         return;
     }
+    // the whole start row: every pair the first step reads of a_0 (the
+    // owner lane's W pairs on open rows, all lanes on periodic ones)
     const int64_t y = s / Lx, x = s % Lx;
-    a0[b * Dv + y * Lx + pair_pos<T>((int)(x / W), (int)(x % W))] = typename Storage<T, false>::type{T(1), T(0)};
+    const int64_t one = pair_pos<T>((int)(x / W), (int)(x % W));
+    for (int64_t k = 0; k < Lx; ++k)
+        a0[b * Dv + y * Lx + k] = typename Storage<T, false>::type{k == one ? T(1) : T(0), T(0)};
     mu_ee[m] = 1.0;
     mu_he[m] = 0.0;
 }
@@ -625,7 +720,8 @@ __global__ void k_vc_coef(const OnSite<T> *__restrict__ ons, typename Storage<T,
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < L2; s += (int64_t)gridDim.x * blockDim.x) {
         const int64_t y = s / Lx, x = s % Lx;
         const OnSite<T> o = ons[s];
-        pc[y * Lx + pair_pos<T>((int)(x / W), (int)(x % W))] = typename Storage<T, false>::type{o.de, o.dr};
+        pc[y * Lx + pair_pos<T>((int)(x / W), (int)(x % W))] =
+            typename Storage<T, false>::type{kCoefScale<T> * o.de, kCoefScale<T> * o.dr};
     }
 }
 

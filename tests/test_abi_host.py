@@ -110,3 +110,19 @@ def test_python_errors_carry_message():
     with pytest.raises(L.CbdgError) as e:
         L.cbdg_moments_workspace_size(None, 0, 0, 0, None)
     assert e.value.code == L.CBDG_EINVAL and "moments_workspace_size" in str(e.value)
+
+
+def test_native_runner_links_the_library_and_checks_its_arguments():
+    """The native runner (host code over the C ABI) is built beside the library,
+    resolves libcbdg.so from its own folder, and rejects bad arguments before
+    any HIP call."""
+    runner = os.path.join(ROOT, "paper_1007_1609_amd", "cbdg_moments_run")
+    if not os.path.exists(runner):
+        sys_path = os.path.join(ROOT, "paper_1007_1609_amd")
+        subprocess.check_call(["python", "-c", "import build; build.build_runner()"], cwd=sys_path)
+    out = subprocess.run(["ldd", runner], capture_output=True, text=True).stdout
+    assert re.search(r"libcbdg\.so => %s" % re.escape(os.path.join(ROOT, "paper_1007_1609_amd")), out), out
+    for args in ([], ["256", "256", "1024", "1024", "0", "fp64"], ["64", "4", "16", "8", "300", "fp64"],
+                 ["64", "4", "16", "8", "10", "bf16"]):
+        r = subprocess.run([runner, *args], capture_output=True, text=True)
+        assert r.returncode == 2, (args, r.stdout, r.stderr)
