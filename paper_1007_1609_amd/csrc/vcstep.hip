@@ -456,6 +456,12 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 #ifndef CBDG_VC_K_F32
 #define CBDG_VC_K_F32 7
 #endif
+#ifndef CBDG_VC_DEFER_F64
+#define CBDG_VC_DEFER_F64 1
+#endif
+#ifndef CBDG_VC_DEFER_F32
+#define CBDG_VC_DEFER_F32 0
+#endif
 // Coefficient ring of 8 slots (a power of two: the slot of a row is a mask
 // of its index, not a remainder by K = 7) instead of K; 131 KB of LDS per
 // workgroup of four FP64 wavefronts at W = 4
@@ -501,7 +507,7 @@ template <typename T, int K> struct VcOcc {
 // segment's rows and K-1-j more at each end.
 // Each trip stores the coefficient row loaded on the trip before into the
 // LDS ring and loads the next one, then loads the a_{n-2} and a_{n-1} rows
-// of later trips.  The a_{n-1} rows sit in a ring of 3 + D1 and the a_{n-2}
+// of later trips (FP64: and stores the two rows the trip before computed).  The a_{n-1} rows sit in a ring of 3 + D1 and the a_{n-2}
 // rows in a ring of 1 + D2, rotated by unrolling the loop U times: a register
 // that a load is still filling is never copied, so no trip waits for the
 // loads it issued itself.  The trip count is rounded up to a multiple of U;
@@ -574,6 +580,17 @@ void k_vc_pass(VcArgs A)
 #pragma unroll
     for (int i = 0; i < 3 * K; ++i) d[i] = 0.0;
 
+    // FP64: the two rows a trip stores (levels K-2 and K-1) go out on the next
+    // trip, after its loads, so that a wait for those loads never waits for
+    // these stores as well (256x256, 64 tiles of 1024 vectors: 3170 -> 3109
+    // ms; FP32 1103 -> 1125 ms at N = 2048, so FP32 stores at once).  The
+    // offset past the buffer range drops the stores of trips that had nothing
+    // to store.
+    constexpr bool DEF = !VAR && (sizeof(T) == 8 ? CBDG_VC_DEFER_F64 : CBDG_VC_DEFER_F32);
+    P pend5[W], pend6[W];
+    unsigned off5 = kOut, off6 = kOut;
+#pragma unroll
+    for (int k = 0; k < W; ++k) pend5[k] = pend6[k] = zero_pair<T, false>();
     // one trip: w0, w1, w2 = a_{n-1} rows r-1, r, r+1; row r+1+D1 is loaded
     // into w3; p = a_{n-2} row r; row r+D2 is loaded into pn
     auto trip = [&](int r, const P *w0, const P *w1, const P *w2, P *w3, const P *p, P *pn)
@@ -587,6 +604,10 @@ void k_vc_pass(VcArgs A)
         __builtin_amdgcn_sched_barrier(0);
         load_row<T, W>(r2, g.template offset<T, W>(r + D2, n - 2), pn);
         load_row<T, W>(r1, g.template offset<T, W>(r + 1 + D1, n - 1), w3);
+        if constexpr (DEF) {
+            store_row<T, W>(ro1, off5, pend5);
+            store_row<T, W>(ro2, off6, pend6);
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -629,12 +650,31 @@ void k_vc_pass(VcArgs A)
                 for (int k = 0; k < W; ++k)
                     v[k] = pass_site<T>(cj[k], ths, cc[k], k > 0 ? cc[k - 1] : hl, k < W - 1 ? cc[k + 1] : hr,
                                         dd[k], uu[k], pp[k]);
+                if (DEF && j == K - 2) {
+                    off5 = own ? g.template offset<T, W>(s, n + j) : kOut;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) pend5[k] = v[k];
+                }
                 if (own) {
 #pragma unroll
                     for (int k = 0; k < W; ++k)
                         dots3(d + 3 * j, (double)v[k].e, (double)v[k].h, (double)cc[k].e, (double)cc[k].h);
-                    if (j == nlev - 2) store_row<T, W>(ro1, g.template offset<T, W>(s, n + j), v);
+                    if (!DEF && j == nlev - 2) store_row<T, W>(ro1, g.template offset<T, W>(s, n + j), v);
                     if (VAR && j == nlev - 1) store_row<T, W>(ro2, g.template offset<T, W>(s, n + j), v);
+                }
+            } else if constexpr (DEF) {
+                // the last level, kept for the next trip's store
+                off6 = kOut;
+                if (own) {
+                    off6 = g.template offset<T, W>(s, n + j);
+                    const P hl = dpp_pair<BCX ? kRor1 : kShr1>(cc[W - 1]);
+                    const P hr = dpp_pair<BCX ? kRol1 : kShl1>(cc[0]);
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        pend6[k] = pass_site<T>(cj[k], th, cc[k], k > 0 ? cc[k - 1] : hl, k < W - 1 ? cc[k + 1] : hr,
+                                                dd[k], uu[k], pp[k]);
+                        dots3(d + 3 * j, (double)pend6[k].e, (double)pend6[k].h, (double)cc[k].e, (double)cc[k].h);
+                    }
                 }
             } else if (own) {
                 // the last level, stored chunk by chunk
@@ -669,6 +709,10 @@ void k_vc_pass(VcArgs A)
             trip(r + u, ra[u % R1], ra[(u + 1) % R1], ra[(u + 2) % R1], ra[(u + R1 - 1) % R1], rp[u % R2],
                  rp[(u + R2 - 1) % R2]);
     }
+    if constexpr (DEF) {
+        store_row<T, W>(ro1, off5, pend5);
+        store_row<T, W>(ro2, off6, pend6);
+    }
     wave_sum<3 * K>(d);
     if (w.lane == 0) {
 #pragma unroll
@@ -693,23 +737,28 @@ template <typename T>
 __global__ void k_vc_seed(typename Storage<T, false>::type *a0, int64_t Dv, int Lx, int W, int Bt, int64_t L2,
                           const int32_t *sites, double *mu_ee, double *mu_he, int N)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= Bt) return;
+    // one thread per (vector, pair of the start row)
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)Bt * Lx) return;
+    const int b = (int)(t / Lx), k = (int)(t % Lx);
     const int64_t s = sites[b];
     const int64_t m = (int64_t)b * N;
     if (s < 0 || s >= L2) {
-        const double nan = __builtin_nan("");
-        for (int n = 0; n < N; ++n) { mu_ee[m + n] = nan; mu_he[m + n] = nan; }
+        if (k == 0) {
+            const double nan = __builtin_nan("");
+            for (int n = 0; n < N; ++n) { mu_ee[m + n] = nan; mu_he[m + n] = nan; }
+        }
         return;
     }
     // the whole start row: every pair the first step reads of a_0 (the
     // owner lane's W pairs on open rows, all lanes on periodic ones)
     const int64_t y = s / Lx, x = s % Lx;
-    const int64_t one = pair_pos<T>((int)(x / W), (int)(x % W));
-    for (int64_t k = 0; k < Lx; ++k)
-        a0[b * Dv + y * Lx + k] = typename Storage<T, false>::type{k == one ? T(1) : T(0), T(0)};
-    mu_ee[m] = 1.0;
-    mu_he[m] = 0.0;
+    const int one = pair_pos<T>((int)(x / W), (int)(x % W));
+    a0[b * Dv + y * Lx + k] = typename Storage<T, false>::type{k == one ? T(1) : T(0), T(0)};
+    if (k == 0) {
+        mu_ee[m] = 1.0;
+        mu_he[m] = 0.0;
+    }
 }
 
 // Packed (de, Delta/a) of every site in the row layout of the passes.
@@ -794,10 +843,10 @@ int launch_vc_seed(void *a0, int64_t Dv, int Lx, bool f32, int Bt, int64_t L2, c
     const int W = vc_width(Lx, f32);
     if (!W) return fail(CBDG_EUNSUPPORTED, "vector-contiguous pass: Lx = %d does not fit", Lx);
     if (f32)
-        hipLaunchKernelGGL((k_vc_seed<float>), dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_vc_seed<float>), dim3((unsigned)ceil_div((int64_t)Bt * Lx, kBlock)), dim3(kBlock), 0, st,
                            reinterpret_cast<float2 *>(a0), Dv, Lx, W, Bt, L2, sites, mu_ee, mu_he, N);
     else
-        hipLaunchKernelGGL((k_vc_seed<double>), dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_vc_seed<double>), dim3((unsigned)ceil_div((int64_t)Bt * Lx, kBlock)), dim3(kBlock), 0, st,
                            reinterpret_cast<double2 *>(a0), Dv, Lx, W, Bt, L2, sites, mu_ee, mu_he, N);
     CBDG_CHECK_LAUNCH("k_vc_seed");
     return CBDG_OK;
