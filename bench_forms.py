@@ -342,6 +342,25 @@ def complex_form(args, dev):
     return line
 
 
+def reversible_streams(N, K=6):
+    """Vector streams of one tile in the checkpoint-free reverse passes (units
+    of one vector of L2 pairs): the forward moments' minimum is counted by
+    the forward; here one more forward step (read 2, write 1), then per pass
+    the regenerated pair and the cotangent pair read and written and G read
+    and written (the first pass reads no cotangents and no G; the last,
+    shorter pass writes only G), then the sum of G over the tile."""
+    M = N // 2
+    passes = -(-M // K)
+    full = M // K
+    streams = 3 + 1
+    for p in range(passes):
+        is_full = p < full
+        reads = 2 + (0 if p == 0 else 3)
+        writes = (4 if is_full else 0) + 1
+        streams += reads + writes
+    return streams
+
+
 def adjoint_form(args, dev):
     from paper_1007_1609_amd import autograd as AG
     w = W.config4()
@@ -369,6 +388,10 @@ def adjoint_form(args, dev):
     d0 = torch.as_tensor(w.delta, device=dev)
     (_, _), t_fwd = _timed(lambda: AG.moments(eps0, d0, geom, sites, N, tile))
     g_sum, t_bwd = forward_backward()
+    # the checkpoint-free reverse passes (forward vectors regenerated backwards)
+    forward_backward(P.REVERSIBLE)
+    g_rev, t_rev = forward_backward(P.REVERSIBLE)
+    torch.cuda.empty_cache()
     # every forward vector stored (checkpoint stride 1: no segment
     # recomputation, about 70 GB of workspace per 1024-vector tile)
     forward_backward(1)
@@ -382,7 +405,13 @@ def adjoint_form(args, dev):
     AG.local_dos(mu_ee, torch.zeros(1, dtype=torch.float64, device=dev), wt).sum().backward()
     torch.cuda.synchronize()
     t_ldos = time.perf_counter() - t0
-    log("adjoint: forward %.2f s, reverse %.2f s" % (t_fwd, t_bwd))
+    log("adjoint: forward %.2f s, reverse %.2f s (checkpoints), %.2f s (regenerated vectors)" % (t_fwd, t_bwd, t_rev))
+    rev_streams = reversible_streams(N)
+    rev_b = sum(rev_streams * w.L2 * 16.0 * min(tile, w.L2 - t * tile) for t in range(-(-w.L2 // tile)))
+    reversible = {"seconds": t_rev, "over_forward": t_rev / t_fwd, "vector_streams_per_tile": rev_streams,
+                  "algorithmic_bytes": rev_b, "algorithmic_GBps": rev_b / t_rev / 1e9, "frac": rev_b / t_rev / 8e12,
+                  "max_abs_grad_diff_vs_checkpoints": float((g_rev - g_sum).abs().max()),
+                  "note": "includes the forward moments of every tile (vector-contiguous passes) and one step more"}
     n_tiles = -(-w.L2 // tile)
     streams, launches = adjoint_traffic(N, w.L2)
     rev_bytes = 0.0  # a vector of a tile: L2 sites x 16 B
@@ -400,7 +429,7 @@ def adjoint_form(args, dev):
                 "config": {"workload": "%s: 128x128, N=%d, reverse pass only" % (w.name, N)},
                 "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse,
                 "reverse_over_forward": t_bwd / t_fwd, "seconds_reverse_stride1": t_bwd1,
-                "reverse_stride1_over_forward": t_bwd1 / t_fwd}
+                "reverse_stride1_over_forward": t_bwd1 / t_fwd, "reverse_regenerated": reversible}
     # self-consistency: plain mixing vs Newton-Krylov (both to 1e-6)
     op = P.Operator.from_workload(w, dev)
     r = scf.plain_mixing(op, w.U, d0, N, tile, tol=1e-6, max_iter=300)
@@ -427,7 +456,7 @@ def adjoint_form(args, dev):
             "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse,
             "reverse_over_forward": t_bwd / t_fwd, "seconds_dldos0_dV_centre": t_ldos,
             "seconds_reverse_stride1": t_bwd1, "reverse_stride1_over_forward": t_bwd1 / t_fwd,
-            "stride1_max_abs_grad_diff": float((g1 - g_sum).abs().max()),
+            "stride1_max_abs_grad_diff": float((g1 - g_sum).abs().max()), "reverse_regenerated": reversible,
             "grad_norm_inf": float(g_sum.abs().max()), "scf": out}
 
 

@@ -412,7 +412,10 @@ int cbdg_ldos_backward(const double *d_ldos, int64_t n_rows, int32_t N,
 
 /* Bytes of workspace cbdg_chebyshev_moments_backward needs (host out).
  * ckpt_stride 0 selects k = ceil(sqrt(N)) (direct) or ceil(sqrt(N/2 + 1))
- * (doubling), rounded up to a multiple of 3. */
+ * (doubling), rounded up to a multiple of 3; -1 the reverse passes without
+ * checkpoints (a moments workspace of one tile, four cotangent buffers and
+ * per-vector gradient terms of one tile; EUNSUPPORTED where they do not
+ * apply). */
 int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
                                  int32_t ckpt_stride, int32_t algorithm, size_t *bytes);
 
@@ -429,7 +432,15 @@ int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N,
  * order, so repeated calls give identical bits, whatever the stride.
  *   ckpt_stride  k; 0: ceil(sqrt(N)) (DIRECT) or ceil(sqrt(N/2 + 1)) (DOUBLING),
  *                rounded up to a multiple of 3 (the forward then advances
- *                three steps per launch on tiles of more than 128 vectors)
+ *                three steps per launch on tiles of more than 128 vectors).
+ *                -1: no checkpoints (DOUBLING on lattices with Lx = 64 W,
+ *                W = 1, 2, 4, else EUNSUPPORTED): the forward moments keep
+ *                only (a_{M+1}, a_M) and the reverse passes regenerate
+ *                a_{m-1} = 2 Ht a_m - a_{m+1} beside the transposed
+ *                recursion, several levels per launch in the
+ *                vector-contiguous layout; the gradient agrees with the
+ *                checkpointed one to rounding (the regenerated vectors differ
+ *                from the forward ones by a few units in the last place).
  *   algorithm    enum cbdg_algorithm.  DOUBLING (AUTO when b == 0, N >= 3)
  *                differentiates the doubling formulas instead: forward and
  *                adjoint run over a_0 .. a_{N/2} only, the cotangent of a_m

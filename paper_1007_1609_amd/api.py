@@ -380,6 +380,21 @@ def backward_workspace_bytes(op: Operator, tile: int, N: int, ckpt_stride: int =
     return n.value
 
 
+# ckpt_stride of the reverse passes that regenerate the forward vectors
+# backwards instead of storing checkpoints (doubling, real operators with
+# uniform hopping, Lx = 64 W)
+REVERSIBLE = -1
+
+
+def reversible_supported(op: Operator, tile: int, N: int) -> bool:
+    """Whether the checkpoint-free reverse passes apply to this operator."""
+    try:
+        backward_workspace_bytes(op, max(1, int(tile)), N, REVERSIBLE, L.CBDG_ALG_DOUBLING)
+        return True
+    except L.CbdgError:
+        return False
+
+
 def chebyshev_moments_backward(op: Operator, sites: torch.Tensor, N: int, tile: int,
                                dmu_ee: Optional[torch.Tensor], dmu_he: Optional[torch.Tensor],
                                ckpt_stride: int = 0, grad_eps: Optional[torch.Tensor] = None,

@@ -417,6 +417,28 @@ static Plan make_plan(int N, int tile, int ckpt_stride, bool dbl)
     return p;
 }
 
+// Workspace of the reverse passes without checkpoints: the moments
+// workspace of one tile (its four buffers hold the regenerated a_m), four
+// cotangent buffers, the per-vector gradient terms G, the forward's moment
+// rows (not returned) and the start-site cotangents, each region aligned to
+// 256 bytes.
+struct RevLayout { size_t moments, cbuf, G, mu, d1, total; };
+static int rev_layout(const cbdg_op *op, int tile, int N, RevLayout *L)
+{
+    size_t mws = 0;
+    int rc = cbdg_moments_workspace_size(op, tile, CBDG_FP64, CBDG_ALG_DOUBLING, &mws);
+    if (rc) return rc;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t vec = (size_t)op->L2 * (size_t)tile * sizeof(double2);
+    L->moments = 0;
+    L->cbuf = al(mws);
+    L->G = L->cbuf + 4 * al(vec);
+    L->mu = L->G + al(vec);
+    L->d1 = L->mu + al((size_t)2 * tile * N * sizeof(double));
+    L->total = L->d1 + al((size_t)2 * tile * sizeof(double));
+    return CBDG_OK;
+}
+
 static size_t plan_bytes(const Plan &p, int64_t L2)
 {
     const size_t vec = (size_t)L2 * (size_t)p.Bp * sizeof(double2);
@@ -454,17 +476,93 @@ static int backward_algorithm(const cbdg_op *op, int32_t algorithm, int32_t N, c
     }
 }
 
+// The reverse passes without checkpoints, tile by tile: the forward moments
+// in the vector-contiguous passes and one step more leave (a_{M+1}, a_M);
+// full reverse passes of K levels then walk m = M .. down, the last (shorter)
+// pass ending at m = 1; the gradient terms of the tile's vectors are summed
+// into grad_eps and grad_delta.
+static int backward_reversible(const cbdg_op *op, const int32_t *start_sites, int64_t n_start, int32_t N, int tile,
+                               const double *dmu_ee, const double *dmu_he, void *workspace, size_t workspace_bytes,
+                               double *grad_eps, double *grad_delta, hipStream_t st)
+{
+    RevLayout R;
+    int rc = rev_layout(op, tile, N, &R);
+    if (rc) return rc;
+    if (workspace_bytes < R.total)
+        return fail(CBDG_EINVAL, "chebyshev_moments_backward: workspace of %zu bytes is smaller than the %zu needed",
+                    workspace_bytes, R.total);
+    char *base = reinterpret_cast<char *>(workspace);
+    const int64_t L2 = op->L2;
+    const size_t vec = ((size_t)L2 * (size_t)tile * sizeof(double2) + 255) / 256 * 256;
+    void *cb[4];
+    for (int i = 0; i < 4; ++i) cb[i] = base + R.cbuf + i * vec;
+    double *G = reinterpret_cast<double *>(base + R.G);
+    double *mu = reinterpret_cast<double *>(base + R.mu);
+    double *d1 = reinterpret_cast<double *>(base + R.d1);
+    const int M = N / 2, K = vc_adj_steps(op->Lx);
+    for (int64_t t0 = 0; t0 < n_start; t0 += tile) {
+        const int Bt = (int)std::min<int64_t>(tile, n_start - t0);
+        const int32_t *ts = start_sites + t0;
+        const double *tee = dmu_ee ? dmu_ee + t0 * N : nullptr;
+        const double *the = dmu_he ? dmu_he + t0 * N : nullptr;
+        void *last[2], *spare[2];
+        const void *coef = nullptr;
+        if ((rc = vc_forward_last(op, ts, Bt, N, base + R.moments, mu, mu + (int64_t)Bt * N, st, last, spare, &coef)))
+            return rc;
+        hipLaunchKernelGGL(k_adj_d1, dim3((unsigned)ceil_div(Bt, kBlock)), dim3(kBlock), 0, st, tee, the, Bt, N, d1);
+        CBDG_CHECK_LAUNCH("k_adj_d1");
+        VcAdjArgs A{};
+        A.G = G;
+        A.coef = coef;
+        A.th = op->t / op->bounds.a;
+        A.Lx = op->Lx; A.Ly = op->Ly; A.bcx = op->bc_x; A.bcy = op->bc_y;
+        A.Dv = L2; A.Bt = Bt; A.N = N;
+        A.n_segs = vc_segments(op->Ly, Bt, K);
+        A.sites = ts; A.dmu_ee = tee; A.dmu_he = the; A.d1 = d1;
+        // a_{m0+1}, a_{m0} in b[0], b[1]; lam_{m0+2}, lam_{m0+1} in c[0], c[1]
+        void *b[4] = {last[0], last[1], spare[0], spare[1]};
+        void *c[4] = {cb[0], cb[1], cb[2], cb[3]};
+        int m0 = M;
+        bool first = true;
+        while (m0 >= 1) {
+            const bool full = m0 >= K;
+            A.m0 = m0;
+            A.nlev = full ? K : m0;
+            A.first = first ? 1 : 0;
+            A.b0 = b[0]; A.b1 = b[1]; A.bo1 = b[2]; A.bo2 = b[3];
+            A.c0 = c[0]; A.c1 = c[1]; A.co1 = c[2]; A.co2 = c[3];
+            if ((rc = launch_vc_adj(A, full, st))) return rc;
+            std::swap(b[0], b[2]); std::swap(b[1], b[3]);
+            std::swap(c[0], c[2]); std::swap(c[1], c[3]);
+            first = false;
+            m0 -= A.nlev;
+        }
+        if ((rc = launch_vc_grad_reduce(G, ts, Bt, L2, op->Lx, L2, 1.0 / op->bounds.a, grad_eps, grad_delta, st)))
+            return rc;
+    }
+    return CBDG_OK;
+}
+
 extern "C" int cbdg_backward_workspace_size(const cbdg_op *op, int32_t tile, int32_t N, int32_t ckpt_stride,
                                             int32_t algorithm, size_t *bytes)
 {
     clear_error();
     int rc = check_backward_op(op, "backward_workspace_size");
     if (rc) return rc;
-    if (!bytes || tile < 1 || N < 1 || ckpt_stride < 0)
-        return fail(CBDG_EINVAL, "backward_workspace_size: need bytes, tile >= 1, N >= 1, ckpt_stride >= 0");
+    if (!bytes || tile < 1 || N < 1 || ckpt_stride < -1)
+        return fail(CBDG_EINVAL, "backward_workspace_size: need bytes, tile >= 1, N >= 1, ckpt_stride >= -1");
     bool dbl = false;
     rc = backward_algorithm(op, algorithm, N, "backward_workspace_size", &dbl);
     if (rc) return rc;
+    if (ckpt_stride == -1) {
+        if (!dbl || !vc_adjoint_supported(op))
+            return fail(CBDG_EUNSUPPORTED, "backward_workspace_size: the reverse passes without checkpoints need "
+                        "moment doubling on a real operator with uniform hopping and Lx = 64 W (W = 1, 2, 4)");
+        RevLayout R;
+        if ((rc = rev_layout(op, tile, N, &R))) return rc;
+        *bytes = R.total;
+        return CBDG_OK;
+    }
     *bytes = plan_bytes(make_plan(N, tile, ckpt_stride, dbl), op->L2);
     return CBDG_OK;
 }
@@ -479,15 +577,21 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
     clear_error();
     int rc = check_backward_op(op, "chebyshev_moments_backward");
     if (rc) return rc;
-    if (n_start < 0 || N < 1 || tile < 1 || ckpt_stride < 0)
-        return fail(CBDG_EINVAL, "chebyshev_moments_backward: need n_start >= 0, N >= 1, tile >= 1, ckpt_stride >= 0");
+    if (n_start < 0 || N < 1 || tile < 1 || ckpt_stride < -1)
+        return fail(CBDG_EINVAL, "chebyshev_moments_backward: need n_start >= 0, N >= 1, tile >= 1, ckpt_stride >= -1");
     bool dbl = false;
     rc = backward_algorithm(op, algorithm, N, "chebyshev_moments_backward", &dbl);
     if (rc) return rc;
+    if (ckpt_stride == -1 && (!dbl || !vc_adjoint_supported(op)))
+        return fail(CBDG_EUNSUPPORTED, "chebyshev_moments_backward: the reverse passes without checkpoints need "
+                    "moment doubling on a real operator with uniform hopping and Lx = 64 W (W = 1, 2, 4)");
     if (n_start == 0 || N == 1 || (!dmu_ee && !dmu_he)) return CBDG_OK;  // nothing depends on eps or Delta
     if (!start_sites || !workspace || (!grad_eps && !grad_delta))
         return fail(CBDG_EINVAL, "chebyshev_moments_backward: start_sites, workspace and a gradient output are required");
     const int eff_tile = (int)std::min<int64_t>(tile, n_start);
+    if (ckpt_stride == -1)
+        return backward_reversible(op, start_sites, n_start, N, eff_tile, dmu_ee, dmu_he, workspace, workspace_bytes,
+                                   grad_eps, grad_delta, as_stream(stream));
     const Plan plan = make_plan(N, eff_tile, ckpt_stride, dbl);
     const size_t need = plan_bytes(plan, op->L2);
     if (workspace_bytes < need)

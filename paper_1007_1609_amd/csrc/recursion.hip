@@ -1443,7 +1443,7 @@ int seed_tile_f64_real(void *a0, int64_t L2, int Bt, const int32_t *sites, doubl
 template <typename T, bool C>
 static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start, int N, int tile,
                        bool doubling, void *ws, double *mu_ee, double *mu_he, hipStream_t st,
-                       double *nb_ee = nullptr, double *nb_he = nullptr)
+                       double *nb_ee = nullptr, double *nb_he = nullptr, void **vc_out = nullptr)
 {
     using S = typename Storage<T, C>::type;
     const int64_t L2 = op->L2;
@@ -1523,6 +1523,8 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             const int rest = n_steps - n + 1;
             V.n = n; V.a2 = P2; V.a1 = P1; V.out = Q0; V.out2 = Q1;
             if ((rc = launch_vc(V, rest, f32, st)) || (rc = vc_reduce(segsK, n, rest))) return rc;
+            std::swap(P2, Q0);
+            std::swap(P1, Q1);
             n += rest;
         }
         V.n_segs = segs1;
@@ -1530,6 +1532,13 @@ static int run_moments(const cbdg_op *op, const int32_t *sites, int64_t n_start,
             V.n = n; V.a1 = P1; V.a2 = P2; V.out = P2;
             if ((rc = launch_vc(V, 1, f32, st)) || (rc = vc_reduce(segs1, n, 1))) return rc;
             std::swap(P1, P2);
+        }
+        // P2 = a_{M-1}, P1 = a_M (M = n_steps)
+        if (vc_out) {
+            // one step more for the reverse pass: a_{M+1} into P2
+            V.n = n_steps + 1; V.a1 = P1; V.a2 = P2; V.out = P2;
+            if ((rc = launch_vc(V, 1, f32, st)) || (rc = vc_reduce(segs1, n_steps + 1, 1))) return rc;
+            vc_out[0] = P2; vc_out[1] = P1; vc_out[2] = Q0; vc_out[3] = Q1; vc_out[4] = vc_coef;
         }
         return bound_moments(mee, mhe, (int64_t)Bt * N, false, false, moment_limit(f32), st);
     };
@@ -1743,6 +1752,30 @@ static size_t tile_buffer_bytes(const cbdg_op *op, int64_t tile, int precision)
     const size_t nbuf = uses_two_step(op) ? 4 : 2;
     return nbuf * (size_t)op->L2 * (size_t)lane_stride(tile) * pair_bytes(op->scalar, precision);
 }
+
+namespace cbdg {
+
+bool vc_adjoint_supported(const cbdg_op *op)
+{
+    return op && op->scalar == CBDG_REAL && !op->general && op->bounds.b == 0.0 && uses_two_step(op) &&
+           vc_width(op->Lx, false) > 0;
+}
+
+int vc_forward_last(const cbdg_op *op, const int32_t *sites, int Bt, int N, void *ws, double *mu_ee, double *mu_he,
+                    hipStream_t st, void **last, void **spare, const void **coef)
+{
+    if (!vc_adjoint_supported(op) || N < 3 || Bt < kVcMinVectors)
+        return fail(CBDG_EUNSUPPORTED, "chebyshev_moments_backward: the reverse passes need the vector-contiguous "
+                    "forward (real operator, uniform hopping, b = 0, Lx = 64 W, N >= 3)");
+    void *out[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = run_moments<double, false>(op, sites, Bt, N, Bt, true, ws, mu_ee, mu_he, st, nullptr, nullptr, out);
+    if (rc) return rc;
+    if (!out[0]) return fail(CBDG_EINVAL, "chebyshev_moments_backward: the forward did not take the vector-contiguous passes");
+    last[0] = out[0]; last[1] = out[1]; spare[0] = out[2]; spare[1] = out[3]; *coef = out[4];
+    return CBDG_OK;
+}
+
+}  // namespace cbdg
 
 extern "C" int cbdg_moments_workspace_size(const cbdg_op *op, int32_t tile, int32_t precision, int32_t algorithm,
                                            size_t *bytes)

@@ -105,6 +105,48 @@ int vc_segments(int Ly, int Bt, int steps);
 int launch_vc(const VcArgs &A, int steps, bool f32, hipStream_t st);
 // Steps of a full multi-step vector-contiguous pass (3 .. kMaxPassSteps).
 int vc_steps(bool f32);
+// Reverse passes of the doubling adjoint that regenerate the forward vectors
+// backwards (a_{m-1} = 2 Ht a_m - a_{m+1}) instead of reading checkpoints,
+// in the vector-contiguous layout (FP64; the operators and lattices of the
+// forward passes).  A pass of nlev levels takes m = m0 .. m0-nlev+1:
+//   inputs   b0 = a_{m0+1}, b1 = a_{m0} (inside their light cones),
+//            c0 = lam_{m0+2}, c1 = lam_{m0+1} (zero when first),
+//   outputs  (full passes only) bo1 = a_{m0-K+1}, bo2 = a_{m0-K},
+//            co1 = lam_{m0-K+2}, co2 = lam_{m0-K+1},
+//   G        per vector and site, the terms c_m (lam_m . dHt/deps a_{m-1},
+//            lam_m . dHt/dDelta a_{m-1}) * a of the gradient, added to what
+//            G holds (G starts at zero when first).
+// Outputs must not alias inputs.
+struct VcAdjArgs {
+    const void *b0, *b1, *c0, *c1;
+    void *bo1, *bo2, *co1, *co2;
+    double *G;
+    const void *coef;    // the passes' packed coefficients
+    double th;           // t/a
+    int Lx, Ly, bcx, bcy;
+    int64_t Dv;
+    int Bt, n_segs, nblocks;
+    int m0, nlev, N, first;
+    const int32_t *sites;
+    const double *dmu_ee, *dmu_he;  // tile rows (either may be null)
+    const double *d1;               // [Bt][2] start-site cotangents at m = 1
+};
+// Levels of a full reverse pass on lattices of width Lx (0: unsupported).
+int vc_adj_steps(int Lx);
+int launch_vc_adj(VcAdjArgs A, bool full, hipStream_t st);
+// grad_eps[j] += scale * sum_b G_b(j).e, grad_delta[j] += scale * sum_b G_b(j).h
+// over the vectors of valid start sites (summed in order)
+int launch_vc_grad_reduce(const double *G, const int32_t *sites, int Bt, int64_t Dv, int Lx, int64_t L2, double scale,
+                          double *grad_eps, double *grad_delta, hipStream_t st);
+// The forward moments of one tile in the vector-contiguous passes, then one
+// more step: a_{M+1} and a_M (M = N/2) are left in two of the four tile
+// buffers of the moments workspace ws, whose addresses come back in last[0]
+// and last[1]; the other two go to spare[0], spare[1], and the packed
+// coefficients the passes read to coef.
+int vc_forward_last(const cbdg_op *op, const int32_t *sites, int Bt, int N, void *ws, double *mu_ee, double *mu_he,
+                    hipStream_t st, void **last, void **spare, const void **coef);
+bool vc_adjoint_supported(const cbdg_op *op);
+
 // a_0 (its whole start row) and the zeroth moments of a tile
 int launch_vc_seed(void *a0, int64_t Dv, int Lx, bool f32, int Bt, int64_t L2, const int32_t *sites, double *mu_ee,
                    double *mu_he, int N, hipStream_t st);

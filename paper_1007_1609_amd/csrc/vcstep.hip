@@ -156,7 +156,7 @@ struct VcGeo {
         }
         return d < 0 ? -d : d;
     }
-    __device__ bool in_lattice(int v) const { return BCY || (v >= 0 && v < Ly); }
+    __device__ bool in_lattice(int v) const { return BCY || (unsigned)v < (unsigned)Ly; }
     __device__ int phys(int v) const
     {
         if constexpr (!BCY) return v;
@@ -631,7 +631,7 @@ void k_vc_pass(VcArgs A)
             const P *dd = j == 0 ? w0 : lv[j - 1][0];
             const P *uu = j == 0 ? w2 : lv[j - 1][2];
             const P *pp = j == 0 ? p : (j == 1 ? w0 : lv[j - 2][0]);
-            const bool own = s >= y0 && s < y1;
+            const bool own = (unsigned)(s - y0) < (unsigned)(y1 - y0);  // y0 <= s < y1
             if (VAR && j >= nlev) {
                 // past the last level of a shorter pass
             } else if (j < K - 1) {
@@ -727,6 +727,306 @@ void k_vc_pass(VcArgs A)
                 }
             }
         }
+    }
+}
+
+// Reverse passes of the doubling adjoint.  The three-term recursion runs
+// backwards as well as forwards, a_{m-1} = 2 Ht a_m - a_{m+1}, so one sweep
+// m = M .. 1 regenerates the forward vectors from (a_{M+1}, a_M) beside the
+// transposed recursion of the cotangents,
+//   lam_m = w_m + 2 Ht lam_{m+1} - lam_{m+2},
+//   w_m   = cA a_m + cP a_{m+1} + cQ (-a_{m+1,h}, a_{m+1,e})
+//         + cR a_{m-1} + cS (a_{m-1,h}, -a_{m-1,e})   (+ the start-site
+//           cotangents of mu[1] at m = 1),
+// with no checkpoints: a pass streams two vectors of each recursion in and
+// out.  Rounding makes the regenerated a_m differ from the forward ones by a
+// few units in the last place per step (the recursion matrix is unitary on
+// the spectrum's eigenvectors, so the differences grow linearly at most).
+// Each wavefront (one vector, one row segment) adds c_m lam_m . dHt a_{m-1}
+// of its own rows to its vector's G, read and written once per pass; the
+// vectors' G are summed in order afterwards.  The rows go through the
+// pipeline of the forward passes (trip r computes row r-j of level j); each
+// level keeps three-row windows of both recursions, and the gradient terms
+// of a row collect in a ring of K rows until its last level has passed.
+// Levels per reverse pass and rows of the input vectors loaded ahead, by
+// lanes' width W (the trips' unrolling is a common multiple of the two ring
+// lengths and K).  W <= 2: six levels, b1/c1 rows three trips ahead (128x128,
+// N = 512, all 16384 start vectors in tiles of 1024: 0.627 s with four
+// levels one trip ahead, 0.533 s with five levels two ahead, 0.477 s); W = 4
+// keeps four levels, its windows being twice as wide.
+#ifndef CBDG_VC_ADJ_K
+#define CBDG_VC_ADJ_K 6
+#endif
+#ifndef CBDG_VC_ADJ_D1
+#define CBDG_VC_ADJ_D1 3
+#endif
+#ifndef CBDG_VC_ADJ_D2
+#define CBDG_VC_ADJ_D2 1
+#endif
+template <int W> struct VcAdjShape {
+    static constexpr int K = W >= 4 ? 4 : CBDG_VC_ADJ_K;
+    static constexpr int D1 = W >= 4 ? 1 : CBDG_VC_ADJ_D1;
+    static constexpr int D2 = W >= 4 ? 1 : CBDG_VC_ADJ_D2;
+};
+constexpr int cx_gcd(int a, int b) { return b == 0 ? a : cx_gcd(b, a % b); }
+constexpr int cx_lcm(int a, int b) { return a / cx_gcd(a, b) * b; }
+int vc_adj_steps(int Lx)
+{
+    switch (vc_width(Lx, false)) {
+    case 1: return VcAdjShape<1>::K;
+    case 2: return VcAdjShape<2>::K;
+    case 4: return VcAdjShape<4>::K;
+    default: return 0;
+    }
+}
+
+template <int W, bool BCX, bool BCY, bool VAR>
+__global__ __launch_bounds__(kVcBlock) __attribute__((amdgpu_waves_per_eu(1))) void k_vc_adj(VcAdjArgs A)
+{
+    using T = double;
+    using P = Pair<T, false>;
+    using S = typename Storage<T, false>::type;
+    constexpr int K = VcAdjShape<W>::K;
+    static_assert(K >= 2 && K <= 8, "the coefficient ring holds at most eight rows");
+    constexpr int kFar = 1 << 29;  // a radius past every lattice: no light-cone clipping
+    const int blk = xcd_remap(blockIdx.x, A.nblocks);
+    const int seg = blk % A.n_segs;
+    const int lane = threadIdx.x % kWave;
+    const int b = (blk / A.n_segs) * kVcWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (b >= A.Bt) return;
+    const int Lx = A.Lx, Ly = A.Ly;
+    const int si = A.sites[b];
+    if (si < 0 || si >= Lx * Ly) return;  // an invalid start site adds nothing
+    VcGeo<BCX, BCY> g;
+    g.Lx = Lx; g.Ly = Ly;
+    g.yi = si / Lx; g.xi = si - g.yi * Lx;
+    g.lo = lane * W; g.lane = lane;
+    const int per = max(4, (Ly + A.n_segs - 1) / A.n_segs);
+    const int y0 = seg * per, y1 = min(y0 + per, Ly);
+    if (y0 >= y1) return;
+    const int m0 = A.m0;
+    const int nlev = VAR ? A.nlev : K;
+    const bool first = A.first != 0;
+
+    // cotangent coefficients of the pass's levels (wave-uniform)
+    double cA[K], cP[K], cQ[K], cR[K], cS[K], cg[K];
+    {
+        const int N = A.N;
+        const int64_t row = (int64_t)b * N;
+        auto gee = [&](int i) { return (A.dmu_ee && i >= 2 && i < N) ? A.dmu_ee[row + i] : 0.0; };
+        auto ghe = [&](int i) { return (A.dmu_he && i >= 2 && i < N) ? A.dmu_he[row + i] : 0.0; };
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int m = m0 - j;
+            const double sg = (m & 1) ? -2.0 : 2.0;  // 2 (-1)^m
+            cA[j] = 4.0 * gee(2 * m);
+            cP[j] = 2.0 * gee(2 * m + 1);
+            cQ[j] = -sg * ghe(2 * m + 1);
+            cR[j] = m >= 2 ? 2.0 * gee(2 * m - 1) : 0.0;
+            cS[j] = m >= 2 ? sg * ghe(2 * m - 1) : 0.0;
+            cg[j] = m == 1 ? 1.0 : 2.0;
+        }
+    }
+    const int j1 = m0 - 1;  // the level of m = 1, if the pass reaches it
+    const double we = (j1 >= 0 && j1 < nlev) ? A.d1[2 * b] : 0.0;
+    const double wh = (j1 >= 0 && j1 < nlev) ? A.d1[2 * b + 1] : 0.0;
+    const bool own_x = lane == g.xi / W;
+    const int kx = g.xi % W;
+
+    const auto rb0 = vec_rsrc<T>(A.b0, b, A.Dv), rb1 = vec_rsrc<T>(A.b1, b, A.Dv);
+    const auto rc0 = vec_rsrc<T>(A.c0, b, A.Dv), rc1 = vec_rsrc<T>(A.c1, b, A.Dv);
+    const auto rbo1 = vec_rsrc<T>(A.bo1, b, A.Dv), rbo2 = vec_rsrc<T>(A.bo2, b, A.Dv);
+    const auto rco1 = vec_rsrc<T>(A.co1, b, A.Dv), rco2 = vec_rsrc<T>(A.co2, b, A.Dv);
+    const auto rg = vec_rsrc<T>(A.G, b, A.Dv);
+    const T th = kCoefScale<T> * T(A.th);
+    // row offsets: the forward vectors inside their cones, the cotangents and
+    // G over every lattice row (not loaded at all on the first pass)
+    auto off_b = [&](int v, int R) -> unsigned { return g.template offset<T, W>(v, R); };
+    auto off_c = [&](int v) -> unsigned { return first ? kOut : g.template offset<T, W>(v, kFar); };
+    auto own = [&](int v) -> bool { return (unsigned)(v - y0) < (unsigned)(y1 - y0); };
+
+    constexpr int NQ = W / kPer<T>;
+    constexpr int KR = K <= 4 ? 4 : 8;
+    __shared__ U4 ring_all[kVcWaves][KR][NQ][kWave];
+    U4 (*ring)[NQ][kWave] = ring_all[threadIdx.x / kWave];
+    const U4 *pc4 = reinterpret_cast<const U4 *>(A.coef);
+    auto coef_chunks = [&](int v, U4 *cp) __attribute__((always_inline)) {
+        const int64_t at = g.template coef_row<T>(v) / kPer<T>;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) cp[q] = pc4[at + q * kWave];
+    };
+    U4 cpre[NQ];
+    for (int v = y0 - 2 * (K - 1); v < y0 - (K - 1); ++v) {
+        coef_chunks(v, cpre);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ring[v & (KR - 1)][q][lane] = cpre[q];
+    }
+    coef_chunks(y0 - (K - 1), cpre);
+
+    // rings of the input rows: b1/c1 rows r-1 .. r+1 and one in flight, b0/c0
+    // row r and one in flight
+    constexpr int D1 = VcAdjShape<W>::D1, D2 = VcAdjShape<W>::D2;
+    constexpr int R1 = 3 + D1, R2 = 1 + D2;
+    P ab1[R1][W], ab0[R2][W], ac1[R1][W], ac0[R2][W];
+    P wb[K - 1][3][W], wc[K - 1][3][W];  // level j: rows r-j-2, r-j-1, r-j of a_{m0-j-1} and lam_{m0-j}
+    P gacc[K][W];                        // gradient terms (eps, Delta) of rows r-K+1 .. r
+    P gpre[W];
+    const int r0 = y0 - (K - 1);
+#pragma unroll
+    for (int i = 0; i < R1 - 1; ++i) {
+        load_row<T, W>(rb1, off_b(r0 - 1 + i, m0), ab1[i]);
+        load_row<T, W>(rc1, off_c(r0 - 1 + i), ac1[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < R2 - 1; ++i) {
+        load_row<T, W>(rb0, off_b(r0 + i, m0 + 1), ab0[i]);
+        load_row<T, W>(rc0, off_c(r0 + i), ac0[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < K - 1; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < W; ++k) wb[j][i][k] = wc[j][i][k] = zero_pair<T, false>();
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int k = 0; k < W; ++k) gacc[i][k] = zero_pair<T, false>();
+
+    // trip r (u = its place in the unrolled iteration, which fixes the ring
+    // slots): bw/cw = b1/c1 rows r-1, r, r+1 and the slot for row r+1+D1,
+    // bp/cp = b0/c0 row r and the slot for row r+D2
+    auto trip = [&](int r, int u, const P *bw0, const P *bw1, const P *bw2, P *bw3, const P *bp0, P *bpn,
+                    const P *cw0, const P *cw1, const P *cw2, P *cw3, const P *cp0, P *cpn)
+                    __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ring[r & (KR - 1)][q][lane] = cpre[q];
+        coef_chunks(r + 1, cpre);
+        __builtin_amdgcn_sched_barrier(0);
+        load_row<T, W>(rb0, off_b(r + D2, m0 + 1), bpn);
+        load_row<T, W>(rb1, off_b(r + 1 + D1, m0), bw3);
+        load_row<T, W>(rc0, off_c(r + D2), cpn);
+        load_row<T, W>(rc1, off_c(r + 1 + D1), cw3);
+        const int rg_row = r - (K - 1);
+        load_row<T, W>(rg, (!first && own(rg_row)) ? g.template offset<T, W>(rg_row, kFar) : kOut, gpre);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (VAR && j >= nlev) continue;
+            const int s = r - j;
+            S cj[W];
+            {
+                const int ss = s & (KR - 1);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const U4 v = ring[ss][q][lane];
+                    cj[q] = S{__hiloint2double((int)v[1], (int)v[0]), __hiloint2double((int)v[3], (int)v[2])};
+                }
+            }
+            // a_m rows s-1, s, s+1 and a_{m+1}(s); lam_{m+1} rows and lam_{m+2}(s)
+            const P *bd = j == 0 ? bw0 : wb[j - 1][0];
+            const P *bc = j == 0 ? bw1 : wb[j - 1][1];
+            const P *bu = j == 0 ? bw2 : wb[j - 1][2];
+            const P *bq = j == 0 ? bp0 : (j == 1 ? bw0 : wb[j - 2][0]);
+            const P *cd = j == 0 ? cw0 : wc[j - 1][0];
+            const P *cc = j == 0 ? cw1 : wc[j - 1][1];
+            const P *cu = j == 0 ? cw2 : wc[j - 1][2];
+            const P *cq = j == 0 ? cp0 : (j == 1 ? cw0 : wc[j - 2][0]);
+            const T ths = g.in_lattice(s) ? th : T(0);
+            const bool start_row = j == j1 && g.phys(s) == g.yi && own_x;
+            const P bl = dpp_pair<BCX ? kRor1 : kShr1>(bc[W - 1]);
+            const P br = dpp_pair<BCX ? kRol1 : kShl1>(bc[0]);
+            const P cl = dpp_pair<BCX ? kRor1 : kShr1>(cc[W - 1]);
+            const P cr = dpp_pair<BCX ? kRol1 : kShl1>(cc[0]);
+            P bn[W], cn[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+#pragma clang fp contract(off)
+                // a_{m-1}(s)
+                bn[k] = pass_site<T>(cj[k], ths, bc[k], k > 0 ? bc[k - 1] : bl, k < W - 1 ? bc[k + 1] : br, bd[k],
+                                     bu[k], bq[k]);
+                // w_m(s)
+                double w_e = __builtin_fma(cA[j], bc[k].e, __builtin_fma(cR[j], bn[k].e, cS[j] * bn[k].h));
+                double w_h = __builtin_fma(cA[j], bc[k].h, __builtin_fma(cR[j], bn[k].h, -(cS[j] * bn[k].e)));
+                w_e = w_e + __builtin_fma(cP[j], bq[k].e, -(cQ[j] * bq[k].h));
+                w_h = w_h + __builtin_fma(cP[j], bq[k].h, cQ[j] * bq[k].e);
+                if (start_row && k == kx) { w_e = w_e + we; w_h = w_h + wh; }
+                // lam_m(s)
+                const P l2 = pass_site<T>(cj[k], ths, cc[k], k > 0 ? cc[k - 1] : cl, k < W - 1 ? cc[k + 1] : cr, cd[k],
+                                          cu[k], cq[k]);
+                cn[k] = P{l2.e + w_e, l2.h + w_h};
+            }
+            if (own(s)) {
+                P *ga = gacc[(u - j + K * 4) % K];
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+#pragma clang fp contract(off)
+                    ga[k].e = __builtin_fma(cg[j], __builtin_fma(cn[k].e, bn[k].e, -(cn[k].h * bn[k].h)), ga[k].e);
+                    ga[k].h = __builtin_fma(cg[j], __builtin_fma(cn[k].e, bn[k].h, cn[k].h * bn[k].e), ga[k].h);
+                }
+                if (!VAR && j == K - 2) {
+                    store_row<T, W>(rbo1, off_b(s, m0 - j - 1), bn);
+                    store_row<T, W>(rco1, g.template offset<T, W>(s, kFar), cn);
+                }
+                if (!VAR && j == K - 1) {
+                    store_row<T, W>(rbo2, off_b(s, m0 - j - 1), bn);
+                    store_row<T, W>(rco2, g.template offset<T, W>(s, kFar), cn);
+                }
+            }
+            if (j < K - 1) {
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    wb[j][0][k] = wb[j][1][k]; wb[j][1][k] = wb[j][2][k]; wb[j][2][k] = bn[k];
+                    wc[j][0][k] = wc[j][1][k]; wc[j][1][k] = wc[j][2][k]; wc[j][2][k] = cn[k];
+                }
+            }
+        }
+        // row r-K+1 has had all its levels: G += its terms
+        P *ga = gacc[(u - (K - 1) + K * 4) % K];
+        if (own(rg_row)) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) { gpre[k].e = gpre[k].e + ga[k].e; gpre[k].h = gpre[k].h + ga[k].h; }
+            store_row<T, W>(rg, g.template offset<T, W>(rg_row, kFar), gpre);
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) ga[k] = zero_pair<T, false>();
+    };
+    constexpr int U = cx_lcm(cx_lcm(R1, R2), K);  // a multiple of R1, R2 and K
+    static_assert(U <= 12, "unrolling");
+    const int trips = (y1 + K - 2) - r0 + 1;
+    const int r_end = r0 + U * ((trips + U - 1) / U);
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll 1
+    for (int r = r0; r < r_end; r += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            trip(r + u, u, ab1[u % R1], ab1[(u + 1) % R1], ab1[(u + 2) % R1], ab1[(u + R1 - 1) % R1], ab0[u % R2],
+                 ab0[(u + R2 - 1) % R2], ac1[u % R1], ac1[(u + 1) % R1], ac1[(u + 2) % R1], ac1[(u + R1 - 1) % R1],
+                 ac0[u % R2], ac0[(u + R2 - 1) % R2]);
+    }
+}
+
+// grad_eps[j] += scale * sum_b G_b(j).e and grad_delta[j] += scale * sum_b
+// G_b(j).h over the vectors of valid start sites (the reverse passes never
+// touch the others' G), added in order; one thread per pair of the row layout
+__global__ void k_vc_grad_reduce(const double2 *__restrict__ G, const int32_t *__restrict__ sites, int Bt, int64_t Dv,
+                                 int Lx, int W, int64_t L2, double scale, double *grad_eps, double *grad_delta)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L2; p += (int64_t)gridDim.x * blockDim.x) {
+        double ge = 0.0, gd = 0.0;
+        for (int b = 0; b < Bt; ++b) {
+            const int32_t sb = sites[b];
+            if (sb < 0 || sb >= L2) continue;
+            const double2 v = G[b * Dv + p];
+            ge += v.x;
+            gd += v.y;
+        }
+        // position p of row y holds column lane * W + k with p % Lx = k * 64 + lane
+        const int64_t y = p / Lx;
+        const int q = (int)(p - y * Lx);
+        const int64_t site = y * Lx + (q % kWave) * W + q / kWave;
+        if (grad_eps) grad_eps[site] += scale * ge;
+        if (grad_delta) grad_delta[site] += scale * gd;
     }
 }
 
@@ -868,6 +1168,55 @@ int launch_vc_coef(const void *onsite, void *coef, int Lx, bool f32, int64_t L2,
 }
 
 int vc_steps(bool f32) { return f32 ? kVcSteps<float> : kVcSteps<double>; }
+
+template <int W, bool BCX, bool BCY>
+static int launch_vc_adj_w(VcAdjArgs A, bool full, hipStream_t st)
+{
+    const int64_t nb = ceil_div(A.Bt, kVcWaves) * (int64_t)A.n_segs;
+    if (nb > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments_backward: launch grid too large");
+    A.nblocks = (int)nb;
+    if (full) hipLaunchKernelGGL((k_vc_adj<W, BCX, BCY, false>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    else hipLaunchKernelGGL((k_vc_adj<W, BCX, BCY, true>), dim3(A.nblocks), dim3(kVcBlock), 0, st, A);
+    CBDG_CHECK_LAUNCH("k_vc_adj");
+    return CBDG_OK;
+}
+
+template <int W>
+static int launch_vc_adj_bc(const VcAdjArgs &A, bool full, hipStream_t st)
+{
+    if (A.bcx)
+        return A.bcy ? launch_vc_adj_w<W, true, true>(A, full, st) : launch_vc_adj_w<W, true, false>(A, full, st);
+    return A.bcy ? launch_vc_adj_w<W, false, true>(A, full, st) : launch_vc_adj_w<W, false, false>(A, full, st);
+}
+
+int launch_vc_adj(VcAdjArgs A, bool full, hipStream_t st)
+{
+    const int K = vc_adj_steps(A.Lx);
+    if (!full && (A.nlev < 1 || A.nlev > K))
+        return fail(CBDG_EINVAL, "chebyshev_moments_backward: reverse pass of %d levels", A.nlev);
+    if (full && A.m0 < K) return fail(CBDG_EINVAL, "chebyshev_moments_backward: full reverse pass below m = K");
+    if (A.Dv * 16 > INT32_MAX) return fail(CBDG_EINVAL, "chebyshev_moments_backward: lattice too large");
+    if (A.n_segs < 1) return fail(CBDG_EINVAL, "chebyshev_moments_backward: no row segments");
+    switch (vc_width(A.Lx, false)) {
+    case 1: return launch_vc_adj_bc<1>(A, full, st);
+    case 2: return launch_vc_adj_bc<2>(A, full, st);
+    case 4: return launch_vc_adj_bc<4>(A, full, st);
+    default: break;
+    }
+    return fail(CBDG_EUNSUPPORTED, "reverse pass: Lx = %d is not 64 times a supported width", A.Lx);
+}
+
+int launch_vc_grad_reduce(const double *G, const int32_t *sites, int Bt, int64_t Dv, int Lx, int64_t L2, double scale,
+                          double *grad_eps, double *grad_delta, hipStream_t st)
+{
+    const int W = vc_width(Lx, false);
+    if (!W) return fail(CBDG_EUNSUPPORTED, "reverse pass: Lx = %d does not fit", Lx);
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(L2, kBlock), 4096);
+    hipLaunchKernelGGL(k_vc_grad_reduce, dim3(grid), dim3(kBlock), 0, st, reinterpret_cast<const double2 *>(G), sites,
+                       Bt, Dv, Lx, W, L2, scale, grad_eps, grad_delta);
+    CBDG_CHECK_LAUNCH("k_vc_grad_reduce");
+    return CBDG_OK;
+}
 
 int launch_vc(const VcArgs &A, int steps, bool f32, hipStream_t st)
 {

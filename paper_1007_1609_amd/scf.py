@@ -297,12 +297,14 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
 
     J_F v is one reverse pass (the gap map's Jacobian is symmetric for a real
     operator with uniform U, so the vector-Jacobian product J_F^T v equals
-    J_F v), or a forward finite difference (jv="fd").  The residual test is
-    the one of plain mixing: max|F(Delta) - Delta| < tol.  counts["F"] is
+    J_F v; it takes the checkpoint-free reverse passes where the operator
+    allows them), or a forward finite difference (jv="fd").  The residual
+    test is the one of plain mixing: max|F(Delta) - Delta| < tol.  counts["F"] is
     the number of gap-map evaluations, counts["J"] the Jacobian products.
     """
     import numpy as np
-    from .api import backward_workspace_bytes, chebyshev_moments_backward, gap_update_backward
+    from .api import (REVERSIBLE, backward_workspace_bytes, chebyshev_moments_backward, gap_update_backward,
+                      reversible_supported)
     if op.is_complex:
         raise L.CbdgError(L.CBDG_EUNSUPPORTED, "newton_krylov", "real operators only")
     dev = delta0.device
@@ -348,7 +350,9 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
         counts["newton"] += 1
         op.update_delta(delta)
         if jv != "fd" and "ws" not in bw_ws:
-            bw_ws["ws"] = workspace(backward_workspace_bytes(op, min(tile, op.L2), N), dev)
+            # the checkpoint-free reverse passes where the operator allows them
+            bw_ws["stride"] = REVERSIBLE if reversible_supported(op, min(tile, op.L2), N) else 0
+            bw_ws["ws"] = workspace(backward_workspace_bytes(op, min(tile, op.L2), N, bw_ws["stride"]), dev)
         Fd_now, delta_now = Fd, delta
 
         def matvec(v_np):
@@ -361,7 +365,7 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
                 jvv = (Fp - Fd_now) / h
             else:
                 d_mu, _ = gap_update_backward(v, N, w, U, 1.0, want_delta_in=False, coeff=coeff)
-                _, jvv = chebyshev_moments_backward(op, sites, N, tile, None, d_mu, ws=bw_ws["ws"])
+                _, jvv = chebyshev_moments_backward(op, sites, N, tile, None, d_mu, bw_ws["stride"], ws=bw_ws["ws"])
             return (jvv - v).cpu().numpy()
 
         d_np, _ = _gmres(matvec, -g.cpu().numpy(), gmres_tol)
