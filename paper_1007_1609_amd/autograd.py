@@ -15,8 +15,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib as L
-from .api import (Operator, chebyshev_moments, chebyshev_moments_backward, gap_update,
-                  gap_update_backward, ldos, ldos_backward)
+from .api import (REVERSIBLE, Operator, chebyshev_moments, chebyshev_moments_backward, gap_update,
+                  gap_update_backward, ldos, ldos_backward, reversible_supported)
 
 
 @dataclass(frozen=True)
@@ -42,6 +42,8 @@ class _Moments(torch.autograd.Function):
                       delta.detach().contiguous(), bc_x=geom.bc_x, bc_y=geom.bc_y,
                       fixed=(geom.a, geom.b))
         mu_ee, mu_he = chebyshev_moments(op, sites, N, tile)
+        if ckpt is None:  # the checkpoint-free reverse passes where they apply
+            ckpt = REVERSIBLE if reversible_supported(op, min(tile, max(1, sites.numel())), N) else 0
         ctx.op, ctx.sites, ctx.N, ctx.tile, ctx.ckpt = op, sites, N, tile, ckpt
         return mu_ee, mu_he
 
@@ -55,7 +57,11 @@ class _Moments(torch.autograd.Function):
         return ge, gd, None, None, None, None, None
 
 
-def moments(eps, delta, geom: Geometry, sites, N: int, tile: int, ckpt: int = 0):
+def moments(eps, delta, geom: Geometry, sites, N: int, tile: int, ckpt=None):
+    """Moments of eqs. (coeff1)/(coeff2) with a backward through the library's
+    adjoint.  ckpt: the reverse pass's checkpoint stride (0: sqrt(N)), -1 for
+    the checkpoint-free passes, None for those where they apply (doubling,
+    lattices 64 W wide), else 0."""
     return _Moments.apply(eps, delta, geom, sites, N, tile, ckpt)
 
 
