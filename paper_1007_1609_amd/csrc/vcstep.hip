@@ -756,8 +756,10 @@ void k_vc_pass(VcArgs A)
 //           cotangents of mu[1] at m = 1),
 // with no checkpoints: a pass streams two vectors of each recursion in and
 // out.  Rounding makes the regenerated a_m differ from the forward ones by a
-// few units in the last place per step (the recursion matrix is unitary on
-// the spectrum's eigenvectors, so the differences grow linearly at most).
+// few units in the last place per step, and those differences grow at most
+// linearly: on each eigenvector of Ht the two-term recursion matrix has its
+// eigenvalues e^{+-i theta} on the unit circle, theta kept away from 0 and
+// pi by the rescaling's margin.
 // Each wavefront (one vector, one row segment) adds c_m lam_m . dHt a_{m-1}
 // of its own rows to its vector's G, read and written once per pass; the
 // vectors' G are summed in order afterwards.  The rows go through the
