@@ -106,3 +106,19 @@ def test_vc_fp32_recursion(Lx, Ly, bc, N):
     ee, he, a, b = _run(w, N, 256, precision=1)
     o_ee, o_he = oracle.workload_moments(w, a, b)
     assert maxdiff(ee, o_ee) <= TOL_FP32 and maxdiff(he, o_he) <= TOL_FP32
+
+
+def test_native_runner_one_call():
+    """The native runner (host code over the C ABI, no Python in the process)
+    runs one moments call of a 128-wide lattice in both precisions and finds
+    every moment bounded and mu_ee[0][0] = 1."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    runner = os.path.join(root, "paper_1007_1609_amd", "cbdg_moments_run")
+    for prec in ("fp64", "fp32"):
+        r = subprocess.run([runner, "128", "40", "64", "256", "1000", prec, "16", "100"], capture_output=True,
+                           text=True, timeout=120)
+        print(r.stdout)
+        assert r.returncode == 0, r.stderr
+        assert "bounded yes" in r.stdout and "copy: 16 MiB" in r.stdout
