@@ -47,7 +47,8 @@ def _backward(w, N, dee, dhe, tile, ckpt, sites=None):
     (64, 70, 0, 0, 20, 37),     # four row segments per vector
     (128, 7, 0, 1, 41, 300),    # W = 2, periodic y, M = 20, two tiles
     (128, 5, 1, 0, 18, 64),     # periodic x, M = 9 (two full passes and one level)
-    (256, 4, 0, 0, 27, 512),    # W = 4, M = 13
+    (256, 4, 0, 0, 27, 512),    # W = 4 (two levels per pass), M = 13: six full passes and one level
+    (256, 5, 1, 1, 20, 300),    # W = 4, periodic both ways, M = 10: full passes only, two tiles
     (128, 3, 1, 1, 14, 200),    # three rows, periodic: rows wrap within a pass
 ])
 def test_reverse_passes_match_oracle_and_checkpoints(Lx, Ly, bcx, bcy, N, tile):
@@ -66,8 +67,8 @@ def test_reverse_passes_match_oracle_and_checkpoints(Lx, Ly, bcx, bcy, N, tile):
 
 @pytest.mark.parametrize("N", [3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16, 17, 19])
 def test_every_split_of_the_reverse_sweep(N):
-    """M = N/2 levels as full passes of four and one shorter last pass, for
-    every remainder, including M below the pass length."""
+    """M = N/2 levels as full passes of six (64-wide lattice) and one shorter
+    last pass, for every remainder, including M below the pass length."""
     w = W.small_random(64, 8, N=N, seed=N)
     rng = np.random.default_rng(3 * N)
     n = len(w.start_sites)
