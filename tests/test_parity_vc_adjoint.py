@@ -49,6 +49,7 @@ def _backward(w, N, dee, dhe, tile, ckpt, sites=None):
     (128, 5, 1, 0, 18, 64),     # periodic x, M = 9 (two full passes and one level)
     (256, 4, 0, 0, 27, 512),    # W = 4 (two levels per pass), M = 13: six full passes and one level
     (256, 5, 1, 1, 20, 300),    # W = 4, periodic both ways, M = 10: full passes only, two tiles
+    (256, 40, 0, 0, 22, 64),    # W = 4, several row segments per vector, M = 11
     (128, 3, 1, 1, 14, 200),    # three rows, periodic: rows wrap within a pass
 ])
 def test_reverse_passes_match_oracle_and_checkpoints(Lx, Ly, bcx, bcy, N, tile):
@@ -132,6 +133,25 @@ def test_unsupported_operators_are_rejected():
     dee = torch.zeros((len(w.start_sites), 16), dtype=torch.float64, device=DEV)
     with pytest.raises(Exception):
         P.chebyshev_moments_backward(op, s, 16, 64, dee, None, REV, algorithm=DOUBLING)
+    assert not P.reversible_supported(op, 64, 16)
+    op.close()
+
+
+def test_two_moments_take_the_direct_algorithm_and_are_rejected():
+    """N = 2 has no doubling step (the automatic choice is the direct
+    algorithm), so the reverse passes without checkpoints refuse it with
+    EUNSUPPORTED and the automatic choice of the autograd path falls back
+    to checkpoints."""
+    P = _P()
+    w = W.small_random(64, 8, N=2, seed=2)
+    op = P.Operator.from_workload(w, DEV)
+    s = torch.as_tensor(w.start_sites, dtype=torch.int32, device=DEV)
+    dee = torch.ones((len(w.start_sites), 2), dtype=torch.float64, device=DEV)
+    assert P.reversible_supported(op, 64, 4)
+    assert not P.reversible_supported(op, 64, 2)
+    with pytest.raises(P.CbdgError) as e:
+        P.chebyshev_moments_backward(op, s, 2, 64, dee, None, REV)
+    assert "EUNSUPPORTED" in str(e.value)
     op.close()
 
 
