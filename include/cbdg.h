@@ -458,6 +458,40 @@ int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t *start_site
                                     size_t workspace_bytes, double *grad_eps,
                                     double *grad_delta, void *stream);
 
+/*
+ * The derivative of the same L one start vector at a time: row k holds the
+ * gradient of L_k = sum_n (dmu_ee[k][n] mu_ee[k][n] + dmu_he[k][n]
+ * mu_he[k][n]) with respect to eps_j and Delta_j (the terms that
+ * cbdg_chebyshev_moments_backward sums over k).  With dmu_he[k][n] the
+ * derivative of the gap update of site k by its own moments
+ * (cbdg_gap_update_backward with d_delta_out = 1), row k is row k of the
+ * Jacobian dDelta_new/dDelta of the self-consistency map (the gap equation
+ * after eq. (op1) with the moments of eq. (ref2)): one reverse sweep gives
+ * the whole matrix.  It runs the reverse passes without checkpoints, so it
+ * needs what they need (REAL operator with uniform hopping, b = 0, N >= 3,
+ * Lx = 64 W with W = 1, 2, 4; else EUNSUPPORTED) and the workspace of
+ * cbdg_backward_workspace_size(op, tile, N, -1, ...).
+ *   dmu_ee, dmu_he  [n_start*N] FP64 (either may be NULL: zero; not both)
+ *   jac_eps, jac_delta  out [n_start][ld] FP64, ld >= Lx*Ly (either may be
+ *                NULL); columns Lx*Ly .. ld-1 are not written.  Rows of
+ *                invalid start sites are zero.  Overwritten, not added to.
+ * The rows agree with one backward call per start vector to rounding.
+ */
+int cbdg_chebyshev_moments_jacobian(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                                    int32_t N, int32_t tile, const double *dmu_ee, const double *dmu_he,
+                                    void *workspace, size_t workspace_bytes, double *jac_eps,
+                                    double *jac_delta, int64_t ld, void *stream);
+
+/*
+ * y = A x for a dense row-major FP64 matrix on the device (the Jacobian of
+ * cbdg_chebyshev_moments_jacobian applied to a Newton direction): one
+ * wavefront per row, summed in a fixed order, so repeated calls give the
+ * same bits.
+ *   A  [rows][ld], ld >= cols;  x  [cols];  y  out [rows] (must not alias x)
+ */
+int cbdg_jacobian_matvec(const double *A, int64_t rows, int64_t cols, int64_t ld, const double *x,
+                         double *y, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

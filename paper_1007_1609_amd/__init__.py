@@ -19,7 +19,8 @@ from .api import (Operator, Bounds, weights, chebyshev_moments, check_moments,  
                   chebyshev_moments_backward, moments_workspace_bytes,
                   backward_workspace_bytes, workspace, sum_coefficients, density, density_backward,
                   chebyshev_moments_nb, bond_gap_update, bond_current, chebyshev_moments_resident,
-                  resident_workspace_bytes, REVERSIBLE, reversible_supported)
+                  resident_workspace_bytes, REVERSIBLE, reversible_supported,
+                  chebyshev_moments_jacobian, jacobian_matvec)
 
 __all__ = [
     "CbdgError", "CBDG_FP64", "CBDG_FP32_ACC64", "CBDG_REAL", "CBDG_COMPLEX", "CBDG_BC_OPEN",
@@ -28,5 +29,5 @@ __all__ = [
     "moments_workspace_bytes", "backward_workspace_bytes", "workspace", "CBDG_QTY_GAP",
     "CBDG_QTY_DENSITY", "sum_coefficients", "density", "density_backward", "chebyshev_moments_nb",
     "bond_gap_update", "bond_current", "chebyshev_moments_resident", "resident_workspace_bytes",
-    "REVERSIBLE", "reversible_supported",
+    "REVERSIBLE", "reversible_supported", "chebyshev_moments_jacobian", "jacobian_matvec",
 ]

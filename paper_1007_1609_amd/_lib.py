@@ -82,6 +82,8 @@ SIGNATURES = {
     "cbdg_backward_workspace_size": [_vp, _i32, _i32, _i32, _i32, C.POINTER(_sz)],
     "cbdg_chebyshev_moments_backward": [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _sz,
                                         _vp, _vp, _vp],
+    "cbdg_chebyshev_moments_jacobian": [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _sz, _vp, _vp, _i64, _vp],
+    "cbdg_jacobian_matvec": [_vp, _i64, _i64, _i64, _vp, _vp, _vp],
 }
 
 _lib = None
@@ -148,6 +150,8 @@ cbdg_gap_update_backward = _call("cbdg_gap_update_backward")
 cbdg_ldos_backward = _call("cbdg_ldos_backward")
 cbdg_backward_workspace_size = _call("cbdg_backward_workspace_size")
 cbdg_chebyshev_moments_backward = _call("cbdg_chebyshev_moments_backward")
+cbdg_chebyshev_moments_jacobian = _call("cbdg_chebyshev_moments_jacobian")
+cbdg_jacobian_matvec = _call("cbdg_jacobian_matvec")
 
 
 def cbdg_last_error() -> str:

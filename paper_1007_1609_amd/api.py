@@ -395,6 +395,51 @@ def reversible_supported(op: Operator, tile: int, N: int) -> bool:
         return False
 
 
+def chebyshev_moments_jacobian(op: Operator, sites: torch.Tensor, N: int, tile: int,
+                               dmu_ee: Optional[torch.Tensor], dmu_he: Optional[torch.Tensor],
+                               jac_eps: Optional[torch.Tensor] = None, jac_delta: Optional[torch.Tensor] = None,
+                               want_eps: bool = False, ws: Optional[torch.Tensor] = None):
+    """Per-start-vector rows of the moments' reverse-mode derivative
+    (cbdg_chebyshev_moments_jacobian): row k of the returned [n_start, L2]
+    matrices is the gradient of sum_n dmu[k][n] mu[k][n] with respect to eps
+    and Delta.  jac_eps is filled only when given or want_eps."""
+    n = int(sites.numel())
+    eff = max(1, min(int(tile), n))
+    need = backward_workspace_bytes(op, eff, N, REVERSIBLE, L.CBDG_ALG_DOUBLING)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, sites.device)
+    _need(dmu_ee, n * int(N), "dmu_ee")
+    _need(dmu_he, n * int(N), "dmu_he")
+    _need(jac_eps, n * op.L2, "jac_eps")
+    _need(jac_delta, n * op.L2, "jac_delta")
+    if jac_delta is None:
+        jac_delta = torch.empty((n, op.L2), dtype=torch.float64, device=sites.device)
+    if jac_eps is None and want_eps:
+        jac_eps = torch.empty((n, op.L2), dtype=torch.float64, device=sites.device)
+    L.cbdg_chebyshev_moments_jacobian(op.handle, _ptr(sites, torch.int32, "sites"), n, int(N), int(tile),
+                                      _ptr(dmu_ee, torch.float64, "dmu_ee"),
+                                      _ptr(dmu_he, torch.float64, "dmu_he"),
+                                      _ptr(ws, None, "workspace"), ws.numel(),
+                                      _ptr(jac_eps, torch.float64, "jac_eps"),
+                                      _ptr(jac_delta, torch.float64, "jac_delta"), op.L2, _stream())
+    return jac_eps, jac_delta
+
+
+def jacobian_matvec(A: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x for a dense row-major FP64 matrix on the device
+    (cbdg_jacobian_matvec; fixed summation order)."""
+    if A.dim() != 2 or not A.is_contiguous():
+        raise ValueError("A must be a contiguous 2-D tensor")
+    rows, cols = A.shape
+    _need(x, cols, "x")
+    if out is None:
+        out = torch.empty(rows, dtype=torch.float64, device=A.device)
+    _need(out, rows, "out")
+    L.cbdg_jacobian_matvec(_ptr(A, torch.float64, "A"), rows, cols, cols, _ptr(x, torch.float64, "x"),
+                           _ptr(out, torch.float64, "out"), _stream())
+    return out
+
+
 def chebyshev_moments_backward(op: Operator, sites: torch.Tensor, N: int, tile: int,
                                dmu_ee: Optional[torch.Tensor], dmu_he: Optional[torch.Tensor],
                                ckpt_stride: int = 0, grad_eps: Optional[torch.Tensor] = None,

@@ -481,9 +481,12 @@ static int backward_algorithm(const cbdg_op *op, int32_t algorithm, int32_t N, c
 // full reverse passes of K levels then walk m = M .. down, the last (shorter)
 // pass ending at m = 1; the gradient terms of the tile's vectors are summed
 // into grad_eps and grad_delta.
+// With ld > 0 the terms of each start vector are written as its own row
+// (row_eps/row_delta + (start index) * ld) instead of summed into grad_*.
 static int backward_reversible(const cbdg_op *op, const int32_t *start_sites, int64_t n_start, int32_t N, int tile,
                                const double *dmu_ee, const double *dmu_he, void *workspace, size_t workspace_bytes,
-                               double *grad_eps, double *grad_delta, hipStream_t st)
+                               double *grad_eps, double *grad_delta, hipStream_t st, double *row_eps = nullptr,
+                               double *row_delta = nullptr, int64_t ld = 0)
 {
     RevLayout R;
     int rc = rev_layout(op, tile, N, &R);
@@ -537,8 +540,13 @@ static int backward_reversible(const cbdg_op *op, const int32_t *start_sites, in
             first = false;
             m0 -= A.nlev;
         }
-        if ((rc = launch_vc_grad_reduce(G, ts, Bt, L2, op->Lx, L2, 1.0 / op->bounds.a, grad_eps, grad_delta, st)))
-            return rc;
+        if (ld > 0) {
+            rc = launch_vc_grad_rows(G, ts, Bt, L2, op->Lx, L2, 1.0 / op->bounds.a, row_eps ? row_eps + t0 * ld : nullptr,
+                                     row_delta ? row_delta + t0 * ld : nullptr, ld, st);
+        } else {
+            rc = launch_vc_grad_reduce(G, ts, Bt, L2, op->Lx, L2, 1.0 / op->bounds.a, grad_eps, grad_delta, st);
+        }
+        if (rc) return rc;
     }
     return CBDG_OK;
 }
@@ -752,5 +760,69 @@ extern "C" int cbdg_chebyshev_moments_backward(const cbdg_op *op, const int32_t 
                            st, gpart, nchunk, L2, grad_eps, grad_delta);
         CBDG_CHECK_LAUNCH("k_grad_reduce");
     }
+    return CBDG_OK;
+}
+
+// Per-start-vector rows of the reverse-mode derivative: the checkpoint-free
+// reverse passes of cbdg_chebyshev_moments_backward with each vector's
+// gradient terms written as a row of their own instead of summed.
+extern "C" int cbdg_chebyshev_moments_jacobian(const cbdg_op *op, const int32_t *start_sites, int64_t n_start,
+                                               int32_t N, int32_t tile, const double *dmu_ee, const double *dmu_he,
+                                               void *workspace, size_t workspace_bytes, double *jac_eps,
+                                               double *jac_delta, int64_t ld, void *stream)
+{
+    clear_error();
+    int rc = check_backward_op(op, "chebyshev_moments_jacobian");
+    if (rc) return rc;
+    if (n_start < 0 || N < 1 || tile < 1)
+        return fail(CBDG_EINVAL, "chebyshev_moments_jacobian: need n_start >= 0, N >= 1, tile >= 1");
+    bool dbl = false;
+    rc = backward_algorithm(op, CBDG_ALG_AUTO, N, "chebyshev_moments_jacobian", &dbl);
+    if (rc) return rc;
+    if (!dbl || !vc_adjoint_supported(op))
+        return fail(CBDG_EUNSUPPORTED, "chebyshev_moments_jacobian: needs moment doubling (b = 0, N >= 3) on a real "
+                    "operator with uniform hopping and Lx = 64 W (W = 1, 2, 4)");
+    if (n_start == 0) return CBDG_OK;
+    if (ld < op->L2)
+        return fail(CBDG_EINVAL, "chebyshev_moments_jacobian: ld = %lld is below the %lld sites",
+                    (long long)ld, (long long)op->L2);
+    if (!start_sites || !workspace || (!jac_eps && !jac_delta) || (!dmu_ee && !dmu_he))
+        return fail(CBDG_EINVAL, "chebyshev_moments_jacobian: start_sites, workspace, a cotangent and an output are "
+                    "required");
+    return backward_reversible(op, start_sites, n_start, N, (int)std::min<int64_t>(tile, n_start), dmu_ee, dmu_he,
+                               workspace, workspace_bytes, nullptr, nullptr, as_stream(stream), jac_eps, jac_delta, ld);
+}
+
+namespace cbdg {
+// y[r] = sum_c A[r * ld + c] x[c]: one wavefront per row, each lane summing
+// the columns c = lane (mod 64) in order, then a fixed butterfly, so repeated
+// calls give identical bits
+__global__ __launch_bounds__(kBlock) void k_matvec(const double *__restrict__ A, int64_t rows, int64_t cols,
+                                                   int64_t ld, const double *__restrict__ x, double *__restrict__ y)
+{
+    const int64_t r = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (r >= rows) return;  // the whole wavefront
+    const int lane = threadIdx.x % kWave;
+    const double *a = A + r * ld;
+    double s = 0.0;
+    for (int64_t c = lane; c < cols; c += kWave) s = __builtin_fma(a[c], x[c], s);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if (lane == 0) y[r] = s;
+}
+}  // namespace cbdg
+
+extern "C" int cbdg_jacobian_matvec(const double *A, int64_t rows, int64_t cols, int64_t ld, const double *x,
+                                    double *y, void *stream)
+{
+    clear_error();
+    if (rows < 0 || cols < 0 || ld < cols)
+        return fail(CBDG_EINVAL, "jacobian_matvec: need rows >= 0, cols >= 0, ld >= cols");
+    if (rows == 0) return CBDG_OK;
+    if (!A || !y || (cols > 0 && !x)) return fail(CBDG_EINVAL, "jacobian_matvec: A, x and y are required");
+    const int64_t nb = ceil_div(rows, kBlock / kWave);
+    if (nb > INT32_MAX) return fail(CBDG_EINVAL, "jacobian_matvec: too many rows");
+    hipLaunchKernelGGL(k_matvec, dim3((unsigned)nb), dim3(kBlock), 0, as_stream(stream), A, rows, cols, ld, x, y);
+    CBDG_CHECK_LAUNCH("k_matvec");
     return CBDG_OK;
 }

@@ -138,6 +138,11 @@ int launch_vc_adj(VcAdjArgs A, bool full, hipStream_t st);
 // over the vectors of valid start sites (summed in order)
 int launch_vc_grad_reduce(const double *G, const int32_t *sites, int Bt, int64_t Dv, int Lx, int64_t L2, double scale,
                           double *grad_eps, double *grad_delta, hipStream_t st);
+// the same terms one row per vector: row_eps[b * ld + j] = scale * G_b(j).e,
+// row_delta[b * ld + j] = scale * G_b(j).h (zero rows for invalid start
+// sites; either output may be null)
+int launch_vc_grad_rows(const double *G, const int32_t *sites, int Bt, int64_t Dv, int Lx, int64_t L2, double scale,
+                        double *row_eps, double *row_delta, int64_t ld, hipStream_t st);
 // The forward moments of one tile in the vector-contiguous passes, then one
 // more step: a_{M+1} and a_M (M = N/2) are left in two of the four tile
 // buffers of the moments workspace ws, whose addresses come back in last[0]

@@ -1051,6 +1051,26 @@ __global__ void k_vc_grad_reduce(const double2 *__restrict__ G, const int32_t *_
     }
 }
 
+// The same terms kept apart, one row per start vector: rows[b][j] = scale *
+// G_b(j).e / .h for a valid start site, zero for the others; one thread per
+// (vector, pair of the row layout)
+__global__ void k_vc_grad_rows(const double2 *__restrict__ G, const int32_t *__restrict__ sites, int Bt, int64_t Dv,
+                               int Lx, int W, int64_t L2, double scale, double *row_eps, double *row_delta, int64_t ld)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)Bt * L2) return;
+    const int b = (int)(t / L2);
+    const int64_t p = t - (int64_t)b * L2;
+    const int32_t sb = sites[b];
+    const bool ok = sb >= 0 && sb < L2;
+    const double2 v = ok ? G[b * Dv + p] : make_double2(0.0, 0.0);
+    const int64_t y = p / Lx;
+    const int q = (int)(p - y * Lx);
+    const int64_t site = y * Lx + (q % kWave) * W + q / kWave;
+    if (row_eps) row_eps[b * ld + site] = scale * v.x;
+    if (row_delta) row_delta[b * ld + site] = scale * v.y;
+}
+
 // a_0 = |s_b, e> in the vector-contiguous layout, and the zeroth moments; an
 // invalid start site leaves its vector untouched (no pass reads or writes it)
 // and its moment row NaN.
@@ -1236,6 +1256,19 @@ int launch_vc_grad_reduce(const double *G, const int32_t *sites, int Bt, int64_t
     hipLaunchKernelGGL(k_vc_grad_reduce, dim3(grid), dim3(kBlock), 0, st, reinterpret_cast<const double2 *>(G), sites,
                        Bt, Dv, Lx, W, L2, scale, grad_eps, grad_delta);
     CBDG_CHECK_LAUNCH("k_vc_grad_reduce");
+    return CBDG_OK;
+}
+
+int launch_vc_grad_rows(const double *G, const int32_t *sites, int Bt, int64_t Dv, int Lx, int64_t L2, double scale,
+                        double *row_eps, double *row_delta, int64_t ld, hipStream_t st)
+{
+    const int W = vc_width(Lx, false);
+    if (!W) return fail(CBDG_EUNSUPPORTED, "reverse pass: Lx = %d does not fit", Lx);
+    const int64_t nb = ceil_div((int64_t)Bt * L2, kBlock);
+    if (nb > INT32_MAX) return fail(CBDG_EINVAL, "jacobian: launch grid too large");
+    hipLaunchKernelGGL(k_vc_grad_rows, dim3((unsigned)nb), dim3(kBlock), 0, st, reinterpret_cast<const double2 *>(G),
+                       sites, Bt, Dv, Lx, W, L2, scale, row_eps, row_delta, ld);
+    CBDG_CHECK_LAUNCH("k_vc_grad_rows");
     return CBDG_OK;
 }
 

@@ -286,7 +286,8 @@ def anderson_mixing(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: 
 def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: int,
                   tol: float = 1e-6, max_newton: int = 30, jv: str = "vjp", fd_step: float = 1e-7,
                   gmres_tol: float = 1e-2, warmup_tol: float = 1e-2, max_warmup: int = 100,
-                  kernel: str = "jackson", callback=None, T: float = 0.0) -> ScfResult:
+                  kernel: str = "jackson", callback=None, T: float = 0.0,
+                  rebuild_jacobian: bool = True) -> ScfResult:
     """Solve F(Delta) = Delta with inexact Newton steps (J_F - I) d = -(F - Delta).
 
     The gap map has more than one fixed point (Delta -> -Delta, and the
@@ -298,13 +299,22 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
     J_F v is one reverse pass (the gap map's Jacobian is symmetric for a real
     operator with uniform U, so the vector-Jacobian product J_F^T v equals
     J_F v; it takes the checkpoint-free reverse passes where the operator
-    allows them), or a forward finite difference (jv="fd").  The residual
-    test is the one of plain mixing: max|F(Delta) - Delta| < tol.  counts["F"] is
-    the number of gap-map evaluations, counts["J"] the Jacobian products.
+    allows them), or a forward finite difference (jv="fd"), or, with
+    jv="jacobian", a product with the whole Jacobian J_F, built by one
+    checkpoint-free reverse sweep whose per-start-vector gradients are its
+    rows (cbdg_chebyshev_moments_jacobian; L2 x L2 FP64 on the device) and
+    applied by the library's matrix-vector kernel; rebuild_jacobian=False
+    keeps the first Newton step's matrix for the later steps (a chord
+    iteration).  The residual test is the one of plain mixing:
+    max|F(Delta) - Delta| < tol.  counts["F"] is the number of gap-map
+    evaluations, counts["J"] the Jacobian products, counts["jacobian"] the
+    matrices built.
     """
     import numpy as np
-    from .api import (REVERSIBLE, backward_workspace_bytes, chebyshev_moments_backward, gap_update_backward,
-                      reversible_supported)
+    from .api import (REVERSIBLE, backward_workspace_bytes, chebyshev_moments_backward, chebyshev_moments_jacobian,
+                      gap_update_backward, jacobian_matvec, reversible_supported)
+    if jv not in ("vjp", "fd", "jacobian"):
+        raise ValueError("jv must be 'vjp', 'fd' or 'jacobian'")
     if op.is_complex:
         raise L.CbdgError(L.CBDG_EUNSUPPORTED, "newton_krylov", "real operators only")
     dev = delta0.device
@@ -315,8 +325,9 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
     mu_ee = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
     mu_he = torch.empty((op.L2, N), dtype=torch.float64, device=dev)
     resid = torch.empty(1, dtype=torch.float64, device=dev)
-    counts = {"F": 0, "J": 0, "warmup": 0, "newton": 0}
+    counts = {"F": 0, "J": 0, "warmup": 0, "newton": 0, "jacobian": 0}
     bw_ws = {}
+    jac = {}
 
     def F(delta_t):
         op.update_delta(delta_t)
@@ -352,7 +363,17 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
         if jv != "fd" and "ws" not in bw_ws:
             # the checkpoint-free reverse passes where the operator allows them
             bw_ws["stride"] = REVERSIBLE if reversible_supported(op, min(tile, op.L2), N) else 0
+            if jv == "jacobian" and bw_ws["stride"] != REVERSIBLE:
+                raise L.CbdgError(L.CBDG_EUNSUPPORTED, "newton_krylov",
+                                  "the whole Jacobian needs the checkpoint-free reverse passes")
             bw_ws["ws"] = workspace(backward_workspace_bytes(op, min(tile, op.L2), N, bw_ws["stride"]), dev)
+        if jv == "jacobian" and (rebuild_jacobian or "J" not in jac):
+            # row k: d F_k / d Delta (the gap update's cotangent of its own moments, one reverse sweep)
+            d_mu, _ = gap_update_backward(torch.ones(op.L2, dtype=torch.float64, device=dev), N, w, U, 1.0,
+                                          want_delta_in=False, coeff=coeff)
+            _, jac["J"] = chebyshev_moments_jacobian(op, sites, N, tile, None, d_mu, jac_delta=jac.get("J"),
+                                                     ws=bw_ws["ws"])
+            counts["jacobian"] += 1
         Fd_now, delta_now = Fd, delta
 
         def matvec(v_np):
@@ -363,6 +384,8 @@ def newton_krylov(op: Operator, U: float, delta0: torch.Tensor, N: int, tile: in
                 Fp = F(delta_now + h * v)
                 counts["F"] -= 1
                 jvv = (Fp - Fd_now) / h
+            elif jv == "jacobian":
+                jvv = jacobian_matvec(jac["J"], v)
             else:
                 d_mu, _ = gap_update_backward(v, N, w, U, 1.0, want_delta_in=False, coeff=coeff)
                 _, jvv = chebyshev_moments_backward(op, sites, N, tile, None, d_mu, bw_ws["stride"], ws=bw_ws["ws"])

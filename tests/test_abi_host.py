@@ -35,7 +35,8 @@ def test_header_declares_the_boundary_calls():
     d = _declared()
     for name in ("cbdg_build_bdg", "cbdg_op_update_delta", "cbdg_op_destroy", "cbdg_chebyshev_moments",
                  "cbdg_gap_update", "cbdg_ldos", "cbdg_chebyshev_moments_backward",
-                 "cbdg_gap_update_backward", "cbdg_ldos_backward", "cbdg_last_error"):
+                 "cbdg_gap_update_backward", "cbdg_ldos_backward", "cbdg_last_error",
+                 "cbdg_chebyshev_moments_jacobian", "cbdg_jacobian_matvec"):
         assert name in d, name
 
 

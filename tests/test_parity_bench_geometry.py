@@ -155,7 +155,7 @@ def test_config1_self_consistent_delta_is_an_oracle_fixed_point():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("jv", ["vjp", "fd"])
+@pytest.mark.parametrize("jv", ["vjp", "fd", "jacobian"])
 def test_config4_newton_krylov_delta_is_an_oracle_fixed_point(jv):
     """Newton-Krylov on the full 128x128 differentiation workload (N = 512):
     its Delta satisfies the oracle's gap map at 64 sampled sites."""
