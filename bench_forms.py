@@ -412,6 +412,37 @@ def adjoint_form(args, dev):
                   "algorithmic_bytes": rev_b, "algorithmic_GBps": rev_b / t_rev / 1e9, "frac": rev_b / t_rev / 8e12,
                   "max_abs_grad_diff_vs_checkpoints": float((g_rev - g_sum).abs().max()),
                   "note": "includes the forward moments of every tile (vector-contiguous passes) and one step more"}
+    # the whole Jacobian of the gap map (one reverse sweep, rows kept) and its
+    # product with a vector
+    op = P.Operator.from_workload(w, dev)
+    d_mu, _ = P.gap_update_backward(torch.ones(w.L2, dtype=torch.float64, device=dev), N, op.weights("jackson"),
+                                    w.U, 1.0, want_delta_in=False)
+    all_sites = torch.arange(w.L2, dtype=torch.int32, device=dev)
+    _, Jm = P.chebyshev_moments_jacobian(op, all_sites, N, tile, None, d_mu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.chebyshev_moments_jacobian(op, all_sites, N, tile, None, d_mu, jac_delta=Jm)
+    torch.cuda.synchronize()
+    t_jac = time.perf_counter() - t0
+    op.close()
+    xv = torch.ones(w.L2, dtype=torch.float64, device=dev)
+    yv = torch.empty_like(xv)
+    P.jacobian_matvec(Jm, xv, out=yv)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        P.jacobian_matvec(Jm, xv, out=yv)
+    e1.record()
+    torch.cuda.synchronize()
+    mv_ms = e0.elapsed_time(e1) / 20
+    jacobian = {"seconds_build": t_jac, "rows": w.L2, "bytes": Jm.numel() * 8,
+                "matvec_ms": mv_ms, "matvec_GBps": Jm.numel() * 8 / (mv_ms * 1e-3) / 1e9,
+                "matvec_frac": Jm.numel() * 8 / (mv_ms * 1e-3) / 8e12,
+                "note": "rows of dF/dDelta from one checkpoint-free reverse sweep (its forward included); "
+                        "the matvec reads the matrix once per product"}
+    del Jm
+    torch.cuda.empty_cache()
+    log("jacobian: build %.2f s, matvec %.3f ms" % (t_jac, mv_ms))
     n_tiles = -(-w.L2 // tile)
     streams, launches = adjoint_traffic(N, w.L2)
     rev_bytes = 0.0  # a vector of a tile: L2 sites x 16 B
@@ -429,7 +460,8 @@ def adjoint_form(args, dev):
                 "config": {"workload": "%s: 128x128, N=%d, reverse pass only" % (w.name, N)},
                 "seconds_forward": t_fwd, "seconds_reverse_dsumdelta_dV": t_bwd, "reverse": reverse,
                 "reverse_over_forward": t_bwd / t_fwd, "seconds_reverse_stride1": t_bwd1,
-                "reverse_stride1_over_forward": t_bwd1 / t_fwd, "reverse_regenerated": reversible}
+                "reverse_stride1_over_forward": t_bwd1 / t_fwd, "reverse_regenerated": reversible,
+                "jacobian": jacobian}
     # self-consistency: plain mixing vs Newton-Krylov (both to 1e-6)
     op = P.Operator.from_workload(w, dev)
     r = scf.plain_mixing(op, w.U, d0, N, tile, tol=1e-6, max_iter=300)
@@ -459,6 +491,7 @@ def adjoint_form(args, dev):
             "reverse_over_forward": t_bwd / t_fwd, "seconds_dldos0_dV_centre": t_ldos,
             "seconds_reverse_stride1": t_bwd1, "reverse_stride1_over_forward": t_bwd1 / t_fwd,
             "stride1_max_abs_grad_diff": float((g1 - g_sum).abs().max()), "reverse_regenerated": reversible,
+            "jacobian": jacobian,
             "grad_norm_inf": float(g_sum.abs().max()), "scf": out}
 
 
