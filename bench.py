@@ -16,20 +16,23 @@ the timed steps if it has not converged by then).
 
 Prints one JSON line.  `value` is moments/s (start vectors x N per second)
 with every input resident in HBM.  The moments come from moment doubling
-(N/2 recursion steps per tile, each followed by a small FP64 reduction of the
-dot products) unless --algorithm direct asks for N - 1 steps; after the first
-step the library advances the tile three steps per launch (two for tiles of
-at most 128 vectors).  `roofline` reports the recursion launches, timed with
-HIP events on the launch stream around each tile (the tile's clear, seed and
-reduction kernels are charged to the recursion launches): `achieved` counts
-the bytes each launch must move through HBM -- its input and output vectors
-inside the light cone of the tile's start sites -- over the average launch
+(N/2 recursion steps per tile) unless --algorithm direct asks for N - 1
+steps; on this lattice (256 = 64 x 4 columns) the library advances a tile
+seven steps per launch in the vector-contiguous passes, one wavefront per
+start vector, each vector clipped to its own light cone, the pass writing the
+doubling moments of its steps itself.  `roofline` reports the recursion
+launches, timed with HIP events on the launch stream around each tile (the
+tile's seed and coefficient kernels are charged to the recursion launches):
+`achieved` counts the bytes each launch must move through HBM -- its input
+and output vectors inside their light cones -- over the average launch
 duration; `effective_GBps` counts instead the bytes of the plain one-step
 recursion streamed over the whole lattice, which the multi-step passes and
 the light cone avoid.  `traffic` is the HBM traffic per launch from the
 rocprofv3 counters stored under profiles/ (null when they were taken on a
 different kernel source).  `precision_form` runs the FP32-recursion form
 (FP64 moment sums) and the FP64 path at N = 2048 on the same 16 tiles;
+`differentiation_form` the 128x128 gradient (against a finite difference)
+and the Newton solve on the whole Jacobian against plain mixing;
 `cpu_baseline` times the CPU oracle on a bounded sample of start vectors.
 """
 from __future__ import annotations
@@ -278,6 +281,8 @@ def main():
                     help="default form: do not continue the iterations past the timed steps to convergence")
     ap.add_argument("--no-precision-form", action="store_true",
                     help="default form: skip the FP32 / FP64 passes at N = 2048")
+    ap.add_argument("--no-diff-form", action="store_true",
+                    help="default form: skip the differentiation summary (128x128 gradient and Newton solve)")
     ap.add_argument("--no-scf", action="store_true",
                     help="--form adjoint: time the forward and reverse passes only (no solves)")
     ap.add_argument("--scf-fp32", action="store_true",
@@ -473,6 +478,9 @@ def main():
     if args.precision == "fp64" and full and not args.no_precision_form:
         line["precision_form"] = precision_form(w, op, delta, dev,
                                                 "self-consistent" if line["scf_solve"]["converged"] else "current")
+    if args.precision == "fp64" and full and not args.no_diff_form:
+        import bench_forms
+        line["differentiation_form"] = bench_forms.differentiation_summary(dev)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
         line["cpu_baseline"] = cpu_baseline(w, a, b, args.cpu_sites, threads)

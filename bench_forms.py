@@ -495,6 +495,74 @@ def adjoint_form(args, dev):
             "grad_norm_inf": float(g_sum.abs().max()), "scf": out}
 
 
+def differentiation_summary(dev):
+    """The differentiation form in brief, for the default bench line (128x128
+    workload, N = 512): d(sum Delta)/dV by the checkpoint-free reverse passes
+    against a Richardson finite difference at the centre site, the whole
+    Jacobian of the gap map, and the self-consistent solve by Newton on that
+    Jacobian (kept from the first Newton step) against plain mixing."""
+    from paper_1007_1609_amd import autograd as AG
+    from paper_1007_1609_amd import scf
+    w = W.config4()
+    N, tile = w.N, w.tile
+    op = P.Operator.from_workload(w, dev)
+    a, b = op.bounds.a, op.bounds.b
+    op.close()
+    geom = AG.Geometry.of(w, a, b)
+    sites = torch.as_tensor(w.start_sites, device=dev)
+    wt = P.weights(a, b)
+    d0 = torch.as_tensor(w.delta, device=dev)
+
+    def grad_sum_delta():
+        eps = torch.as_tensor(w.eps, device=dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, mu_he = AG.moments(eps, d0, geom, sites, N, tile, P.REVERSIBLE)
+        AG.gap_map(mu_he, d0, w.U, wt).sum().backward()
+        torch.cuda.synchronize()
+        return eps.grad.cpu().numpy(), time.perf_counter() - t0
+
+    def sum_delta(eps_np):
+        with torch.no_grad():
+            _, mu_he = AG.moments(torch.as_tensor(eps_np, device=dev), d0, geom, sites, N, tile)
+            return float(AG.gap_map(mu_he, d0, w.U, wt).sum())
+
+    grad_sum_delta()
+    g, t_grad = grad_sum_delta()
+    j = int(w.notes["centre_site"])
+
+    def f(h):
+        e = np.array(w.eps, dtype=np.float64)
+        e[j] += h
+        return sum_delta(e)
+
+    d1 = (f(1e-3) - f(-1e-3)) / 2e-3
+    d2 = (f(5e-4) - f(-5e-4)) / 1e-3
+    rich = (4 * d2 - d1) / 3
+    op = P.Operator.from_workload(w, dev)
+    plain = scf.plain_mixing(op, w.U, d0, N, tile, tol=1e-6, max_iter=300)
+    op.close()
+    op = P.Operator.from_workload(w, dev)
+    nk = scf.newton_krylov(op, w.U, d0, N, tile, tol=1e-6, jv="jacobian", rebuild_jacobian=False)
+    op.close()
+    torch.cuda.empty_cache()
+    log("differentiation: gradient %.2f s, FD rel err %.1e; plain %.2f s, Newton (Jacobian) %.2f s" % (
+        t_grad, abs(g[j] - rich) / np.max(np.abs(g)), plain.seconds, nk.seconds))
+    return {"workload": "%s: 128x128 open lattice, 64 impurities V~U[0,4] (seed 4), t=1 mu=-0.5 U=2, N=%d, "
+                        "all 16384 start sites in tiles of %d" % (w.name, N, tile),
+            "grad_sum_delta_dV_seconds": t_grad,
+            "grad_note": "forward moments and checkpoint-free reverse passes, through torch.autograd",
+            "fd_check": {"site": j, "adjoint": float(g[j]), "richardson_fd": float(rich),
+                         "rel_err_vs_max_grad": float(abs(g[j] - rich) / np.max(np.abs(g))), "bar": 1e-6},
+            "plain_mixing": {"seconds": plain.seconds, "gap_map_evaluations": plain.iterations,
+                             "residual": plain.residual},
+            "newton_whole_jacobian": {"seconds": nk.seconds, "gap_map_evaluations": nk.counts["F"],
+                                      "jacobians_built": nk.counts["jacobian"], "newton_steps": nk.counts["newton"],
+                                      "jacobian_products": nk.counts["J"], "residual": nk.residual,
+                                      "max_abs_diff_vs_plain": float((nk.delta - plain.delta).abs().max())},
+            "newton_over_plain_speedup": plain.seconds / nk.seconds}
+
+
 def scf_form(args, dev):
     w = W.config1()
     op = P.Operator.from_workload(w, dev)
