@@ -163,3 +163,20 @@ def test_closed_operator_raises_before_any_library_call():
     with pytest.raises(ValueError, match="closed"):
         op.update_delta(None)
     op.close()   # closing twice is a no-op
+
+
+def test_newton_krylov_rejects_an_unknown_product_before_any_library_call():
+    from paper_1007_1609_amd import scf
+    with pytest.raises(ValueError):
+        scf.newton_krylov(None, 2.0, None, 64, 64, jv="hessian")
+
+
+def test_jacobian_matvec_checks_its_operands_on_the_host():
+    import torch
+    import paper_1007_1609_amd as P
+    with pytest.raises(ValueError):
+        P.jacobian_matvec(torch.zeros(3, 4, dtype=torch.float64).t(), torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        P.jacobian_matvec(torch.zeros(3, 4, dtype=torch.float64), torch.zeros(2, dtype=torch.float64))
+    with pytest.raises(ValueError):  # host tensors never reach the library
+        P.jacobian_matvec(torch.zeros(3, 4, dtype=torch.float64), torch.zeros(4, dtype=torch.float64))
