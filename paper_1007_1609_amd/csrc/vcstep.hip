@@ -771,10 +771,11 @@ void k_vc_pass(VcArgs A)
 // lengths and K).  W <= 2: six levels, b1/c1 rows three trips ahead (128x128,
 // N = 512, all 16384 start vectors in tiles of 1024: 0.627 s with four
 // levels one trip ahead, 0.533 s with five levels two ahead, 0.477 s); W = 4
-// takes two levels, its windows being twice as wide: the rings of more levels
-// no longer fit the registers (four levels spill 784 bytes per lane; 256x256,
-// N = 1024, two tiles of 1024 vectors: 1.58 s with four levels, 1.06 s with
-// two).
+// takes three levels with no rows loaded ahead, its windows being twice as
+// wide: deeper rings no longer fit the registers (256x256, N = 1024, two
+// tiles of 1024 vectors: four levels one row ahead 1.58 s, spilling 784
+// bytes per lane; two levels one row ahead 1.06 s; three levels none ahead
+// 0.745 s, 480 registers; three levels one ahead spill 528 bytes).
 #ifndef CBDG_VC_ADJ_K
 #define CBDG_VC_ADJ_K 6
 #endif
@@ -785,9 +786,9 @@ void k_vc_pass(VcArgs A)
 #define CBDG_VC_ADJ_D2 1
 #endif
 template <int W> struct VcAdjShape {
-    static constexpr int K = W >= 4 ? 2 : CBDG_VC_ADJ_K;
-    static constexpr int D1 = W >= 4 ? 1 : CBDG_VC_ADJ_D1;
-    static constexpr int D2 = W >= 4 ? 1 : CBDG_VC_ADJ_D2;
+    static constexpr int K = W >= 4 ? 3 : CBDG_VC_ADJ_K;
+    static constexpr int D1 = W >= 4 ? 0 : CBDG_VC_ADJ_D1;
+    static constexpr int D2 = W >= 4 ? 0 : CBDG_VC_ADJ_D2;
 };
 constexpr int cx_gcd(int a, int b) { return b == 0 ? a : cx_gcd(b, a % b); }
 constexpr int cx_lcm(int a, int b) { return a / cx_gcd(a, b) * b; }
