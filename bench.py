@@ -271,9 +271,9 @@ def main():
                          "gradients and Newton-Krylov; scf: a self-consistent solve of the 256x256 workload "
                          "by a chosen method; paper: the paper's two example geometries; resident: "
                          "cache-resident persistent tiles vs the streaming path (128x128)")
-    ap.add_argument("--scf-method", choices=["plain", "nk-fd", "anderson"], default="plain",
+    ap.add_argument("--scf-method", choices=["plain", "nk-fd", "nk-jacobian", "anderson"], default="plain",
                     help="--form scf: plain mixing, Newton-Krylov with finite-difference products, "
-                         "or Anderson mixing")
+                         "Newton on the whole Jacobian, or Anderson mixing")
     ap.add_argument("--scf-warmup-n", type=int, default=0,
                     help="--form scf --scf-method anderson: moments of the plain-mixing warm-up "
                          "evaluations (0: the workload's N)")

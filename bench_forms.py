@@ -588,6 +588,13 @@ def scf_form(args, dev):
         passes = r.iterations
         extra = {"fp32_passes": r.fast_passes, "fp64_passes": passes - r.fast_passes,
                  "warmup_passes": r.warmup_passes, "warmup_N": wn}
+    elif method == "nk-jacobian":
+        r = scf.newton_krylov(op, w.U, d0, w.N, w.tile, tol=1e-6, jv="jacobian", rebuild_jacobian=False,
+                              callback=cb)
+        how = ("Newton on the whole Jacobian (one checkpoint-free reverse sweep, kept from the first Newton "
+               "step) after plain-mixing warm-up to 1e-2")
+        passes = r.counts["F"]
+        extra = {"counts": r.counts}
     else:
         r = scf.newton_krylov(op, w.U, d0, w.N, w.tile, tol=1e-6, jv="fd", callback=cb)
         how = "Newton-Krylov with finite-difference Jacobian products after plain-mixing warm-up to 1e-2"
