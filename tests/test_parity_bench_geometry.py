@@ -195,3 +195,32 @@ def test_config4_ldos_gradient_at_full_size():
     rel = float(np.max(np.abs(g - oe)) / np.max(np.abs(oe)))
     print("128x128 dLDOS(0)/dV rel err %.2e" % rel)
     assert rel < 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_config4_jacobian_rows_at_full_size():
+    """The whole Jacobian of the 128x128 workload's gap map (N = 512, all
+    16384 start sites in tiles of 1024: the geometry of the differentiation
+    benchmark's Newton solve), its cotangent the oracle's gap-map weights:
+    rows at the centre, a corner, the last site and sampled sites against the
+    oracle's full-storage adjoint of that one start site (1e-10 relative)."""
+    import paper_1007_1609_amd as P
+    w = W.config4()
+    _, _, a, b = oracle.workload_bounds(w)
+    cot = 0.5 * w.U * oracle.gap_weights(w.N)          # dF_k / dmu_he[k][n] of eq. (op1)
+    op = P.Operator.from_workload(w, DEV, fixed=(a, b))
+    d_mu = torch.as_tensor(np.ascontiguousarray(np.broadcast_to(cot, (w.L2, w.N))), device=DEV)
+    s = torch.arange(w.L2, dtype=torch.int32, device=DEV)
+    _, J = P.chebyshev_moments_jacobian(op, s, w.N, w.tile, None, d_mu)
+    rows = np.unique(np.concatenate([[w.notes["centre_site"], 0, w.L2 - 1, 1023, 1024],
+                                     _sampled_sites(w, 8, 21)])).astype(np.int64)
+    Jr = J[torch.as_tensor(rows, device=DEV)].cpu().numpy()
+    del J
+    op.close()
+    csr = oracle.workload_csr(w, a, b)
+    for k, site in enumerate(rows):
+        _, od = oracle.moments_backward(csr, [int(site)], w.N, np.zeros((1, w.N)), cot[None, :],
+                                        n_threads=_threads())
+        err = float(np.max(np.abs(Jr[k] - od)) / np.max(np.abs(od)))
+        print("128x128 Jacobian row %d: rel err %.2e" % (site, err))
+        assert err < 1e-10, site
