@@ -172,44 +172,83 @@ struct LdosArgs {
     double *out;
 };
 
-// Rows in a grid-stride loop; per row the damped moments pref_n g_n mu_n go to
-// LDS in chunks of kLdosChunk and each thread advances the three-term
-// recurrence of T_n for its energies through every chunk (any N).
-constexpr int kLdosChunk = 2048, kLdosTable = 4096;
+// LDOS(r, m) = norm / sqrt(1 - x_m^2) * sum_n mu[r][n] w_n T_n(x_m) with
+// w_n = pref_n g_n, x_m = (E_m - b)/a: a product of the moments [rows x N]
+// with the weighted Chebyshev table [N x nE], tiled through LDS.  A
+// workgroup takes 64 rows x 64 energies; per chunk of 32 moments it stages
+// the rows' moments and the table's chunk (threads 0..63 advance the
+// three-term recurrence of T_n for one energy each, in order of n, so the
+// table is exact to the recurrence's rounding), then each thread adds 4 x 4
+// outputs, every output summed over n in order.
+constexpr int kLdR = 64, kLdE = 64, kLdN = 32, kLdosTable = 4096;
 
 __global__ __launch_bounds__(kBlock) void k_ldos(LdosArgs A)
 {
-    __shared__ double m[kLdosChunk];
+    __shared__ double ms[kLdR][kLdN + 1];
+    __shared__ double ts[kLdN][kLdE];
     __shared__ double gt[kLdosTable];  // pref_n g_n, once per workgroup when N fits
     const int N = A.P.N;
     const bool table = N <= kLdosTable;
+    const int tid = threadIdx.x;
     if (table)
-        for (int n = threadIdx.x; n < N; n += blockDim.x) gt[n] = (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P);
+        for (int n = tid; n < N; n += blockDim.x) gt[n] = (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P);
     const double norm = 1.0 / (M_PI * A.a);
-    for (int64_t r = blockIdx.x; r < A.rows; r += gridDim.x) {
-        for (int e0 = 0; e0 < A.nE; e0 += kBlock) {
-            const int e = e0 + threadIdx.x;
-            const double x = e < A.nE ? (A.E[e] - A.b) / A.a : 0.0;
-            double t0 = 1.0, t1 = x, acc = 0.0;  // T_{n-2}, T_{n-1} entering each chunk
-            for (int c0 = 0; c0 < N; c0 += kLdosChunk) {
-                const int cn = min(kLdosChunk, N - c0);
-                __syncthreads();
-                for (int k = threadIdx.x; k < cn; k += blockDim.x) {
-                    const int n = c0 + k;
-                    const double g = table ? gt[n] : (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P);
-                    m[k] = g * A.mu[r * N + n];
-                }
-                __syncthreads();
-                for (int k = 0; k < cn; ++k) {
+    const int n_et = (A.nE + kLdE - 1) / kLdE;
+    const int64_t n_tiles = (A.rows + kLdR - 1) / kLdR * n_et;
+    const int tr = tid / 16, tc = tid % 16;  // the thread's rows tr*4.., energies tc*4..
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile / n_et * kLdR;
+        const int e0 = (int)(tile % n_et) * kLdE;
+        const double x = tid < kLdE && e0 + tid < A.nE ? (A.E[e0 + tid] - A.b) / A.a : 0.0;
+        double t0 = 1.0, t1 = x;  // T_{n-2}, T_{n-1}
+        double acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int c0 = 0; c0 < N; c0 += kLdN) {
+            const int cn = min(kLdN, N - c0);
+            __syncthreads();
+            for (int i = tid; i < kLdR * kLdN; i += blockDim.x) {
+                const int rr = i / kLdN, k = i % kLdN;
+                const int64_t row = r0 + rr;
+                ms[rr][k] = row < A.rows && k < cn ? A.mu[row * N + c0 + k] : 0.0;
+            }
+            if (tid < kLdE) {
+                for (int k = 0; k < kLdN; ++k) {
                     const int n = c0 + k;
                     double tn;
                     if (n == 0) tn = 1.0;
                     else if (n == 1) tn = x;
                     else { tn = 2.0 * x * t1 - t0; t0 = t1; t1 = tn; }
-                    acc += m[k] * tn;
+                    const double g = k >= cn ? 0.0 : table ? gt[n] : (n == 0 ? 1.0 : 2.0) * kernel_factor(n, A.P);
+                    ts[k][tid] = g * tn;
                 }
             }
-            if (e < A.nE) A.out[r * A.nE + e] = fabs(x) < 1.0 ? acc * norm / sqrt(1.0 - x * x) : __builtin_nan("");
+            __syncthreads();
+            for (int k = 0; k < cn; ++k) {
+                double mv[4], tv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) mv[i] = ms[tr * 4 + i][k];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) tv[j] = ts[k][tc * 4 + j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(mv[i], tv[j], acc[i][j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = e0 + tc * 4 + j;
+            if (e >= A.nE) continue;
+            const double xe = (A.E[e] - A.b) / A.a;
+            const double f = fabs(xe) < 1.0 ? norm / sqrt(1.0 - xe * xe) : __builtin_nan("");
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t row = r0 + tr * 4 + i;
+                if (row < A.rows) A.out[row * A.nE + e] = acc[i][j] * f;
+            }
         }
     }
 }
@@ -592,7 +631,8 @@ extern "C" int cbdg_ldos(const double *mu_ee, int64_t n_rows, int32_t N, const c
     if (n_rows == 0 || n_E == 0) return CBDG_OK;
     if (!mu_ee || !energies || !ldos) return fail(CBDG_EINVAL, "ldos: mu_ee, energies and ldos must not be NULL");
     LdosArgs A{mu_ee, n_rows, P, w->a, w->b, energies, n_E, ldos};
-    hipLaunchKernelGGL(k_ldos, dim3(grid_rows(n_rows, 1)), dim3(kBlock), 0, as_stream(stream), A);
+    const int64_t tiles = ceil_div(n_rows, kLdR) * ceil_div(n_E, kLdE);
+    hipLaunchKernelGGL(k_ldos, dim3((unsigned)std::min<int64_t>(tiles, 65536)), dim3(kBlock), 0, as_stream(stream), A);
     CBDG_CHECK_LAUNCH("k_ldos");
     return CBDG_OK;
 }
