@@ -180,3 +180,15 @@ def test_jacobian_matvec_checks_its_operands_on_the_host():
         P.jacobian_matvec(torch.zeros(3, 4, dtype=torch.float64), torch.zeros(2, dtype=torch.float64))
     with pytest.raises(ValueError):  # host tensors never reach the library
         P.jacobian_matvec(torch.zeros(3, 4, dtype=torch.float64), torch.zeros(4, dtype=torch.float64))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; --gpus N > 1 exits with a message before
+    anything touches a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
