@@ -459,6 +459,9 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 // Whether a pass skips the rows of a level outside the lattice or its light
 // cone (they are zero) instead of computing them (FP32, 256x256, 16 tiles of
 // 1024 vectors at N = 2048: 1101 -> 1083 ms; FP64 unchanged)
+#ifndef CBDG_VC_DLDS_F64
+#define CBDG_VC_DLDS_F64 5
+#endif
 #ifndef CBDG_VC_SKIP
 #define CBDG_VC_SKIP 1
 #endif
@@ -482,10 +485,11 @@ __global__ __launch_bounds__(kVcBlock) void k_vc_step1(VcArgs A)
 #endif
 template <typename T> constexpr int kVcSteps = sizeof(T) == 8 ? CBDG_VC_K_F64 : CBDG_VC_K_F32;
 // Trips ahead that the a_{n-1} and a_{n-2} rows are loaded (FP64 six steps:
-// 55.0 ms one and one, 51.9 three and two; at seven steps the deeper rings
-// no longer fit the registers.  FP32 seven steps: 73.2 -> 71.9)
+// 55.0 ms one and one, 51.9 three and two; at seven steps the a_{n-1} rows
+// go three trips ahead in the registers the LDS-held doubling sums free.
+// FP32 seven steps: 73.2 -> 71.9)
 #ifndef CBDG_VC_D1_F64
-#define CBDG_VC_D1_F64 1
+#define CBDG_VC_D1_F64 3
 #endif
 #ifndef CBDG_VC_D2_F64
 #define CBDG_VC_D2_F64 1
@@ -543,7 +547,9 @@ void k_vc_pass(VcArgs A)
 
     // a_{n-1} rows r-1 .. r+1 and the D1 rows in flight; a_{n-2} row r and
     // the D2 rows in flight
-    constexpr int D1 = VcDepth<T>::a1, D2 = VcDepth<T>::a2;
+    // (the shorter last pass, one launch per tile, keeps the rows one trip
+    // ahead: its stores at a run-time level leave no room for more)
+    constexpr int D1 = VAR && sizeof(T) == 8 ? 1 : VcDepth<T>::a1, D2 = VcDepth<T>::a2;
     constexpr int R1 = 3 + D1, R2 = 1 + D2;
     P ra[R1][W], rp[R2][W];
     P lv[K - 1][3][W];              // level j: rows r-j-2, r-j-1, r-j
@@ -585,6 +591,16 @@ void k_vc_pass(VcArgs A)
     double d[3 * K];
 #pragma unroll
     for (int i = 0; i < 3 * K; ++i) d[i] = 0.0;
+    // FP64: the doubling sums of levels 0 .. NDL-1 collect in LDS, one slot
+    // per lane, each added to once per trip; the registers they free hold the
+    // a_{n-1} rows three trips ahead (256x256, N = 1024, 64 tiles: 3121-3126
+    // ms against 3150-3160 with the sums in registers and the rows one trip
+    // ahead; the sums alone in LDS gain nothing, nor do two trips ahead)
+    constexpr int NDL = sizeof(T) == 8 ? (CBDG_VC_DLDS_F64 < K - 1 ? CBDG_VC_DLDS_F64 : K - 1) : 0;
+    __shared__ double dl_all[kVcWaves][NDL > 0 ? 3 * NDL : 1][kWave];
+    double (*dl)[kWave] = dl_all[threadIdx.x / kWave];
+#pragma unroll
+    for (int i = 0; i < 3 * NDL; ++i) dl[i][w.lane] = 0.0;
 
     // FP64: the two rows a trip stores (levels K-2 and K-1) go out on the next
     // trip, after its loads, so that a wait for those loads never waits for
@@ -670,7 +686,16 @@ void k_vc_pass(VcArgs A)
                     for (int k = 0; k < W; ++k) pend5[k] = v[k];
                 }
                 if (own) {
-                    if (live) {
+                    if (live && j < NDL) {
+                        double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int k = 0; k < W; ++k)
+                            dots3(t, (double)v[k].e, (double)v[k].h, (double)cc[k].e, (double)cc[k].h);
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            __hip_atomic_fetch_add(&dl[3 * j + i][w.lane], t[i], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    } else if (live) {
 #pragma unroll
                         for (int k = 0; k < W; ++k)
                             dots3(d + 3 * j, (double)v[k].e, (double)v[k].h, (double)cc[k].e, (double)cc[k].h);
@@ -729,6 +754,8 @@ void k_vc_pass(VcArgs A)
         store_row<T, W>(ro1, off5, pend5);
         store_row<T, W>(ro2, off6, pend6);
     }
+#pragma unroll
+    for (int i = 0; i < 3 * NDL; ++i) d[i] = dl[i][w.lane];
     wave_sum<3 * K>(d);
     if (w.lane == 0) {
 #pragma unroll
