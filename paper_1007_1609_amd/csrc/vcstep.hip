@@ -548,8 +548,9 @@ void k_vc_pass(VcArgs A)
     // a_{n-1} rows r-1 .. r+1 and the D1 rows in flight; a_{n-2} row r and
     // the D2 rows in flight
     // (the shorter last pass, one launch per tile, keeps the rows one trip
-    // ahead: its stores at a run-time level leave no room for more)
-    constexpr int D1 = VAR && sizeof(T) == 8 ? 1 : VcDepth<T>::a1, D2 = VcDepth<T>::a2;
+    // ahead: its stores at a run-time level leave no room for more; so do
+    // narrower rows, W < 4, whose passes the deeper ring does not speed up)
+    constexpr int D1 = sizeof(T) == 8 && (VAR || W < 4) ? 1 : VcDepth<T>::a1, D2 = VcDepth<T>::a2;
     constexpr int R1 = 3 + D1, R2 = 1 + D2;
     P ra[R1][W], rp[R2][W];
     P lv[K - 1][3][W];              // level j: rows r-j-2, r-j-1, r-j
@@ -595,8 +596,10 @@ void k_vc_pass(VcArgs A)
     // per lane, each added to once per trip; the registers they free hold the
     // a_{n-1} rows three trips ahead (256x256, N = 1024, 64 tiles: 3121-3126
     // ms against 3150-3160 with the sums in registers and the rows one trip
-    // ahead; the sums alone in LDS gain nothing, nor do two trips ahead)
-    constexpr int NDL = sizeof(T) == 8 ? (CBDG_VC_DLDS_F64 < K - 1 ? CBDG_VC_DLDS_F64 : K - 1) : 0;
+    // ahead; the sums alone in LDS gain nothing, nor do two trips ahead.  W =
+    // 4 only: at W = 2, 128x128, N = 512, 140.5-143.0 ms with the sums in
+    // registers against 140.1-144.8 ms)
+    constexpr int NDL = sizeof(T) == 8 && W >= 4 ? (CBDG_VC_DLDS_F64 < K - 1 ? CBDG_VC_DLDS_F64 : K - 1) : 0;
     __shared__ double dl_all[kVcWaves][NDL > 0 ? 3 * NDL : 1][kWave];
     double (*dl)[kWave] = dl_all[threadIdx.x / kWave];
 #pragma unroll
