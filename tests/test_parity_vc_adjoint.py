@@ -175,3 +175,28 @@ def test_differentiation_workload_matches_checkpoints():
     rd = float((gd - cd).abs().max() / cd.abs().max())
     print("128x128 N=%d: rel diff eps %.2e delta %.2e" % (N, re, rd))
     assert re < 1e-9 and rd < 1e-9
+
+
+def test_benchmark_lattice_matches_checkpoints():
+    """256x256, N = 1024 (three levels per reverse pass at W = 4): one
+    contiguous 1024-site tile of the benchmark's geometry (its light cones
+    grow from a four-row band) and a ragged tile of spread sites; the
+    regenerated vectors keep the gradient within 1e-9 of the checkpointed
+    reverse pass over 512 reverse levels."""
+    P = _P()
+    w = W.config1()
+    N = w.N
+    op = P.Operator.from_workload(w, DEV)
+    sites = torch.cat([torch.arange(32768, 32768 + 1024, dtype=torch.int32),
+                       torch.arange(0, 200, dtype=torch.int32) * 331 % w.L2]).to(DEV)
+    rng = np.random.default_rng(12)
+    dee = torch.as_tensor(rng.normal(size=(sites.numel(), N)) / N, device=DEV)
+    dhe = torch.as_tensor(rng.normal(size=(sites.numel(), N)) / N, device=DEV)
+    ge, gd = P.chebyshev_moments_backward(op, sites, N, 1024, dee, dhe, REV, algorithm=DOUBLING)
+    ce, cd = P.chebyshev_moments_backward(op, sites, N, 1024, dee, dhe, 0, algorithm=DOUBLING)
+    torch.cuda.synchronize()
+    op.close()
+    re = float((ge - ce).abs().max() / ce.abs().max())
+    rd = float((gd - cd).abs().max() / cd.abs().max())
+    print("256x256 N=%d: rel diff eps %.2e delta %.2e" % (N, re, rd))
+    assert re < 1e-9 and rd < 1e-9
